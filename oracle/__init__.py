@@ -1,0 +1,146 @@
+"""FP64 CPU oracle for the even-odd asqtad CG (ctypes wrapper over asqtad_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg.  The GPU library never imports or calls it, and it
+shares no code with the HIP path.
+
+Every function takes the canonical host arrays produced by ``synth``:
+links complex128 (V, 4, 3, 3), even/odd colour vectors complex128 (V/2, 3).
+
+Pins (tests/test_oracle_*.py) tie it to facts that do not come from itself:
+free-field plane-wave spectrum (closed form), anti-Hermiticity of D, gauge
+covariance, hand-derived point-source values, brute-force dense solves and the
+finite termination of CG on an operator with few distinct eigenvalues.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "asqtad_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dptr = ctypes.POINTER(ctypes.c_double)
+_iptr = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        L.oracle_dslash.argtypes = [_iptr, _dptr, _dptr, ctypes.c_int, _dptr, _dptr]
+        L.oracle_dslash.restype = ctypes.c_int
+        L.oracle_apply_A.argtypes = [_iptr, _dptr, _dptr, ctypes.c_double, _dptr, _dptr]
+        L.oracle_apply_A.restype = ctypes.c_int
+        L.oracle_true_residual.argtypes = [_iptr, _dptr, _dptr, ctypes.c_double, _dptr, _dptr]
+        L.oracle_true_residual.restype = ctypes.c_double
+        L.oracle_cg.argtypes = [_iptr, _dptr, _dptr, ctypes.c_double, _dptr, _dptr, ctypes.c_double,
+                                ctypes.c_int, _iptr, _dptr, _dptr]
+        L.oracle_cg.restype = ctypes.c_int
+        L.oracle_num_threads.argtypes = []
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dims(dims):
+    return (ctypes.c_int * 4)(*[int(d) for d in dims])
+
+
+def _c128(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if shape is not None and a.shape != tuple(shape):
+        a = a.reshape(shape)
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(_dptr)
+
+
+def _check_links(dims, fat, lng):
+    V = int(np.prod(dims))
+    return _c128(fat, (V, 4, 3, 3)), _c128(lng, (V, 4, 3, 3))
+
+
+def dslash(dims, fat, lng, out_parity: int, vec) -> np.ndarray:
+    """D restricted to sites of ``out_parity`` acting on a vector of the other parity."""
+    fat, lng = _check_links(dims, fat, lng)
+    half = int(np.prod(dims)) // 2
+    v = _c128(vec, (half, 3))
+    out = np.empty((half, 3), dtype=np.complex128)
+    rc = lib().oracle_dslash(_dims(dims), _p(fat), _p(lng), int(out_parity), _p(v), _p(out))
+    if rc != 0:
+        raise ValueError(f"oracle_dslash failed ({rc})")
+    return out
+
+
+def apply_A(dims, fat, lng, mass: float, vec) -> np.ndarray:
+    """(4 m^2 - D_eo D_oe) vec on even sites."""
+    fat, lng = _check_links(dims, fat, lng)
+    half = int(np.prod(dims)) // 2
+    v = _c128(vec, (half, 3))
+    out = np.empty((half, 3), dtype=np.complex128)
+    rc = lib().oracle_apply_A(_dims(dims), _p(fat), _p(lng), float(mass), _p(v), _p(out))
+    if rc != 0:
+        raise ValueError(f"oracle_apply_A failed ({rc})")
+    return out
+
+
+def true_residual(dims, fat, lng, mass: float, b, x) -> float:
+    """|b - A x| / |b| computed in FP64."""
+    fat, lng = _check_links(dims, fat, lng)
+    half = int(np.prod(dims)) // 2
+    bb, xx = _c128(b, (half, 3)), _c128(x, (half, 3))
+    return float(lib().oracle_true_residual(_dims(dims), _p(fat), _p(lng), float(mass), _p(bb), _p(xx)))
+
+
+def cg(dims, fat, lng, mass: float, b, tol: float = 1e-10, maxiter: int = 100000, history: bool = False):
+    """Plain FP64 CG from x0 = 0.  Returns (x, iters, true_resid, converged[, resid_history])."""
+    fat, lng = _check_links(dims, fat, lng)
+    half = int(np.prod(dims)) // 2
+    bb = _c128(b, (half, 3))
+    x = np.zeros((half, 3), dtype=np.complex128)
+    it = ctypes.c_int(0)
+    tr = ctypes.c_double(0)
+    hist = np.zeros(maxiter + 1) if history else None
+    rc = lib().oracle_cg(_dims(dims), _p(fat), _p(lng), float(mass), _p(bb), _p(x), float(tol), int(maxiter),
+                         ctypes.byref(it), ctypes.byref(tr), _p(hist) if history else None)
+    if rc < 0:
+        raise ValueError(f"oracle_cg failed ({rc})")
+    if history:
+        return x, it.value, tr.value, rc == 0, hist[: it.value + 1]
+    return x, it.value, tr.value, rc == 0
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def dense_operator(apply, n_sites: int) -> np.ndarray:
+    """Dense matrix of a linear map on (n_sites, 3) complex vectors, built column by column."""
+    n = n_sites * 3
+    M = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for k in range(n):
+        e[k] = 1.0
+        M[:, k] = apply(e.reshape(n_sites, 3)).reshape(n)
+        e[k] = 0.0
+    return M
