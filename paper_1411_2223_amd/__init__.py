@@ -1,0 +1,278 @@
+"""MI355X (gfx950) even-odd asqtad CG: Python binding of libasqtad.so.
+
+The binding only marshals arguments: PyTorch provides device memory and the
+stream, and every step of the operator and the solvers runs in the library's
+HIP kernels.  There is no CPU fallback: if the library is missing, loading
+fails with an error that says how to build it.
+
+The functions named like the C ABI (``asq_gauge_create``, ``asqtad_dslash_eo``,
+``cg_solve``, ``cg_solve_batch``, ``serve_*`` ...) take raw integers for device
+pointers and streams, exactly as ``include/asqtad.h`` declares them.  The
+classes ``Gauge`` and ``Server`` wrap them around torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libasqtad.so")
+
+ASQ_OK, ASQ_PENDING = 0, 1
+ASQ_EINVAL, ASQ_ENOMEM, ASQ_ENOCONV, ASQ_ENOTSU3, ASQ_EHIP, ASQ_ENAN, ASQ_EAGAIN = -1, -2, -3, -4, -5, -6, -7
+ASQ_F64, ASQ_F32, ASQ_F16 = 0, 1, 2
+ASQ_MODE_F64, ASQ_MODE_MIXED32, ASQ_MODE_MIXED16 = 0, 1, 2
+MODES = {"f64": ASQ_MODE_F64, "mixed32": ASQ_MODE_MIXED32, "mixed16": ASQ_MODE_MIXED16}
+PRECS = {"f64": ASQ_F64, "f32": ASQ_F32, "f16": ASQ_F16}
+
+FLOPS_PER_SITE_DSLASH = 1146
+
+
+class asq_gauge_desc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("prec_mask", ctypes.c_int), ("recon", ctypes.c_int),
+                ("fat_scale", ctypes.c_double), ("long_scale", ctypes.c_double)]
+
+
+class asq_cg_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("mode", ctypes.c_int),
+                ("delta", ctypes.c_double), ("poll_iters", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class asq_cg_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
+                ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("gflops", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class AsqError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        detail = _lib.asq_last_error().decode() if _lib is not None else ""
+        super().__init__(f"{where}: {_lib.asq_strerror(code).decode()} ({code}) {detail}")
+
+
+_vp = ctypes.c_void_p
+_SIGS = {
+    "asq_gauge_bytes": (ctypes.c_size_t, [ctypes.POINTER(asq_gauge_desc)]),
+    "asq_gauge_create": (ctypes.c_int, [ctypes.POINTER(asq_gauge_desc), _vp, _vp, _vp, ctypes.c_size_t, _vp,
+                                        ctypes.POINTER(_vp)]),
+    "asq_gauge_destroy": (ctypes.c_int, [_vp]),
+    "asqtad_dslash_eo": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    "asq_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int]),
+    "cg_solve": (ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t,
+                                ctypes.POINTER(asq_cg_params), ctypes.POINTER(asq_cg_stats), _vp]),
+    "cg_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp, _vp,
+                                      ctypes.c_size_t, ctypes.POINTER(asq_cg_params),
+                                      ctypes.POINTER(asq_cg_stats), _vp]),
+    "serve_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "serve_register_gauge": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int)]),
+    "serve_submit": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp,
+                                    ctypes.POINTER(asq_cg_params), ctypes.POINTER(ctypes.c_uint64)]),
+    "serve_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(asq_cg_stats),
+                                  ctypes.POINTER(ctypes.c_double)]),
+    "serve_destroy": (ctypes.c_int, [_vp]),
+    "asq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "asq_last_error": (ctypes.c_char_p, []),
+    "asq_copy_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+}
+
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+def load():
+    """Load libasqtad.so (built in-tree by ``python -m paper_1411_2223_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1411_2223_amd.build` "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _fn(name):
+    def call(*args):
+        return getattr(load(), name)(*args)
+
+    call.__name__ = name
+    return call
+
+
+for _n in _SIGS:
+    globals()[_n] = _fn(_n)
+
+
+def check(rc, where):
+    if rc < 0:
+        raise AsqError(rc, where)
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# torch-side helpers (device memory and streams only)
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def empty_bytes(n, device="cuda"):
+    """Caller-owned device buffer of n bytes (256-byte aligned by the caching allocator)."""
+    torch = _torch()
+    t = torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def vec_to_device(v, prec="f64", device="cuda"):
+    """(nrhs, V/2, 3) complex host array -> device tensor in the library's layout.
+
+    f64/f32: [nrhs][3][V/2][2]; f16: 16-byte records [nrhs][V/2] (encoded on the host).
+    """
+    torch = _torch()
+    v = np.asarray(v)
+    if v.ndim == 2:
+        v = v[None]
+    if prec == "f16":
+        return torch.from_numpy(encode_f16n(v)).to(device)
+    dt = np.float64 if prec == "f64" else np.float32
+    a = np.ascontiguousarray(np.stack([v.real, v.imag], axis=-1).transpose(0, 2, 1, 3)).astype(dt)
+    return torch.from_numpy(a).to(device)
+
+
+def vec_from_device(t, nrhs, half, prec="f64"):
+    """Inverse of vec_to_device: device tensor -> (nrhs, V/2, 3) complex128 host array."""
+    a = t.detach().cpu().numpy()
+    if prec == "f16":
+        return decode_f16n(a.view(np.uint8).reshape(-1)[: nrhs * half * 16], nrhs, half)
+    a = a.reshape(nrhs, 3, half, 2).astype(np.float64)
+    return (a[..., 0] + 1j * a[..., 1]).transpose(0, 2, 1)
+
+
+def encode_f16n(v):
+    """Host encoding of the F16 vector tier: per site six binary16 of psi/nu, then nu (float32)."""
+    v = np.asarray(v, dtype=np.complex128)
+    nrhs, half = v.shape[:2]
+    comp = np.stack([v.real, v.imag], axis=-1).reshape(nrhs, half, 6).astype(np.float32)
+    nu = np.abs(comp).max(axis=-1)
+    inv = np.where(nu > 0, 1.0 / np.where(nu > 0, nu, 1), 0).astype(np.float32)
+    h = (comp * inv[..., None]).astype(np.float16)
+    rec = np.empty((nrhs, half, 16), dtype=np.uint8)
+    rec[..., :12] = h.view(np.uint8).reshape(nrhs, half, 12)
+    rec[..., 12:] = nu.astype(np.float32).view(np.uint8).reshape(nrhs, half, 4)
+    return rec.reshape(-1)
+
+
+def decode_f16n(rec, nrhs, half):
+    rec = np.asarray(rec, dtype=np.uint8).reshape(nrhs, half, 16)
+    h = rec[..., :12].copy().view(np.float16).reshape(nrhs, half, 6).astype(np.float64)
+    nu = rec[..., 12:].copy().view(np.float32).reshape(nrhs, half).astype(np.float64)
+    comp = (h * nu[..., None]).reshape(nrhs, half, 3, 2)
+    return comp[..., 0] + 1j * comp[..., 1]
+
+
+@dataclass
+class SolveResult:
+    x: object
+    stats: list
+    rc: int
+
+
+class Gauge:
+    """A resident gauge field: canonical links uploaded, imported into device storage."""
+
+    def __init__(self, dims, fat, lng, precs=("f64", "f32"), recon=18, fat_scale=9 / 8, long_scale=-1 / 24,
+                 device="cuda", stream=None):
+        torch = _torch()
+        load()
+        self.dims = tuple(int(d) for d in dims)
+        self.half = int(np.prod(self.dims)) // 2
+        mask = 0
+        for p in precs:
+            mask |= 1 << PRECS[p]
+        self.desc = asq_gauge_desc((ctypes.c_int * 4)(*self.dims), mask, int(recon), float(fat_scale),
+                                   float(long_scale))
+        nbytes = asq_gauge_bytes(ctypes.byref(self.desc))
+        if nbytes == 0:
+            raise AsqError(ASQ_EINVAL, "asq_gauge_bytes")
+        self.storage = empty_bytes(nbytes, device)
+        V = int(np.prod(self.dims))
+
+        def up(a):
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(V, 4, 3, 3))
+            return torch.from_numpy(a.view(np.float64)).to(device)
+
+        fat_d, lng_d = up(fat), up(lng)
+        h = ctypes.c_void_p()
+        rc = asq_gauge_create(ctypes.byref(self.desc), fat_d.data_ptr(), lng_d.data_ptr(), self.storage.data_ptr(),
+                              nbytes, stream_ptr(stream), ctypes.byref(h))
+        del fat_d, lng_d
+        check(rc, "asq_gauge_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            asq_gauge_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dslash(self, out_parity, vin, prec="f64", nrhs=1, out=None, stream=None):
+        """out = D_{out_parity <- other} vin on device tensors in the library layout."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(vin)
+        rc = asqtad_dslash_eo(self.handle, int(out_parity), PRECS[prec], int(nrhs), vin.data_ptr(), out.data_ptr(),
+                              stream_ptr(stream))
+        check(rc, "asqtad_dslash_eo")
+        return out
+
+    def workspace(self, nrhs, mode="mixed32"):
+        n = asq_workspace_bytes(self.handle, int(nrhs), MODES[mode])
+        return empty_bytes(n, self.device)
+
+    def solve(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.1, poll_iters=8, use_graph=True,
+              work=None, x=None, stream=None):
+        """Batched CG: b is a device tensor [nrhs][3][V/2][2] float64; returns SolveResult."""
+        torch = _torch()
+        masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
+        nrhs = len(masses)
+        if work is None:
+            work = self.workspace(nrhs, mode)
+        if x is None:
+            x = torch.empty_like(b)
+        params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
+                               1 if use_graph else 0)
+        stats = (asq_cg_stats * nrhs)()
+        m = (ctypes.c_double * nrhs)(*masses)
+        rc = cg_solve_batch(self.handle, nrhs, m, b.data_ptr(), x.data_ptr(), work.data_ptr(), work.numel(),
+                            ctypes.byref(params), stats, stream_ptr(stream))
+        if rc < 0 and rc not in (ASQ_ENOCONV,):
+            check(rc, "cg_solve_batch")
+        return SolveResult(x, [s.as_dict() for s in stats], rc)

@@ -1,0 +1,45 @@
+// asq_batch.h -- a batch of CG columns sharing one gauge field and one set of
+// device buffers; used by cg_solve_batch and by the serving loop.
+#pragma once
+#include "asq_internal.h"
+
+namespace asq {
+
+using Gauge_t = asq_gauge;
+
+struct Batch {
+  const asq_gauge* g = nullptr;
+  int ncol = 0;
+  int mode = 0;
+  int pt = 0, rt = 0;  // storage tiers of p/Ap/t and of r
+  int link = 0;        // link tier of the iterated Dslash
+  int rt_sloppy_plain = 1, rt_sloppy_xpay = 1, rt64_plain = 1, rt64_resid = 1;
+  ColState* st = nullptr;
+  double* partials = nullptr;
+  double* b = nullptr;  // F64 [ncol][3][half][2]
+  double* x = nullptr;
+  void* r = nullptr;
+  void* p = nullptr;
+  void* Ap = nullptr;
+  void* t = nullptr;
+  void* t64 = nullptr;
+};
+
+int mode_pt(int mode);
+int mode_rt(int mode);
+size_t batch_bytes(const asq_gauge* g, int ncol, int mode, bool with_bx);
+// Lay the batch out in `work`; b == nullptr puts b and x in the workspace too.
+int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, size_t bytes, const double* b,
+                double* x);
+void batch_pick_tiles(Batch& B);
+int batch_tune(Batch& B, hipStream_t s);
+int enqueue_init(const Batch& B, int c0, int n, hipStream_t s);
+int enqueue_iteration(const Batch& B, hipStream_t s);
+int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s);
+int enqueue_block(const Batch& B, int iters, hipStream_t s);
+int capture_block(const Batch& B, int iters, hipStream_t cap, hipGraphExec_t* exec);
+void init_states(const Batch& B, const double* masses, const asq_cg_params* p, ColState* host);
+void fill_stats(const Batch& B, const ColState* S, double seconds, asq_cg_stats* out, int* worst);
+int check_params(const asq_gauge* g, const asq_cg_params* p);
+
+}  // namespace asq

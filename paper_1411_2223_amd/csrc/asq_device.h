@@ -1,0 +1,456 @@
+// asq_device.h -- device-side building blocks of the gfx950 asqtad path:
+// lattice geometry on a checkerboard, complex arithmetic with explicit FMAs,
+// SU(3) link loaders (18-real and 12-real), colour-vector loaders/stores for
+// the three storage tiers, and deterministic FP64 block reductions.
+//
+// Conventions (the staggered operator of the paper's CG workload; the paper
+// gives no formulas, so the standard MILC asqtad forms are used):
+//   lex = x + X*(y + Y*(z + Z*t)); parity = (x+y+z+t) & 1; checkerboard index = lex >> 1
+//   eta_x = 1, eta_y = (-1)^x, eta_z = (-1)^(x+y), eta_t = (-1)^(x+y+z)
+//   fermions antiperiodic in t, links periodic.
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace asq {
+
+constexpr int kBlock = 256;  // sites per block and per reduction group (fixed: keeps sums batch-invariant)
+
+// n / d for 32-bit n and 2 <= d < 2^32 with a 64-bit magic multiplier:
+// m = floor(2^64 / d) + 1 gives floor(n*m / 2^64) = floor(n / d) exactly.
+struct FastDiv {
+  uint32_t d;
+  uint64_t m;
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    return (uint32_t)__umul64hi((uint64_t)n, m);
+  }
+};
+
+struct Geom {
+  int X, Y, Z, T;
+  int Xh;          // X / 2
+  int half;        // V / 2 sites of one parity
+  int sY, sZ, sT;  // checkerboard-index strides of y, z, t: Xh, Xh*Y, Xh*Y*Z
+  FastDiv dXh, dY, dZ;
+};
+
+struct Site {
+  int x, y, z, t;
+};
+
+// Coordinates of checkerboard site i of parity p.
+__device__ __forceinline__ Site decode(const Geom& g, int i, int p) {
+  const uint32_t r = g.dXh.div((uint32_t)i);
+  const int xh = i - (int)r * g.Xh;
+  const uint32_t r2 = g.dY.div(r);
+  const int y = (int)r - (int)r2 * g.Y;
+  const uint32_t t = g.dZ.div(r2);
+  const int z = (int)r2 - (int)t * g.Z;
+  Site s;
+  s.y = y;
+  s.z = z;
+  s.t = (int)t;
+  s.x = 2 * xh + ((y + z + (int)t + p) & 1);
+  return s;
+}
+
+__device__ __forceinline__ int wrap(int v, int L) {
+  return v < 0 ? v + L : (v >= L ? v - L : v);
+}
+
+// Checkerboard index of the site h steps (|h| = 1 or 3) from site (i, s) along mu.
+template <int MU>
+__device__ __forceinline__ int neighbour(const Geom& g, int i, const Site& s, int h) {
+  if constexpr (MU == 0) {
+    const int xn = wrap(s.x + h, g.X);
+    return i - (s.x >> 1) + (xn >> 1);
+  } else if constexpr (MU == 1) {
+    return i + (wrap(s.y + h, g.Y) - s.y) * g.sY;
+  } else if constexpr (MU == 2) {
+    return i + (wrap(s.z + h, g.Z) - s.z) * g.sZ;
+  } else {
+    return i + (wrap(s.t + h, g.T) - s.t) * g.sT;
+  }
+}
+
+// MILC staggered phase eta_mu at site s.
+template <int MU>
+__device__ __forceinline__ int eta_sign(const Site& s) {
+  if (MU == 0) return 1;
+  if (MU == 1) return (s.x & 1) ? -1 : 1;
+  if (MU == 2) return ((s.x + s.y) & 1) ? -1 : 1;
+  return ((s.x + s.y + s.z) & 1) ? -1 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// complex arithmetic (explicit FMAs so that every instance rounds identically)
+// ---------------------------------------------------------------------------
+template <class R>
+struct cx {
+  R re, im;
+};
+
+template <class R>
+__device__ __forceinline__ R fmaR(R a, R b, R c);
+template <>
+__device__ __forceinline__ float fmaR<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fmaR<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc += a * b
+template <class R>
+__device__ __forceinline__ void cmac(cx<R>& acc, const cx<R>& a, const cx<R>& b) {
+  acc.re = fmaR(a.re, b.re, acc.re);
+  acc.re = fmaR(-a.im, b.im, acc.re);
+  acc.im = fmaR(a.re, b.im, acc.im);
+  acc.im = fmaR(a.im, b.re, acc.im);
+}
+
+// acc += conj(a) * b
+template <class R>
+__device__ __forceinline__ void cmac_conj(cx<R>& acc, const cx<R>& a, const cx<R>& b) {
+  acc.re = fmaR(a.re, b.re, acc.re);
+  acc.re = fmaR(a.im, b.im, acc.re);
+  acc.im = fmaR(a.re, b.im, acc.im);
+  acc.im = fmaR(-a.im, b.re, acc.im);
+}
+
+template <class R>
+struct Mat3 {
+  cx<R> e[3][3];
+};
+
+template <class R>
+struct Vec3 {
+  cx<R> c[3];
+};
+
+// y = U v
+template <class R>
+__device__ __forceinline__ Vec3<R> mul(const Mat3<R>& U, const Vec3<R>& v) {
+  Vec3<R> y;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    y.c[a].re = U.e[a][0].re * v.c[0].re;
+    y.c[a].im = U.e[a][0].re * v.c[0].im;
+    y.c[a].re = fmaR(-U.e[a][0].im, v.c[0].im, y.c[a].re);
+    y.c[a].im = fmaR(U.e[a][0].im, v.c[0].re, y.c[a].im);
+    cmac(y.c[a], U.e[a][1], v.c[1]);
+    cmac(y.c[a], U.e[a][2], v.c[2]);
+  }
+  return y;
+}
+
+// y = U^dagger v
+template <class R>
+__device__ __forceinline__ Vec3<R> mul_adj(const Mat3<R>& U, const Vec3<R>& v) {
+  Vec3<R> y;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    y.c[a].re = U.e[0][a].re * v.c[0].re;
+    y.c[a].im = U.e[0][a].re * v.c[0].im;
+    y.c[a].re = fmaR(U.e[0][a].im, v.c[0].im, y.c[a].re);
+    y.c[a].im = fmaR(-U.e[0][a].im, v.c[0].re, y.c[a].im);
+    cmac_conj(y.c[a], U.e[1][a], v.c[1]);
+    cmac_conj(y.c[a], U.e[2][a], v.c[2]);
+  }
+  return y;
+}
+
+// acc += s * v
+template <class R>
+__device__ __forceinline__ void axpy3(Vec3<R>& acc, R s, const Vec3<R>& v) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc.c[a].re = fmaR(s, v.c[a].re, acc.c[a].re);
+    acc.c[a].im = fmaR(s, v.c[a].im, acc.c[a].im);
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void add3(Vec3<R>& acc, const Vec3<R>& v) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc.c[a].re += v.c[a].re;
+    acc.c[a].im += v.c[a].im;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void sub3(Vec3<R>& acc, const Vec3<R>& v) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc.c[a].re -= v.c[a].re;
+    acc.c[a].im -= v.c[a].im;
+  }
+}
+
+// Third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1).
+template <class R>
+__device__ __forceinline__ void reconstruct_row2(Mat3<R>& U) {
+  const cx<R>* a = U.e[0];
+  const cx<R>* b = U.e[1];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+    // (a x b)_k = a_k1 b_k2 - a_k2 b_k1
+    R re = a[k1].re * b[k2].re;
+    re = fmaR(-a[k1].im, b[k2].im, re);
+    re = fmaR(-a[k2].re, b[k1].re, re);
+    re = fmaR(a[k2].im, b[k1].im, re);
+    R im = a[k1].re * b[k2].im;
+    im = fmaR(a[k1].im, b[k2].re, im);
+    im = fmaR(-a[k2].re, b[k1].im, im);
+    im = fmaR(-a[k2].im, b[k1].re, im);
+    U.e[2][k].re = re;
+    U.e[2][k].im = -im;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// link storage tiers.  Per parity p and slot s (0..3 fat x,y,z,t; 4..7 long)
+// the links are stored chunk-major: chunk k of site i at
+// base[((p*8 + s)*NCH + k)*half + i]  (structure of arrays, site fastest).
+// 18-real tiers hold the link with eta, the time-boundary sign and the fat /
+// long coefficient folded in.  12-real tiers hold the first two rows of the
+// SU(3) part (link / coefficient); the kernel rebuilds row 3 and applies
+// coefficient * eta * boundary sign to the product.
+// ---------------------------------------------------------------------------
+enum LinkKind { LINK_F64_R18 = 0, LINK_F32_R18 = 1, LINK_F32_R12 = 2, LINK_I16_R12 = 3, LINK_KINDS = 4 };
+
+struct LinkF64R18 {
+  using real = double;
+  using chunk = double2;
+  static constexpr int NCH = 9;
+  static constexpr bool folded = true;
+  __device__ __forceinline__ static Mat3<double> load(const void* base, int half, int p, int slot, int i) {
+    const double2* q = reinterpret_cast<const double2*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    Mat3<double> U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 v = q[(size_t)k * half];
+      U.e[k / 3][k % 3].re = v.x;
+      U.e[k / 3][k % 3].im = v.y;
+    }
+    return U;
+  }
+};
+
+struct LinkF32R18 {
+  using real = float;
+  using chunk = float2;
+  static constexpr int NCH = 9;
+  static constexpr bool folded = true;
+  __device__ __forceinline__ static Mat3<float> load(const void* base, int half, int p, int slot, int i) {
+    const float2* q = reinterpret_cast<const float2*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    Mat3<float> U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const float2 v = q[(size_t)k * half];
+      U.e[k / 3][k % 3].re = v.x;
+      U.e[k / 3][k % 3].im = v.y;
+    }
+    return U;
+  }
+};
+
+struct LinkF32R12 {
+  using real = float;
+  using chunk = float4;
+  static constexpr int NCH = 3;
+  static constexpr bool folded = false;
+  __device__ __forceinline__ static Mat3<float> load(const void* base, int half, int p, int slot, int i) {
+    const float4* q = reinterpret_cast<const float4*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    Mat3<float> U;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 v = q[(size_t)k * half];
+      const int e0 = 2 * k, e1 = 2 * k + 1;
+      U.e[e0 / 3][e0 % 3].re = v.x;
+      U.e[e0 / 3][e0 % 3].im = v.y;
+      U.e[e1 / 3][e1 % 3].re = v.z;
+      U.e[e1 / 3][e1 % 3].im = v.w;
+    }
+    reconstruct_row2(U);
+    return U;
+  }
+};
+
+// 16-bit fixed point: entries of an SU(3) matrix lie in [-1, 1]; value = q / 32767.
+struct LinkI16R12 {
+  using real = float;
+  using chunk = short4;
+  static constexpr int NCH = 3;
+  static constexpr bool folded = false;
+  __device__ __forceinline__ static Mat3<float> load(const void* base, int half, int p, int slot, int i) {
+    const short4* q = reinterpret_cast<const short4*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    constexpr float inv = 1.0f / 32767.0f;
+    Mat3<float> U;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const short4 v = q[(size_t)k * half];
+      const int e0 = 2 * k, e1 = 2 * k + 1;
+      U.e[e0 / 3][e0 % 3].re = (float)v.x * inv;
+      U.e[e0 / 3][e0 % 3].im = (float)v.y * inv;
+      U.e[e1 / 3][e1 % 3].re = (float)v.z * inv;
+      U.e[e1 / 3][e1 % 3].im = (float)v.w * inv;
+    }
+    reconstruct_row2(U);
+    return U;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// colour-vector storage tiers (one parity, ncol columns):
+//   F64: double2 [col][colour][half]       F32: float2 [col][colour][half]
+//   F16: 16-byte record [col][half] = six binary16 values (c0re c0im c1re ...)
+//        scaled by 1/nu, then nu as float32; nu = max |component|.
+// ---------------------------------------------------------------------------
+enum VecKind { VEC_F64 = 0, VEC_F32 = 1, VEC_F16 = 2 };
+
+struct VecF64 {
+  using real = double;
+  static constexpr int kind = VEC_F64;
+  __device__ __forceinline__ static Vec3<double> load(const void* base, int half, int col, int i) {
+    const double2* q = reinterpret_cast<const double2*>(base) + (size_t)col * 3 * half + i;
+    Vec3<double> v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double2 w = q[(size_t)a * half];
+      v.c[a].re = w.x;
+      v.c[a].im = w.y;
+    }
+    return v;
+  }
+  // Stores v; returns the value a later load gives back.
+  __device__ __forceinline__ static Vec3<double> store(void* base, int half, int col, int i, const Vec3<double>& v) {
+    double2* q = reinterpret_cast<double2*>(base) + (size_t)col * 3 * half + i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[(size_t)a * half] = make_double2(v.c[a].re, v.c[a].im);
+    return v;
+  }
+};
+
+struct VecF32 {
+  using real = float;
+  static constexpr int kind = VEC_F32;
+  __device__ __forceinline__ static Vec3<float> load(const void* base, int half, int col, int i) {
+    const float2* q = reinterpret_cast<const float2*>(base) + (size_t)col * 3 * half + i;
+    Vec3<float> v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float2 w = q[(size_t)a * half];
+      v.c[a].re = w.x;
+      v.c[a].im = w.y;
+    }
+    return v;
+  }
+  __device__ __forceinline__ static Vec3<float> store(void* base, int half, int col, int i, const Vec3<float>& v) {
+    float2* q = reinterpret_cast<float2*>(base) + (size_t)col * 3 * half + i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[(size_t)a * half] = make_float2(v.c[a].re, v.c[a].im);
+    return v;
+  }
+};
+
+struct VecF16 {
+  using real = float;
+  static constexpr int kind = VEC_F16;
+  __device__ __forceinline__ static float h2f(unsigned short u) {
+    return __half2float(__ushort_as_half(u));
+  }
+  __device__ __forceinline__ static Vec3<float> load(const void* base, int half, int col, int i) {
+    return unpack(reinterpret_cast<const uint4*>(base)[(size_t)col * half + i]);
+  }
+  __device__ __forceinline__ static Vec3<float> unpack(const uint4 w) {
+    const float nu = __uint_as_float(w.w);
+    Vec3<float> v;
+    v.c[0].re = h2f(w.x & 0xffffu) * nu;
+    v.c[0].im = h2f(w.x >> 16) * nu;
+    v.c[1].re = h2f(w.y & 0xffffu) * nu;
+    v.c[1].im = h2f(w.y >> 16) * nu;
+    v.c[2].re = h2f(w.z & 0xffffu) * nu;
+    v.c[2].im = h2f(w.z >> 16) * nu;
+    return v;
+  }
+  __device__ __forceinline__ static unsigned pack2(float a, float b) {
+    const unsigned lo = __half_as_ushort(__float2half_rn(a));
+    const unsigned hi = __half_as_ushort(__float2half_rn(b));
+    return lo | (hi << 16);
+  }
+  __device__ __forceinline__ static Vec3<float> store(void* base, int half, int col, int i, const Vec3<float>& v) {
+    float nu = fabsf(v.c[0].re);
+    nu = fmaxf(nu, fabsf(v.c[0].im));
+    nu = fmaxf(nu, fabsf(v.c[1].re));
+    nu = fmaxf(nu, fabsf(v.c[1].im));
+    nu = fmaxf(nu, fabsf(v.c[2].re));
+    nu = fmaxf(nu, fabsf(v.c[2].im));
+    const float inv = nu > 0.f ? 1.0f / nu : 0.f;
+    uint4 w;
+    w.x = pack2(v.c[0].re * inv, v.c[0].im * inv);
+    w.y = pack2(v.c[1].re * inv, v.c[1].im * inv);
+    w.z = pack2(v.c[2].re * inv, v.c[2].im * inv);
+    w.w = __float_as_uint(nu);
+    reinterpret_cast<uint4*>(base)[(size_t)col * half + i] = w;
+    return unpack(w);
+  }
+};
+
+template <class RD, class RS>
+__device__ __forceinline__ Vec3<RD> convert(const Vec3<RS>& v) {
+  Vec3<RD> o;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    o.c[a].re = (RD)v.c[a].re;
+    o.c[a].im = (RD)v.c[a].im;
+  }
+  return o;
+}
+
+template <class R>
+__device__ __forceinline__ double norm2_d(const Vec3<R>& v) {
+  double s = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s = __builtin_fma((double)v.c[a].re, (double)v.c[a].re, s);
+    s = __builtin_fma((double)v.c[a].im, (double)v.c[a].im, s);
+  }
+  return s;
+}
+
+template <class R>
+__device__ __forceinline__ double redot_d(const Vec3<R>& u, const Vec3<R>& v) {
+  double s = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s = __builtin_fma((double)u.c[a].re, (double)v.c[a].re, s);
+    s = __builtin_fma((double)u.c[a].im, (double)v.c[a].im, s);
+  }
+  return s;
+}
+
+// Deterministic sum over a kBlock-thread block; the result is valid in thread 0.
+// `sh` holds kBlock/64 doubles; the caller separates successive uses with a barrier.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) s += sh[k];
+  }
+  return s;
+}
+
+// Blocks are dealt to the 8 XCDs round-robin; remap so that each XCD walks a
+// contiguous range of the lattice and neighbour vectors stay in its own L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, rem = n & 7, k = b & 7, j = b >> 3;
+  return k * q + (k < rem ? k : rem) + j;
+}
+
+}  // namespace asq

@@ -1,0 +1,108 @@
+// asq_internal.h -- host-side objects shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/asqtad.h"
+#include "asq_device.h"
+
+#define ASQ_HIP_TRY(expr)                          \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) {                        \
+      asq::set_last_error(hipGetErrorString(e_));  \
+      return ASQ_EHIP;                             \
+    }                                              \
+  } while (0)
+
+namespace asq {
+
+void set_last_error(const std::string& msg);
+bool log_enabled();
+
+inline size_t align_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
+
+FastDiv make_fastdiv(uint32_t d);
+Geom make_geom(const int dims[4]);
+
+// Bytes per site of one link slot for each storage tier.
+size_t link_slot_bytes(int kind);
+// Bytes per site of one colour vector for each storage tier.
+size_t vec_site_bytes(int kind);
+
+}  // namespace asq
+
+// The opaque gauge handle: resident link copies inside caller-owned storage.
+struct asq_gauge {
+  asq_gauge_desc desc;
+  asq::Geom geom;
+  int device;
+  void* base;                    // caller's storage
+  size_t bytes;
+  void* links[asq::LINK_KINDS];  // nullptr when the tier is not kept
+  int sloppy_link32;             // link kind used by F32 vectors (LINK_F32_R18 or LINK_F32_R12)
+  int sloppy_link16;             // link kind used by F16 vectors
+  int nblk;                      // site blocks of kBlock covering one parity
+};
+
+namespace asq {
+
+// Dslash epilogues.
+enum Epi { EPI_PLAIN = 0, EPI_XPAY_DOT = 1, EPI_RESID = 2 };
+// Column masks (read from the per-column solver state).
+enum Mask { MASK_ALL = 0, MASK_ACTIVE = 1, MASK_RELIABLE = 2 };
+
+// Per-column solver state, resident in device memory.
+struct alignas(128) ColState {
+  double a;        // 4 m^2
+  double bb;       // |b|^2
+  double rr;       // |r|^2 of the iterated residual
+  double alpha;
+  double beta;
+  double maxr;     // max |r| since the last reliable update
+  double true_rr;  // |b - A x|^2 from the last FP64 residual
+  double pAp;
+  double tol;      // relative tolerance on the FP64 true residual
+  double delta;    // reliable-update trigger (0: only at convergence)
+  int maxiter;
+  int active;      // 1 while the column iterates
+  int iters;
+  int want_ru;     // reliable update requested
+  int n_ru;        // reliable updates done
+  int converged;
+  int frozen;      // sloppy residual met tol: skip iterations until the FP64 check
+  int status;      // 0 ok, ASQ_ENAN on a non-finite or non-positive reduction
+};
+
+struct DslashArgs {
+  Geom g;
+  int out_parity;
+  int ncol;
+  int ntiles;
+  const void* links;
+  const void* in;
+  void* out;
+  const void* y;        // XPAY / RESID: the vector multiplied by a = 4 m^2
+  const double* b;      // RESID: right-hand side (F64)
+  const ColState* st;   // per-column a and masks (nullptr: a = 0, all columns)
+  int mask;
+  double* partials;     // [ncol][nblk] FP64 block partials (XPAY_DOT, RESID)
+  int nblk;
+  double coeff_fat;     // 12-real tiers: fat / long coefficients re-applied in-kernel
+  double coeff_long;
+};
+
+// Launch one Dslash; link_kind / in_kind / out_kind select the template.
+int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
+                  hipStream_t s);
+
+// Tuned RHS tile (columns per thread) for a Dslash configuration.
+int tuned_rtile(const asq_gauge* g, int link_kind, int in_kind, int out_kind, int epi, int ncol);
+// Time the candidate tiles once per configuration (in_buf read, out_buf scratch).
+int tune_dslash(const asq_gauge* g, int link_kind, int in_kind, int ncol, const void* in_buf, void* out_buf,
+                hipStream_t s);
+
+}  // namespace asq

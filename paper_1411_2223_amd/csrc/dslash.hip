@@ -1,0 +1,239 @@
+// dslash.hip -- the single-parity asqtad hopping term on gfx950.
+//
+//   out(x) = sum_mu eta_mu(x) [ F_mu(x) in(x+mu) - F_mu(x-mu)^dag in(x-mu)
+//                             + L_mu(x) in(x+3mu) - L_mu(x-3mu)^dag in(x-3mu) ]
+// for x of the output parity (the operator whose cost dominates the paper's
+// CG inverter; the paper gives no formula, this is the standard asqtad form).
+//
+// One thread per output site and R columns: every link is loaded once and
+// applied to R colour vectors.  Links and vectors are site-fastest structures
+// of arrays, so each wavefront load is one contiguous run; neighbour vectors
+// come through L2 (blocks are remapped so each XCD walks a contiguous slab).
+// Epilogues fuse the CG arithmetic that touches the same sites:
+//   EPI_PLAIN    out = D in
+//   EPI_XPAY_DOT out = a_c y - D in, block partials of Re<y, out>   (A p and <p, A p>)
+//   EPI_RESID    out = b - a_c y + D in (FP64), block partials of |out|^2,
+//                stored in the output tier (true residual + sloppy copy)
+#include "asq_internal.h"
+
+namespace asq {
+namespace {
+
+__device__ __forceinline__ bool col_on(const DslashArgs& A, int c) {
+  if (c >= A.ncol) return false;
+  if (A.mask == MASK_ALL || A.st == nullptr) return true;
+  const ColState& s = A.st[c];
+  if (A.mask == MASK_ACTIVE) return s.active != 0 && s.frozen == 0;
+  return s.active != 0 && s.want_ru != 0;
+}
+
+// The four terms of direction MU for output site i, accumulated into R columns.
+template <class Link, class InT, int R, int MU>
+__device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, int c0, const bool (&on)[R],
+                                        Vec3<typename InT::real> (&acc)[R]) {
+  using real = typename InT::real;
+  static_assert(sizeof(typename Link::real) == sizeof(real), "link and vector arithmetic must match");
+  const Geom& g = A.g;
+  const int p = A.out_parity;
+  const int half = g.half;
+  const int jf1 = neighbour<MU>(g, i, s, +1);
+  const int jb1 = neighbour<MU>(g, i, s, -1);
+  const int jf3 = neighbour<MU>(g, i, s, +3);
+  const int jb3 = neighbour<MU>(g, i, s, -3);
+  // 12-real tiers: coefficient * eta * time-boundary sign, applied to U psi.
+  real sf1 = 1, sb1 = 1, sf3 = 1, sb3 = 1;
+  if constexpr (!Link::folded) {
+    const real e = (real)eta_sign<MU>(s);
+    const real cf = (real)A.coeff_fat, cl = (real)A.coeff_long;
+    sf1 = e * cf;
+    sb1 = -e * cf;
+    sf3 = e * cl;
+    sb3 = -e * cl;
+    if constexpr (MU == 3) {
+      if (s.t == g.T - 1) sf1 = -sf1;
+      if (s.t == 0) sb1 = -sb1;
+      if (s.t >= g.T - 3) sf3 = -sf3;
+      if (s.t < 3) sb3 = -sb3;
+    }
+  }
+  {
+    const Mat3<real> U = Link::load(A.links, half, p, MU, i);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (on[r]) {
+        const Vec3<real> v = InT::load(A.in, half, c0 + r, jf1);
+        if constexpr (Link::folded) add3(acc[r], mul(U, v));
+        else axpy3(acc[r], sf1, mul(U, v));
+      }
+  }
+  {
+    const Mat3<real> U = Link::load(A.links, half, 1 - p, MU, jb1);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (on[r]) {
+        const Vec3<real> v = InT::load(A.in, half, c0 + r, jb1);
+        if constexpr (Link::folded) sub3(acc[r], mul_adj(U, v));
+        else axpy3(acc[r], sb1, mul_adj(U, v));
+      }
+  }
+  {
+    const Mat3<real> U = Link::load(A.links, half, p, 4 + MU, i);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (on[r]) {
+        const Vec3<real> v = InT::load(A.in, half, c0 + r, jf3);
+        if constexpr (Link::folded) add3(acc[r], mul(U, v));
+        else axpy3(acc[r], sf3, mul(U, v));
+      }
+  }
+  {
+    const Mat3<real> U = Link::load(A.links, half, 1 - p, 4 + MU, jb3);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (on[r]) {
+        const Vec3<real> v = InT::load(A.in, half, c0 + r, jb3);
+        if constexpr (Link::folded) sub3(acc[r], mul_adj(U, v));
+        else axpy3(acc[r], sb3, mul_adj(U, v));
+      }
+  }
+}
+
+template <class Link, class InT, class OutT, int R, int EPI>
+__global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
+  using real = typename InT::real;
+  const int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int tile = lin % A.ntiles;  // column tiles of the same sites are neighbours in dispatch order
+  const int sblk = lin / A.ntiles;
+  const int c0 = tile * R;
+  bool on[R];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    on[r] = col_on(A, c0 + r);
+    any |= on[r];
+  }
+  if (!any) return;  // uniform over the block
+  const int half = A.g.half;
+  const int i = sblk * kBlock + (int)threadIdx.x;
+  const bool valid = i < half;
+
+  Vec3<real> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[r].c[a].re = acc[r].c[a].im = 0;
+
+  if (valid) {
+    const Site s = decode(A.g, i, A.out_parity);
+    hop_dir<Link, InT, R, 0>(A, i, s, c0, on, acc);
+    hop_dir<Link, InT, R, 1>(A, i, s, c0, on, acc);
+    hop_dir<Link, InT, R, 2>(A, i, s, c0, on, acc);
+    hop_dir<Link, InT, R, 3>(A, i, s, c0, on, acc);
+  }
+
+  if constexpr (EPI == EPI_PLAIN) {
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (on[r]) OutT::store(A.out, half, c0 + r, i, convert<typename OutT::real>(acc[r]));
+    }
+  } else {
+    __shared__ double sh[kBlock / 64];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!on[r]) continue;  // uniform over the block
+      const int c = c0 + r;
+      double d = 0;
+      if (valid) {
+        if constexpr (EPI == EPI_XPAY_DOT) {
+          // out = a y - D in;  d = Re<y, out>
+          const real a = (real)A.st[c].a;
+          const Vec3<real> y = InT::load(A.y, half, c, i);
+          Vec3<real> o;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            o.c[k].re = fmaR(a, y.c[k].re, -acc[r].c[k].re);
+            o.c[k].im = fmaR(a, y.c[k].im, -acc[r].c[k].im);
+          }
+          // the dot uses the stored (possibly 16-bit) A p, the value the update reads back
+          const Vec3<real> os = OutT::store(A.out, half, c, i, convert<typename OutT::real>(o));
+          d = redot_d(y, os);
+        } else {
+          // out = b - a y + D in  (FP64);  d = |out|^2
+          const double a = A.st[c].a;
+          const Vec3<double> y = VecF64::load(A.y, half, c, i);
+          const Vec3<double> b = VecF64::load(A.b, half, c, i);
+          Vec3<double> o;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            o.c[k].re = __builtin_fma(-a, y.c[k].re, b.c[k].re) + (double)acc[r].c[k].re;
+            o.c[k].im = __builtin_fma(-a, y.c[k].im, b.c[k].im) + (double)acc[r].c[k].im;
+          }
+          OutT::store(A.out, half, c, i, convert<typename OutT::real>(o));
+          d = norm2_d(o);
+        }
+      }
+      const double tot = block_sum(d, sh);
+      if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
+      __syncthreads();
+    }
+  }
+}
+
+template <class Link, class InT, class OutT, int R, int EPI>
+int go(const DslashArgs& a0, hipStream_t s) {
+  DslashArgs a = a0;
+  a.ntiles = (a.ncol + R - 1) / R;
+  const long nb = (long)a.nblk * a.ntiles;
+  if (nb <= 0) return ASQ_OK;
+  if (nb >= (1L << 31)) return ASQ_EINVAL;
+  dslash_kernel<Link, InT, OutT, R, EPI><<<(unsigned)nb, kBlock, 0, s>>>(a);
+  return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
+}
+
+template <class Link, class InT, class OutT, int EPI>
+int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
+  switch (rtile) {
+    case 1: return go<Link, InT, OutT, 1, EPI>(a, s);
+    case 2: return go<Link, InT, OutT, 2, EPI>(a, s);
+    case 4: return go<Link, InT, OutT, 4, EPI>(a, s);
+    case 8: return go<Link, InT, OutT, 8, EPI>(a, s);
+  }
+  return ASQ_EINVAL;
+}
+
+template <class Link, class V>
+int pick_epi_sloppy(int epi, int rtile, const DslashArgs& a, hipStream_t s) {
+  if (epi == EPI_PLAIN) return pick_r<Link, V, V, EPI_PLAIN>(rtile, a, s);
+  if (epi == EPI_XPAY_DOT) return pick_r<Link, V, V, EPI_XPAY_DOT>(rtile, a, s);
+  return ASQ_EINVAL;
+}
+
+}  // namespace
+
+int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
+                  hipStream_t s) {
+  if (link_kind == LINK_F64_R18) {
+    if (in_kind != VEC_F64) return ASQ_EINVAL;
+    if (epi == EPI_RESID) {
+      if (out_kind == VEC_F64) return pick_r<LinkF64R18, VecF64, VecF64, EPI_RESID>(rtile, a, s);
+      if (out_kind == VEC_F32) return pick_r<LinkF64R18, VecF64, VecF32, EPI_RESID>(rtile, a, s);
+      return ASQ_EINVAL;
+    }
+    if (out_kind != VEC_F64) return ASQ_EINVAL;
+    return pick_epi_sloppy<LinkF64R18, VecF64>(epi, rtile, a, s);
+  }
+  if (epi == EPI_RESID || in_kind != out_kind) return ASQ_EINVAL;
+  if (link_kind == LINK_F32_R18) {
+    if (in_kind == VEC_F32) return pick_epi_sloppy<LinkF32R18, VecF32>(epi, rtile, a, s);
+    if (in_kind == VEC_F16) return pick_epi_sloppy<LinkF32R18, VecF16>(epi, rtile, a, s);
+  } else if (link_kind == LINK_F32_R12) {
+    if (in_kind == VEC_F32) return pick_epi_sloppy<LinkF32R12, VecF32>(epi, rtile, a, s);
+    if (in_kind == VEC_F16) return pick_epi_sloppy<LinkF32R12, VecF16>(epi, rtile, a, s);
+  } else if (link_kind == LINK_I16_R12) {
+    if (in_kind == VEC_F16) return pick_epi_sloppy<LinkI16R12, VecF16>(epi, rtile, a, s);
+  }
+  return ASQ_EINVAL;
+}
+
+}  // namespace asq

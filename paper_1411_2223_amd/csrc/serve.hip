@@ -1,0 +1,449 @@
+// serve.hip -- request loop with continuous batching for CG solves.
+//
+// A scheduler thread owns "runs": one batch of column slots per (gauge field,
+// precision mode), with its workspace carved from the caller's arena (the HBM
+// budget) and its own HIP stream.  Every run advances in blocks of
+// poll_iters CG iterations (one hipGraph replay).  Between blocks, queued
+// requests join a run when enough contiguous column slots are free, finished
+// columns retire, and their slots go back to the pool; runs of different
+// fields overlap on the device through their streams.  A column's arithmetic
+// depends only on its own data (per-column scalars, fixed reduction order, and
+// reliable updates at multiples of poll_iters of its own iterations), so a
+// request gives the same result alone and in the mix.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "asq_batch.h"
+#include "asq_internal.h"
+
+namespace asq {
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Run;
+
+struct Request {
+  uint64_t id = 0;
+  int gauge_id = 0;
+  int nrhs = 0;
+  std::vector<double> masses;
+  const double* b = nullptr;
+  double* x = nullptr;
+  asq_cg_params params{};
+  clk::time_point t_submit, t_done;
+  int state = 0;  // 0 queued, 1 running, 2 finishing (copy-out in flight), 3 done
+  int rc = ASQ_OK;
+  int cols_left = 0;
+  int slot0 = -1;
+  Run* run = nullptr;
+  hipEvent_t done_ev = nullptr;
+  std::vector<asq_cg_stats> stats;
+};
+
+struct Run {
+  const asq_gauge* g = nullptr;
+  int mode = 0;
+  int cap = 0;
+  int poll = 8;
+  bool use_graph = true;
+  size_t off = 0, bytes = 0;  // arena range
+  Batch B;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev = nullptr;
+  bool in_flight = false;
+  ColState* pinned = nullptr;   // [cap] mirror of the device states
+  ColState* staging = nullptr;  // [cap] host states uploaded when columns join
+  std::vector<Request*> owner;  // per column slot
+  clk::time_point t_block;
+};
+
+// First-fit allocator over the arena.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  void init(void* b, size_t n) {
+    base = (char*)b;
+    size = n;
+    free_.clear();
+    free_[0] = n;
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = align_up(n, 256);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n;
+        const size_t o = it->first + n;
+        free_.erase(it);
+        if (rest) free_[o] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = align_up(n, 256);
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+}  // namespace
+}  // namespace asq
+
+using namespace asq;
+
+struct asq_server {
+  Arena arena;
+  int max_streams = 1;
+  int max_cols = 1;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> queue;
+  std::map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::vector<const asq_gauge*> gauges;
+  std::list<std::unique_ptr<Run>> runs;
+  uint64_t next_id = 1;
+  bool stop = false;
+  int error = ASQ_OK;
+  std::thread worker;
+};
+
+namespace asq {
+namespace {
+
+constexpr size_t kMaxQueue = 1 << 16;
+
+void destroy_run(asq_server* S, Run* r) {
+  if (r->stream) hipStreamSynchronize(r->stream);
+  if (r->exec) hipGraphExecDestroy(r->exec);
+  if (r->ev) hipEventDestroy(r->ev);
+  if (r->stream) hipStreamDestroy(r->stream);
+  if (r->pinned) hipHostFree(r->pinned);
+  if (r->staging) hipHostFree(r->staging);
+  S->arena.release(r->off, r->bytes);
+}
+
+// Create a run for (gauge, mode) if the arena and the stream budget allow it.
+Run* make_run(asq_server* S, const asq_gauge* g, const asq_cg_params& p) {
+  if ((int)S->runs.size() >= S->max_streams) return nullptr;
+  const size_t need = batch_bytes(g, S->max_cols, p.mode, true);
+  size_t off = 0;
+  if (!S->arena.alloc(need, &off)) return nullptr;
+  std::unique_ptr<Run> r(new Run());
+  r->g = g;
+  r->mode = p.mode;
+  r->cap = S->max_cols;
+  r->poll = p.poll_iters > 0 ? p.poll_iters : 8;
+  r->use_graph = p.use_graph != 0;
+  r->off = off;
+  r->bytes = need;
+  r->owner.assign(r->cap, nullptr);
+  bool ok = batch_carve(r->B, g, r->cap, p.mode, S->arena.base + off, need, nullptr, nullptr) == ASQ_OK;
+  ok = ok && hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&r->pinned, r->cap * sizeof(ColState), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&r->staging, r->cap * sizeof(ColState), hipHostMallocDefault) == hipSuccess;
+  if (ok) {
+    // every slot starts inactive
+    memset(r->staging, 0, r->cap * sizeof(ColState));
+    ok = hipMemcpyAsync(r->B.st, r->staging, r->cap * sizeof(ColState), hipMemcpyHostToDevice, r->stream) ==
+         hipSuccess;
+  }
+  ok = ok && batch_tune(r->B, r->stream) == ASQ_OK;
+  if (ok && r->use_graph) ok = capture_block(r->B, r->poll, r->stream, &r->exec) == ASQ_OK;
+  ok = ok && hipStreamSynchronize(r->stream) == hipSuccess;
+  if (!ok) {
+    destroy_run(S, r.get());
+    return nullptr;
+  }
+  S->runs.push_back(std::move(r));
+  return S->runs.back().get();
+}
+
+int free_slots(const Run* r, int n) {
+  int runlen = 0;
+  for (int c = 0; c < r->cap; ++c) {
+    runlen = r->owner[c] ? 0 : runlen + 1;
+    if (runlen == n) return c - n + 1;
+  }
+  return -1;
+}
+
+// Place a queued request into a run (new columns start at this block boundary).
+bool admit(asq_server* S, Request* q) {
+  const asq_gauge* g = S->gauges[q->gauge_id];
+  Run* run = nullptr;
+  int c0 = -1;
+  for (auto& r : S->runs)
+    if (r->g == g && r->mode == q->params.mode && (c0 = free_slots(r.get(), q->nrhs)) >= 0) {
+      run = r.get();
+      break;
+    }
+  if (!run) {
+    run = make_run(S, g, q->params);
+    if (!run) return false;
+    c0 = free_slots(run, q->nrhs);
+    if (c0 < 0) return false;
+  }
+  const size_t half = (size_t)g->geom.half;
+  hipStream_t s = run->stream;
+  Batch& B = run->B;
+  asq_cg_params p = q->params;
+  p.mode = run->mode;
+  // per-column constants, then b into the slots, then the init kernels
+  Batch tmp = B;
+  tmp.ncol = q->nrhs;
+  init_states(tmp, q->masses.data(), &p, run->staging + c0);
+  bool ok = hipMemcpyAsync(B.st + c0, run->staging + c0, q->nrhs * sizeof(ColState), hipMemcpyHostToDevice, s) ==
+            hipSuccess;
+  ok = ok && hipMemcpyAsync(B.b + (size_t)c0 * half * 6, q->b, (size_t)q->nrhs * half * 48,
+                            hipMemcpyDeviceToDevice, s) == hipSuccess;
+  ok = ok && enqueue_init(B, c0, q->nrhs, s) == ASQ_OK;
+  if (!ok) {
+    q->rc = ASQ_EHIP;
+    q->state = 3;
+    q->t_done = clk::now();
+    return true;
+  }
+  for (int c = 0; c < q->nrhs; ++c) run->owner[c0 + c] = q;
+  q->run = run;
+  q->slot0 = c0;
+  q->cols_left = q->nrhs;
+  q->stats.assign(q->nrhs, asq_cg_stats{});
+  q->state = 1;
+  return true;
+}
+
+void launch_block(Run* r) {
+  if (r->exec) hipGraphLaunch(r->exec, r->stream);
+  else enqueue_block(r->B, r->poll, r->stream);
+  hipMemcpyAsync(r->pinned, r->B.st, r->cap * sizeof(ColState), hipMemcpyDeviceToHost, r->stream);
+  hipEventRecord(r->ev, r->stream);
+  r->in_flight = true;
+  r->t_block = clk::now();
+}
+
+// Retire finished columns of a run whose block has completed.
+void harvest(asq_server* S, Run* r) {
+  const size_t half = (size_t)r->g->geom.half;
+  for (int c = 0; c < r->cap; ++c) {
+    Request* q = r->owner[c];
+    if (!q || q->state != 1) continue;
+    const ColState& st = r->pinned[c];
+    if (st.active) continue;
+    const int k = c - q->slot0;
+    int worst = ASQ_OK;
+    Batch one = r->B;
+    one.ncol = 1;
+    fill_stats(one, &st, 0.0, &q->stats[k], &worst);
+    if (worst != ASQ_OK && (q->rc == ASQ_OK || worst == ASQ_ENAN)) q->rc = worst;
+    r->owner[c] = nullptr;  // slot reusable: later work on this stream is ordered after the copy-out
+    if (--q->cols_left == 0) {
+      hipMemcpyAsync(q->x, r->B.x + (size_t)q->slot0 * half * 6, (size_t)q->nrhs * half * 48,
+                     hipMemcpyDeviceToDevice, r->stream);
+      hipEventCreateWithFlags(&q->done_ev, hipEventDisableTiming);
+      hipEventRecord(q->done_ev, r->stream);
+      q->state = 2;
+    }
+  }
+  (void)S;
+}
+
+void finish_copies(asq_server* S) {
+  for (auto& kv : S->reqs) {
+    Request* q = kv.second.get();
+    if (q->state == 2 && hipEventQuery(q->done_ev) == hipSuccess) {
+      hipEventDestroy(q->done_ev);
+      q->done_ev = nullptr;
+      q->t_done = clk::now();
+      const double secs = std::chrono::duration<double>(q->t_done - q->t_submit).count();
+      for (auto& st : q->stats) st.seconds = secs;
+      q->state = 3;
+    }
+  }
+}
+
+bool run_idle(const Run* r) {
+  for (auto* o : r->owner)
+    if (o) return false;
+  return true;
+}
+
+void worker_main(asq_server* S) {
+  hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    // admission at block boundaries: only runs that are not in flight take new columns
+    for (auto it = S->queue.begin(); it != S->queue.end();) {
+      Request* q = *it;
+      bool placed = false;
+      bool blocked_by_flight = false;
+      const asq_gauge* g = S->gauges[q->gauge_id];
+      for (auto& r : S->runs)
+        if (r->g == g && r->mode == q->params.mode && r->in_flight && free_slots(r.get(), q->nrhs) >= 0)
+          blocked_by_flight = true;
+      if (!blocked_by_flight) placed = admit(S, q);
+      if (placed) it = S->queue.erase(it);
+      else ++it;
+    }
+    bool any_flight = false;
+    for (auto& r : S->runs) {
+      if (!r->in_flight && !run_idle(r.get())) launch_block(r.get());
+      any_flight |= r->in_flight;
+    }
+    finish_copies(S);
+    // drop idle runs when others wait for arena memory or streams
+    if (!S->queue.empty()) {
+      for (auto it = S->runs.begin(); it != S->runs.end();) {
+        Run* r = it->get();
+        if (!r->in_flight && run_idle(r)) {
+          bool copies_pending = false;
+          for (auto& kv : S->reqs)
+            if (kv.second->state == 2 && kv.second->run == r) copies_pending = true;
+          if (!copies_pending) {
+            destroy_run(S, r);
+            it = S->runs.erase(it);
+            continue;
+          }
+        }
+        ++it;
+      }
+    }
+    bool copies = false;
+    for (auto& kv : S->reqs) copies |= kv.second->state == 2;
+    if (S->stop && S->queue.empty() && !any_flight && !copies) break;
+    if (!any_flight && S->queue.empty() && !copies) {
+      S->cv.wait(lk);
+      continue;
+    }
+    // poll the in-flight blocks without holding the lock
+    lk.unlock();
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+    lk.lock();
+    for (auto& r : S->runs)
+      if (r->in_flight && hipEventQuery(r->ev) == hipSuccess) {
+        r->in_flight = false;
+        harvest(S, r.get());
+      }
+  }
+  for (auto& r : S->runs) destroy_run(S, r.get());
+  S->runs.clear();
+}
+
+}  // namespace
+}  // namespace asq
+
+extern "C" int serve_create(void* arena_dev, size_t arena_bytes, int max_streams, int max_cols, asq_server** out) {
+  if (!out || !arena_dev || arena_bytes == 0 || max_streams < 1 || max_streams > 64 || max_cols < 1 ||
+      max_cols > 4096 || ((uintptr_t)arena_dev & 255)) {
+    set_last_error("serve_create: invalid arguments (arena 256-byte aligned, 1 <= max_streams <= 64)");
+    return ASQ_EINVAL;
+  }
+  asq_server* S = new asq_server();
+  S->arena.init(arena_dev, arena_bytes);
+  S->max_streams = max_streams;
+  S->max_cols = max_cols;
+  hipGetDevice(&S->device);
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return ASQ_OK;
+}
+
+extern "C" int serve_register_gauge(asq_server* S, const asq_gauge* g, int* gauge_id) {
+  if (!S || !g || !gauge_id) return ASQ_EINVAL;
+  if (!g->links[LINK_F64_R18]) {
+    set_last_error("serve_register_gauge: the gauge field must keep FP64 links");
+    return ASQ_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->gauges.push_back(g);
+  *gauge_id = (int)S->gauges.size() - 1;
+  return ASQ_OK;
+}
+
+extern "C" int serve_submit(asq_server* S, int gauge_id, int nrhs, const double* masses, const double* b_dev,
+                            double* x_dev, const asq_cg_params* params, uint64_t* ticket) {
+  if (!S || !masses || !b_dev || !x_dev || !params || !ticket || nrhs <= 0) return ASQ_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (gauge_id < 0 || gauge_id >= (int)S->gauges.size()) return ASQ_EINVAL;
+  const asq_gauge* g = S->gauges[gauge_id];
+  if (check_params(g, params)) {
+    set_last_error("serve_submit: invalid parameters");
+    return ASQ_EINVAL;
+  }
+  for (int c = 0; c < nrhs; ++c)
+    if (!(masses[c] > 0) || !isfinite(masses[c])) return ASQ_EINVAL;
+  if (((uintptr_t)b_dev & 15) || ((uintptr_t)x_dev & 15)) return ASQ_EINVAL;
+  if (nrhs > S->max_cols || batch_bytes(g, S->max_cols, params->mode, true) > S->arena.size) {
+    set_last_error("serve_submit: request can never fit (nrhs > max_cols or a batch exceeds the arena)");
+    return ASQ_ENOMEM;
+  }
+  if (S->queue.size() >= kMaxQueue) return ASQ_EAGAIN;
+  std::unique_ptr<Request> q(new Request());
+  q->id = S->next_id++;
+  q->gauge_id = gauge_id;
+  q->nrhs = nrhs;
+  q->masses.assign(masses, masses + nrhs);
+  q->b = b_dev;
+  q->x = x_dev;
+  q->params = *params;
+  q->t_submit = clk::now();
+  *ticket = q->id;
+  S->queue.push_back(q.get());
+  S->reqs[q->id] = std::move(q);
+  S->cv.notify_one();
+  return ASQ_OK;
+}
+
+extern "C" int serve_poll(asq_server* S, uint64_t ticket, asq_cg_stats* per_rhs, double* latency_s) {
+  if (!S) return ASQ_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return ASQ_EINVAL;
+  Request* q = it->second.get();
+  if (q->state != 3) return ASQ_PENDING;
+  if (per_rhs)
+    for (int c = 0; c < q->nrhs; ++c) per_rhs[c] = q->stats[c];
+  if (latency_s) *latency_s = std::chrono::duration<double>(q->t_done - q->t_submit).count();
+  const int rc = q->rc;
+  S->reqs.erase(it);
+  return rc;
+}
+
+extern "C" int serve_destroy(asq_server* S) {
+  if (!S) return ASQ_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv.notify_one();
+  }
+  S->worker.join();
+  delete S;
+  return ASQ_OK;
+}

@@ -1,0 +1,471 @@
+// solver.hip -- CG drivers on even sites: plain FP64 CG and mixed-precision
+// CG with reliable updates (the paper's inverter does "most of the
+// calculations in single precision", section "GTX Titan Black"; QUDA's CG
+// that it adopts is mixed precision, section "CPS & QUDA").
+//
+// One iteration, all columns at once, all scalars on the device:
+//   t   = D_oe p                      (sloppy Dslash, odd sites)
+//   Ap  = a p - D_eo t, <p, Ap>       (sloppy Dslash with fused xpay + dot)
+//   alpha = rr / <p, Ap>              (fixed-order FP64 reduction)
+//   x  += alpha p (FP64), r -= alpha Ap, |r|^2
+//   beta = |r|^2 / rr; triggers       (fixed-order FP64 reduction)
+//   p   = r + beta p
+// Every `poll` iterations the reliable update runs for the columns that asked
+// for it: r = b - A x with the FP64 operator, which also decides convergence
+// on the true residual.  The host only polls the column flags between blocks
+// (one block ahead, so the GPU never waits on the host); a block can be
+// captured once into a hipGraph and replayed.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "asq_internal.h"
+#include "asq_solver.h"
+#include "asq_batch.h"
+
+namespace asq {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+bool log_enabled() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = getenv("ASQ_LOG");
+    on = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return on == 1;
+}
+
+int mode_pt(int mode) { return mode == ASQ_MODE_F64 ? VEC_F64 : (mode == ASQ_MODE_MIXED32 ? VEC_F32 : VEC_F16); }
+int mode_rt(int mode) { return mode == ASQ_MODE_F64 ? VEC_F64 : VEC_F32; }
+
+int sloppy_link(const asq_gauge* g, int mode) {
+  if (mode == ASQ_MODE_F64) return LINK_F64_R18;
+  if (mode == ASQ_MODE_MIXED32) return g->sloppy_link32;
+  return g->sloppy_link16;
+}
+
+size_t batch_bytes(const asq_gauge* g, int ncol, int mode, bool with_bx) {
+  const size_t half = (size_t)g->geom.half;
+  const int pt = mode_pt(mode), rt = mode_rt(mode);
+  size_t n = 0;
+  n += align_up((size_t)ncol * sizeof(ColState), 256);
+  n += align_up((size_t)ncol * g->nblk * sizeof(double), 256);
+  n += align_up((size_t)ncol * half * vec_site_bytes(rt), 256);      // r
+  n += 3 * align_up((size_t)ncol * half * vec_site_bytes(pt), 256);  // p, Ap, t
+  if (mode != ASQ_MODE_F64) n += align_up((size_t)ncol * half * 48, 256);  // t64
+  if (with_bx) n += 2 * align_up((size_t)ncol * half * 48, 256);         // b, x
+  return n;
+}
+
+int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, size_t bytes, const double* b,
+                double* x) {
+  const size_t need = batch_bytes(g, ncol, mode, b == nullptr);
+  if (bytes < need) return ASQ_ENOMEM;
+  const size_t half = (size_t)g->geom.half;
+  const int pt = mode_pt(mode), rt = mode_rt(mode);
+  char* q = (char*)work;
+  auto take = [&](size_t n) {
+    char* r = q;
+    q += align_up(n, 256);
+    return (void*)r;
+  };
+  B.g = g;
+  B.ncol = ncol;
+  B.mode = mode;
+  B.pt = pt;
+  B.rt = rt;
+  B.st = (ColState*)take((size_t)ncol * sizeof(ColState));
+  B.partials = (double*)take((size_t)ncol * g->nblk * sizeof(double));
+  B.r = take((size_t)ncol * half * vec_site_bytes(rt));
+  B.p = take((size_t)ncol * half * vec_site_bytes(pt));
+  B.Ap = take((size_t)ncol * half * vec_site_bytes(pt));
+  B.t = take((size_t)ncol * half * vec_site_bytes(pt));
+  B.t64 = mode == ASQ_MODE_F64 ? B.t : take((size_t)ncol * half * 48);
+  if (b == nullptr) {
+    B.b = (double*)take((size_t)ncol * half * 48);
+    B.x = (double*)take((size_t)ncol * half * 48);
+  } else {
+    B.b = const_cast<double*>(b);
+    B.x = x;
+  }
+  B.link = sloppy_link(g, mode);
+  batch_pick_tiles(B);
+  return ASQ_OK;
+}
+
+void batch_pick_tiles(Batch& B) {
+  const asq_gauge* g = B.g;
+  B.rt_sloppy_xpay = tuned_rtile(g, B.link, B.pt, B.pt, EPI_XPAY_DOT, B.ncol);
+  B.rt_sloppy_plain = tuned_rtile(g, B.link, B.pt, B.pt, EPI_PLAIN, B.ncol);
+  B.rt64_plain = tuned_rtile(g, LINK_F64_R18, VEC_F64, VEC_F64, EPI_PLAIN, B.ncol);
+  B.rt64_resid = tuned_rtile(g, LINK_F64_R18, VEC_F64, B.rt, EPI_RESID, B.ncol);
+}
+
+// Autotune the batch's Dslash launches on its own buffers (p -> t, x -> t64),
+// before the buffers hold solver data.
+int batch_tune(Batch& B, hipStream_t s) {
+  int rc = tune_dslash(B.g, B.link, B.pt, B.ncol, B.p, B.t, s);
+  if (rc) return rc;
+  rc = tune_dslash(B.g, LINK_F64_R18, VEC_F64, B.ncol, B.x, B.t64, s);
+  if (rc) return rc;
+  batch_pick_tiles(B);
+  return ASQ_OK;
+}
+
+static DslashArgs dargs(const Batch& B, int out_parity, const void* in, void* out, int mask) {
+  DslashArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = B.g->geom;
+  a.out_parity = out_parity;
+  a.ncol = B.ncol;
+  a.in = in;
+  a.out = out;
+  a.st = B.st;
+  a.mask = mask;
+  a.partials = B.partials;
+  a.nblk = B.g->nblk;
+  a.coeff_fat = B.g->desc.fat_scale;
+  a.coeff_long = B.g->desc.long_scale;
+  return a;
+}
+
+static VecArgs vargs(const Batch& B, int c0) {
+  VecArgs v;
+  const size_t half = (size_t)B.g->geom.half;
+  v.half = (int)half;
+  v.nblk = B.g->nblk;
+  // column offset c0: shift every per-column pointer
+  v.b = B.b + (size_t)c0 * half * 6;
+  v.x = B.x + (size_t)c0 * half * 6;
+  v.r = (char*)B.r + (size_t)c0 * half * vec_site_bytes(B.rt);
+  v.p = (char*)B.p + (size_t)c0 * half * vec_site_bytes(B.pt);
+  v.Ap = (char*)B.Ap + (size_t)c0 * half * vec_site_bytes(B.pt);
+  v.st = B.st + c0;
+  v.partials = B.partials + (size_t)c0 * B.g->nblk;
+  return v;
+}
+
+int enqueue_init(const Batch& B, int c0, int n, hipStream_t s) {
+  VecArgs v = vargs(B, c0);
+  int rc = launch_vec_kernel(VK_INIT, B.pt, B.rt, v, n, s);
+  if (rc) return rc;
+  return launch_reduce(OP_INIT, v.st, v.partials, v.nblk, n, s);
+}
+
+int enqueue_iteration(const Batch& B, hipStream_t s) {
+  const Gauge_t* g = B.g;
+  const void* L = g->links[B.link];
+  DslashArgs d1 = dargs(B, 1, B.p, B.t, MASK_ACTIVE);
+  d1.links = L;
+  int rc = launch_dslash(B.link, B.pt, B.pt, EPI_PLAIN, B.rt_sloppy_plain, d1, s);
+  if (rc) return rc;
+  DslashArgs d2 = dargs(B, 0, B.t, B.Ap, MASK_ACTIVE);
+  d2.links = L;
+  d2.y = B.p;
+  rc = launch_dslash(B.link, B.pt, B.pt, EPI_XPAY_DOT, B.rt_sloppy_xpay, d2, s);
+  if (rc) return rc;
+  rc = launch_reduce(OP_ALPHA, B.st, B.partials, g->nblk, B.ncol, s);
+  if (rc) return rc;
+  VecArgs v = vargs(B, 0);
+  rc = launch_vec_kernel(VK_XR, B.pt, B.rt, v, B.ncol, s);
+  if (rc) return rc;
+  rc = launch_reduce(OP_BETA, B.st, B.partials, g->nblk, B.ncol, s);
+  if (rc) return rc;
+  return launch_vec_kernel(VK_P, B.pt, B.rt, v, B.ncol, s);
+}
+
+// r = b - A x with FP64 links and vectors for the columns that asked for it.
+int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s) {
+  const Gauge_t* g = B.g;
+  const void* L = g->links[LINK_F64_R18];
+  DslashArgs d1 = dargs(B, 1, B.x, B.t64, mask);
+  d1.links = L;
+  int rc = launch_dslash(LINK_F64_R18, VEC_F64, VEC_F64, EPI_PLAIN, B.rt64_plain, d1, s);
+  if (rc) return rc;
+  DslashArgs d2 = dargs(B, 0, B.t64, B.r, mask);
+  d2.links = L;
+  d2.y = B.x;
+  d2.b = B.b;
+  rc = launch_dslash(LINK_F64_R18, VEC_F64, B.rt, EPI_RESID, B.rt64_resid, d2, s);
+  if (rc) return rc;
+  return launch_reduce(op, B.st, B.partials, g->nblk, B.ncol, s);
+}
+
+int enqueue_block(const Batch& B, int iters, hipStream_t s) {
+  for (int k = 0; k < iters; ++k) {
+    const int rc = enqueue_iteration(B, s);
+    if (rc) return rc;
+  }
+  return enqueue_reliable(B, MASK_RELIABLE, OP_RU, s);
+}
+
+// Thread-local host resources: pinned state mirrors, events, a capture stream.
+struct HostRes {
+  int device = -1;
+  ColState* pinned = nullptr;
+  size_t pinned_cols = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t cap = nullptr;
+  ~HostRes() {
+    if (pinned) hipHostFree(pinned);
+    for (auto& e : ev)
+      if (e) hipEventDestroy(e);
+    if (cap) hipStreamDestroy(cap);
+  }
+  int ensure(size_t cols) {
+    int dev = 0;
+    ASQ_HIP_TRY(hipGetDevice(&dev));
+    if (dev != device) {
+      if (pinned) hipHostFree(pinned);
+      for (auto& e : ev)
+        if (e) hipEventDestroy(e);
+      if (cap) hipStreamDestroy(cap);
+      pinned = nullptr;
+      pinned_cols = 0;
+      ev[0] = ev[1] = nullptr;
+      cap = nullptr;
+      device = dev;
+      ASQ_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+      ASQ_HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+      ASQ_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    }
+    if (pinned_cols < 2 * cols) {
+      if (pinned) hipHostFree(pinned);
+      pinned = nullptr;
+      ASQ_HIP_TRY(hipHostMalloc((void**)&pinned, 2 * cols * sizeof(ColState), hipHostMallocDefault));
+      pinned_cols = 2 * cols;
+    }
+    return ASQ_OK;
+  }
+};
+
+static HostRes& host_res() {
+  thread_local HostRes r;
+  return r;
+}
+
+int capture_block(const Batch& B, int iters, hipStream_t cap, hipGraphExec_t* exec) {
+  hipGraph_t graph = nullptr;
+  ASQ_HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_block(B, iters, cap);
+  hipError_t e = hipStreamEndCapture(cap, &graph);
+  if (rc) {
+    if (graph) hipGraphDestroy(graph);
+    return rc;
+  }
+  ASQ_HIP_TRY(e);
+  e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  ASQ_HIP_TRY(e);
+  return ASQ_OK;
+}
+
+void fill_stats(const Batch& B, const ColState* S, double seconds, asq_cg_stats* out, int* worst) {
+  const double half = (double)B.g->geom.half;
+  double flops = 0;
+  for (int c = 0; c < B.ncol; ++c)
+    flops += half * ((2.0 * 1146 + 72) * S[c].iters + (2.0 * 1146 + 36) * S[c].n_ru);
+  for (int c = 0; c < B.ncol; ++c) {
+    asq_cg_stats& o = out[c];
+    o.iters = S[c].iters;
+    o.reliable_updates = S[c].n_ru;
+    o.converged = S[c].converged;
+    o.true_resid = S[c].bb > 0 ? sqrt(S[c].true_rr / S[c].bb) : 0.0;
+    o.seconds = seconds;
+    o.gflops = seconds > 0 ? flops / seconds * 1e-9 : 0.0;
+    int st = S[c].status;
+    if (st == 0 && !S[c].converged) st = ASQ_ENOCONV;
+    o.status = st;
+    if (st == ASQ_ENAN) *worst = ASQ_ENAN;
+    else if (st == ASQ_ENOCONV && *worst == ASQ_OK) *worst = ASQ_ENOCONV;
+  }
+}
+
+int check_params(const asq_gauge* g, const asq_cg_params* p) {
+  if (!p) return ASQ_EINVAL;
+  if (!(p->tol > 0) || !isfinite(p->tol) || p->maxiter <= 0) return ASQ_EINVAL;
+  if (p->mode < ASQ_MODE_F64 || p->mode > ASQ_MODE_MIXED16) return ASQ_EINVAL;
+  if (!(p->delta >= 0 && p->delta < 1)) return ASQ_EINVAL;
+  if (p->poll_iters < 0 || p->poll_iters > 4096) return ASQ_EINVAL;
+  if (!g->links[LINK_F64_R18]) return ASQ_EINVAL;  // true residuals need the FP64 links
+  if (p->mode == ASQ_MODE_MIXED32 && !g->links[g->sloppy_link32]) return ASQ_EINVAL;
+  if (p->mode == ASQ_MODE_MIXED16 && !g->links[g->sloppy_link16]) return ASQ_EINVAL;
+  return ASQ_OK;
+}
+
+void init_states(const Batch& B, const double* masses, const asq_cg_params* p, ColState* host) {
+  for (int c = 0; c < B.ncol; ++c) {
+    memset(&host[c], 0, sizeof(ColState));
+    host[c].a = 4.0 * masses[c] * masses[c];
+    host[c].tol = p->tol;
+    host[c].delta = p->mode == ASQ_MODE_F64 ? 0.0 : p->delta;
+    host[c].maxiter = p->maxiter;
+  }
+}
+
+}  // namespace asq
+
+using namespace asq;
+
+extern "C" size_t asq_workspace_bytes(const asq_gauge* g, int nrhs, int mode) {
+  if (!g || nrhs <= 0 || mode < ASQ_MODE_F64 || mode > ASQ_MODE_MIXED16) return 0;
+  return batch_bytes(g, nrhs, mode, false);
+}
+
+extern "C" int cg_solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev,
+                              double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
+                              asq_cg_stats* stats, void* hip_stream) {
+  if (!g || nrhs <= 0 || !masses || !b_dev || !x_dev || !work_dev || !stats) {
+    set_last_error("cg_solve_batch: null pointer or nrhs <= 0");
+    return ASQ_EINVAL;
+  }
+  if (check_params(g, params)) {
+    set_last_error("cg_solve_batch: invalid parameters (tol > 0, maxiter > 0, mode, 0 <= delta < 1, link tiers)");
+    return ASQ_EINVAL;
+  }
+  for (int c = 0; c < nrhs; ++c)
+    if (!(masses[c] > 0) || !isfinite(masses[c])) {
+      set_last_error("cg_solve_batch: masses must be positive and finite");
+      return ASQ_EINVAL;
+    }
+  if (((uintptr_t)b_dev & 15) || ((uintptr_t)x_dev & 15) || ((uintptr_t)work_dev & 255)) {
+    set_last_error("cg_solve_batch: b/x must be 16-byte and work 256-byte aligned");
+    return ASQ_EINVAL;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)hip_stream;
+  Batch B;
+  int rc = batch_carve(B, g, nrhs, params->mode, work_dev, work_bytes, b_dev, x_dev);
+  if (rc) {
+    set_last_error("cg_solve_batch: workspace smaller than asq_workspace_bytes()");
+    return rc;
+  }
+  if ((rc = batch_tune(B, s))) return rc;
+  HostRes& H = host_res();
+  if ((rc = H.ensure((size_t)nrhs))) return rc;
+  ColState* mirror[2] = {H.pinned, H.pinned + nrhs};
+  init_states(B, masses, params, mirror[0]);
+  ASQ_HIP_TRY(hipMemcpyAsync(B.st, mirror[0], nrhs * sizeof(ColState), hipMemcpyHostToDevice, s));
+  if ((rc = enqueue_init(B, 0, nrhs, s))) return rc;
+  // the mirror is reused below: make sure the upload has consumed it
+  ASQ_HIP_TRY(hipStreamSynchronize(s));
+
+  const int poll = params->poll_iters > 0 ? params->poll_iters : 8;
+  hipGraphExec_t exec = nullptr;
+  if (params->use_graph) {
+    rc = capture_block(B, poll, H.cap, &exec);
+    if (rc) return rc;
+  }
+  int slot = 0, pending = -1, last = -1;
+  long blocks = 0;
+  const long max_blocks = (long)params->maxiter / poll + 4;
+  for (;;) {
+    if (exec) {
+      hipError_t e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) {
+        hipGraphExecDestroy(exec);
+        set_last_error(hipGetErrorString(e));
+        return ASQ_EHIP;
+      }
+    } else if ((rc = enqueue_block(B, poll, s))) {
+      return rc;
+    }
+    ++blocks;
+    ASQ_HIP_TRY(hipMemcpyAsync(mirror[slot], B.st, nrhs * sizeof(ColState), hipMemcpyDeviceToHost, s));
+    ASQ_HIP_TRY(hipEventRecord(H.ev[slot], s));
+    last = slot;
+    if (pending >= 0) {
+      ASQ_HIP_TRY(hipEventSynchronize(H.ev[pending]));
+      bool any = false;
+      for (int c = 0; c < nrhs; ++c) any |= mirror[pending][c].active != 0;
+      if (!any) break;
+    }
+    if (blocks > max_blocks + 2) break;  // the device enforces maxiter; this only bounds the loop
+    pending = slot;
+    slot ^= 1;
+  }
+  ASQ_HIP_TRY(hipStreamSynchronize(s));
+  if (exec) hipGraphExecDestroy(exec);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = ASQ_OK;
+  fill_stats(B, mirror[last], secs, stats, &worst);
+  if (log_enabled())
+    fprintf(stderr, "[asq] cg_solve_batch ncol=%d mode=%d iters0=%d ru0=%d resid0=%.3e %.3f s\n", nrhs,
+            params->mode, stats[0].iters, stats[0].reliable_updates, stats[0].true_resid, secs);
+  return worst;
+}
+
+extern "C" int cg_solve(const asq_gauge* g, double mass, const double* b_dev, double* x_dev, void* work_dev,
+                        size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats, void* hip_stream) {
+  return cg_solve_batch(g, 1, &mass, b_dev, x_dev, work_dev, work_bytes, params, stats, hip_stream);
+}
+
+extern "C" int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
+                                void* out_dev, void* hip_stream) {
+  if (!g || !in_dev || !out_dev || nrhs <= 0 || (out_parity != 0 && out_parity != 1)) {
+    set_last_error("asqtad_dslash_eo: null pointer, nrhs <= 0 or parity not 0/1");
+    return ASQ_EINVAL;
+  }
+  int link;
+  if (prec == ASQ_F64) link = LINK_F64_R18;
+  else if (prec == ASQ_F32) link = g->sloppy_link32;
+  else if (prec == ASQ_F16) link = g->sloppy_link16;
+  else {
+    set_last_error("asqtad_dslash_eo: prec must be ASQ_F64, ASQ_F32 or ASQ_F16");
+    return ASQ_EINVAL;
+  }
+  if (!g->links[link]) {
+    set_last_error("asqtad_dslash_eo: the gauge field keeps no links for this precision");
+    return ASQ_EINVAL;
+  }
+  if (((uintptr_t)in_dev & 15) || ((uintptr_t)out_dev & 15)) {
+    set_last_error("asqtad_dslash_eo: vectors must be 16-byte aligned");
+    return ASQ_EINVAL;
+  }
+  const int vk = prec == ASQ_F64 ? VEC_F64 : (prec == ASQ_F32 ? VEC_F32 : VEC_F16);
+  DslashArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = g->geom;
+  a.out_parity = out_parity;
+  a.ncol = nrhs;
+  a.links = g->links[link];
+  a.in = in_dev;
+  a.out = out_dev;
+  a.st = nullptr;
+  a.mask = MASK_ALL;
+  a.nblk = g->nblk;
+  a.coeff_fat = g->desc.fat_scale;
+  a.coeff_long = g->desc.long_scale;
+  int rc0 = tune_dslash(g, link, vk, nrhs, in_dev, out_dev, (hipStream_t)hip_stream);
+  if (rc0) return rc0;
+  const int rt = tuned_rtile(g, link, vk, vk, EPI_PLAIN, nrhs);
+  const int rc = launch_dslash(link, vk, vk, EPI_PLAIN, rt, a, (hipStream_t)hip_stream);
+  if (rc == ASQ_EHIP) set_last_error(hipGetErrorString(hipGetLastError()));
+  return rc;
+}
+
+extern "C" const char* asq_strerror(int code) {
+  switch (code) {
+    case ASQ_OK: return "ok";
+    case ASQ_PENDING: return "pending";
+    case ASQ_EINVAL: return "invalid argument";
+    case ASQ_ENOMEM: return "caller storage, workspace or arena too small";
+    case ASQ_ENOCONV: return "not converged within maxiter";
+    case ASQ_ENOTSU3: return "links are not SU(3) times the given scale";
+    case ASQ_EHIP: return "HIP runtime error";
+    case ASQ_ENAN: return "non-finite or non-positive reduction";
+    case ASQ_EAGAIN: return "queue full, try again";
+  }
+  return "unknown error";
+}
+
+extern "C" const char* asq_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,135 @@
+// tune.hip -- autotuner for the Dslash launch (QUDA's automatic choice of
+// running parameters is the idea, section "CPS & QUDA"; this one is written
+// for gfx950): times each candidate RHS tile (columns per thread) on the
+// caller's own buffers and keeps the fastest per (device, lattice, link tier,
+// vector tiers, epilogue, columns).  Results live in memory and, when the
+// environment variable ASQ_TUNE_CACHE names a file, in that text file.
+// ASQ_TUNE=0 turns timing off and uses the built-in defaults.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "asq_internal.h"
+
+namespace asq {
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, int> g_cache;
+bool g_loaded = false;
+
+std::string key_of(const asq_gauge* g, int link, int in, int out, int epi, int ncol) {
+  char buf[160];
+  hipDeviceProp_t prop;
+  const char* arch = "gfx";
+  if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) arch = prop.gcnArchName;
+  snprintf(buf, sizeof(buf), "%s/%dx%dx%dx%d/L%d/I%d/O%d/E%d/N%d", arch, g->geom.X, g->geom.Y, g->geom.Z,
+           g->geom.T, link, in, out, epi, ncol);
+  for (char* c = buf; *c; ++c)
+    if (*c == ' ' || *c == ':') *c = '_';
+  return buf;
+}
+
+void load_cache_locked() {
+  if (g_loaded) return;
+  g_loaded = true;
+  const char* path = getenv("ASQ_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char k[200];
+  int v;
+  while (fscanf(f, "%199s %d", k, &v) == 2) g_cache[k] = v;
+  fclose(f);
+}
+
+void save_cache_locked() {
+  const char* path = getenv("ASQ_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : g_cache) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+  fclose(f);
+}
+
+int default_rtile(int link, int ncol) {
+  if (ncol <= 1) return 1;
+  if (link == LINK_F64_R18) return 2;
+  return ncol >= 4 ? 4 : 2;
+}
+
+bool tuning_on() {
+  const char* e = getenv("ASQ_TUNE");
+  return !(e && e[0] == '0');
+}
+
+}  // namespace
+
+int tuned_rtile(const asq_gauge* g, int link, int in, int out, int epi, int ncol) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_cache_locked();
+  auto it = g_cache.find(key_of(g, link, in, out, epi, ncol));
+  if (it != g_cache.end()) return it->second;
+  return default_rtile(link, ncol);
+}
+
+// Time the PLAIN Dslash (the loop shared by every epilogue) for each tile on
+// in_buf -> out_buf and record the winner for `epis`.  Buffers are the
+// caller's: in_buf is only read, out_buf is scratch.
+int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_buf, void* out_buf,
+                hipStream_t s) {
+  const std::string kp = key_of(g, link, in, in, EPI_PLAIN, ncol);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache_locked();
+    if (g_cache.count(kp)) return ASQ_OK;
+  }
+  int best = default_rtile(link, ncol);
+  if (tuning_on() && ncol > 1) {
+    DslashArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = g->geom;
+    a.out_parity = 1;
+    a.ncol = ncol;
+    a.links = g->links[link];
+    a.in = in_buf;
+    a.out = out_buf;
+    a.mask = MASK_ALL;
+    a.nblk = g->nblk;
+    a.coeff_fat = g->desc.fat_scale;
+    a.coeff_long = g->desc.long_scale;
+    hipEvent_t e0, e1;
+    ASQ_HIP_TRY(hipEventCreate(&e0));
+    ASQ_HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    const int cands[4] = {1, 2, 4, 8};
+    for (int r : cands) {
+      if (r > 1 && r > 2 * ncol) continue;
+      if (launch_dslash(link, in, in, EPI_PLAIN, r, a, s)) continue;  // warm-up
+      hipEventRecord(e0, s);
+      for (int k = 0; k < 3; ++k) launch_dslash(link, in, in, EPI_PLAIN, r, a, s);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (log_enabled()) fprintf(stderr, "[asq] tune %s R=%d %.3f ms\n", kp.c_str(), r, ms / 3);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = r;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int epi = EPI_PLAIN; epi <= EPI_RESID; ++epi)
+    for (int out = VEC_F64; out <= VEC_F16; ++out) g_cache[key_of(g, link, in, out, epi, ncol)] = best;
+  save_cache_locked();
+  return ASQ_OK;
+}
+
+}  // namespace asq

@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every function that
+include/asqtad.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1411_2223_amd as asq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "asqtad.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(asq.LIB_PATH):
+        from paper_1411_2223_amd import build
+
+        build.build()
+    return asq.load()
+
+
+def test_exports_match_header(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(asq.EXPORTS)
+
+
+def test_strerror(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+        assert asq.asq_strerror(code)
+    assert asq.asq_strerror(-99) == b"unknown error"
+
+
+def _desc(dims=(4, 4, 4, 8), mask=3, recon=18, fs=9 / 8, ls=-1 / 24):
+    return asq.asq_gauge_desc((ctypes.c_int * 4)(*dims), mask, recon, fs, ls)
+
+
+def test_gauge_bytes(lib):
+    d = _desc()
+    half = 4 * 4 * 4 * 8 // 2
+    n = asq.asq_gauge_bytes(ctypes.byref(d))
+    # F64 18-real + F32 18-real copies: 16 slots x half sites x (144 + 72) bytes, plus a flag word
+    assert n >= 16 * half * (144 + 72)
+    assert n < 16 * half * (144 + 72) + 4096
+    d12 = _desc(mask=7, recon=12)
+    assert asq.asq_gauge_bytes(ctypes.byref(d12)) >= 16 * half * (144 + 48 + 24)
+    for bad in (_desc(dims=(5, 4, 4, 8)), _desc(dims=(2, 4, 4, 8)), _desc(mask=0), _desc(recon=15),
+                _desc(mask=7, recon=12, fs=0.0)):
+        assert asq.asq_gauge_bytes(ctypes.byref(bad)) == 0
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    h = ctypes.c_void_p()
+    d = _desc(dims=(5, 4, 4, 8))
+    assert asq.asq_gauge_create(ctypes.byref(d), 16, 16, 256, 1 << 20, None, ctypes.byref(h)) == asq.ASQ_EINVAL
+    d = _desc()
+    assert asq.asq_gauge_create(ctypes.byref(d), None, 16, 256, 1 << 20, None, ctypes.byref(h)) == asq.ASQ_EINVAL
+    # misaligned storage
+    assert asq.asq_gauge_create(ctypes.byref(d), 16, 16, 257, 1 << 20, None, ctypes.byref(h)) == asq.ASQ_EINVAL
+    assert asq.asqtad_dslash_eo(None, 0, 0, 1, 16, 16, None) == asq.ASQ_EINVAL
+    params = asq.asq_cg_params(1e-10, 100, 0, 0.1, 8, 1)
+    stats = (asq.asq_cg_stats * 1)()
+    m = (ctypes.c_double * 1)(0.1)
+    assert asq.cg_solve_batch(None, 1, m, 16, 16, 256, 1, ctypes.byref(params), stats, None) == asq.ASQ_EINVAL
+    assert asq.asq_workspace_bytes(None, 1, 0) == 0
+    srv = ctypes.c_void_p()
+    assert asq.serve_create(None, 1 << 20, 1, 1, ctypes.byref(srv)) == asq.ASQ_EINVAL
+    assert asq.serve_create(256, 1 << 20, 0, 1, ctypes.byref(srv)) == asq.ASQ_EINVAL
+    assert asq.serve_submit(None, 0, 1, m, 16, 16, ctypes.byref(params), None) == asq.ASQ_EINVAL
+    assert asq.serve_poll(None, 1, None, None) == asq.ASQ_EINVAL
+    assert asq.asq_copy_probe(16, 16, 15, None) == asq.ASQ_EINVAL
+
+
+def test_magic_division_formula():
+    # floor(n * (floor(2^64/d) + 1) / 2^64) == n // d for the device's 32-bit site indices
+    rng = np.random.default_rng(0)
+    for d in list(range(2, 70)) + [96, 100, 128, 1000, 4096, 16383]:
+        m = (1 << 64) // d + 1
+        ns = list(range(0, 5000)) + [int(v) for v in rng.integers(0, 2**31, 2000)] + [2**31 - 1, 2**32 - 1]
+        for n in ns:
+            assert (n * m) >> 64 == n // d
+
+
+def test_f16n_host_codec_roundtrip():
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal((2, 50, 3)) + 1j * rng.standard_normal((2, 50, 3))
+    w = asq.decode_f16n(asq.encode_f16n(v), 2, 50)
+    err = np.abs(w - v).max(axis=-1) / np.abs(np.stack([v.real, v.imag], -1)).max(axis=(-1, -2))
+    assert err.max() < 2 ** -11 * 1.01

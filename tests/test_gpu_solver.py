@@ -1,0 +1,132 @@
+"""GPU CG solvers (cg_solve / cg_solve_batch through the C ABI) against the FP64 oracle.
+
+Several x are correct for an iterative solver, so x is never compared with the
+oracle's x elementwise: the oracle applies its own FP64 operator to the GPU's x
+and the relative true residual must be <= tol (1e-10).  Plain FP64 CG must also
+take the oracle's iteration count (+-2).  Batch invariance and graph/eager
+equality are bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import gauge_arrays, oracle_resid_cols
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def asq():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_1411_2223_amd as m
+
+    m.load()
+    return m
+
+
+def _solve(asq, g, masses, b, mode, **kw):
+    import torch
+
+    bd = asq.vec_to_device(b, "f64")
+    res = g.solve(masses, bd, mode=mode, **kw)
+    torch.cuda.synchronize()
+    x = asq.vec_from_device(res.x, len(masses), g.half, "f64")
+    return x, res
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed32", "mixed16"])
+def test_cg_tiny_config(asq, mode):
+    w = synth.WORKLOADS["tiny_4x4x4x8"]
+    dims, m = w["dims"], w["masses"][0]
+    fat, lng = gauge_arrays(dims, w["eps"], synth.gauge_seed(w["index"]))
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
+    b = synth.make_sources(dims, 1, synth.source_seed(w["index"]))
+    x, res = _solve(asq, g, [m], b, mode)
+    st = res.stats[0]
+    r = oracle.true_residual(dims, fat, lng, m, b[0], x[0])
+    _, it_o, _, _ = oracle.cg(dims, fat, lng, m, b[0], tol=TOL)
+    print(f"mode={mode} iters={st['iters']} oracle_iters={it_o} ru={st['reliable_updates']} "
+          f"resid={r:.3e} gpu_resid={st['true_resid']:.3e}", flush=True)
+    assert res.rc == 0 and st["converged"] == 1
+    assert r <= TOL
+    assert abs(st["true_resid"] - r) <= 1e-3 * r + 1e-15
+    if mode == "f64":
+        assert abs(st["iters"] - it_o) <= 2
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed32", "mixed16"])
+def test_cg_batch_columns_match_solo(asq, mode):
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
+    masses = [0.05, 0.1, 0.02, 0.2, 0.07]
+    b = synth.make_sources(dims, len(masses), 42)
+    xb, rb = _solve(asq, g, masses, b, mode)
+    r = oracle_resid_cols(dims, fat, lng, masses, b, xb)
+    print(f"mode={mode} iters={[s['iters'] for s in rb.stats]} resid={r}", flush=True)
+    assert rb.rc == 0
+    assert np.all(r <= TOL)
+    for c in (0, 3):
+        xs, rs = _solve(asq, g, [masses[c]], b[c:c + 1], mode)
+        assert rs.stats[0]["iters"] == rb.stats[c]["iters"]
+        assert np.array_equal(xs[0], xb[c]), "column result depends on the batch"
+
+
+def test_graph_matches_eager(asq):
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    b = synth.make_sources(dims, 2, 43)
+    x1, r1 = _solve(asq, g, [0.05, 0.1], b, "mixed32", use_graph=True)
+    x2, r2 = _solve(asq, g, [0.05, 0.1], b, "mixed32", use_graph=False)
+    assert np.array_equal(x1, x2)
+    assert [s["iters"] for s in r1.stats] == [s["iters"] for s in r2.stats]
+
+
+def test_maxiter_and_zero_source(asq):
+    dims = (4, 4, 4, 8)
+    fat, lng = gauge_arrays(dims, 0.3, 14112223)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    b = synth.make_sources(dims, 2, 44)
+    b[1] = 0
+    x, res = _solve(asq, g, [0.1, 0.1], b, "mixed32", maxiter=5, poll_iters=4)
+    assert res.rc == asq.ASQ_ENOCONV
+    assert res.stats[0]["converged"] == 0 and res.stats[0]["status"] == asq.ASQ_ENOCONV
+    assert res.stats[0]["iters"] <= 8
+    assert res.stats[1]["converged"] == 1 and res.stats[1]["iters"] == 0
+    assert np.all(x[1] == 0)
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed32"])
+def test_cg_full_size_single_rhs(asq, mode):
+    # 20^3 x 64, m = 0.01, 1 RHS: the paper's lattice shape, the bench's workload
+    w = synth.WORKLOADS["single_20x20x20x64"]
+    dims, m = w["dims"], w["masses"][0]
+    fat, lng = gauge_arrays(dims, w["eps"], synth.gauge_seed(w["index"]))
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    b = synth.make_sources(dims, 1, synth.source_seed(w["index"]))
+    x, res = _solve(asq, g, [m], b, mode, maxiter=20000)
+    st = res.stats[0]
+    r = oracle.true_residual(dims, fat, lng, m, b[0], x[0])
+    print(f"20^3x64 mode={mode} iters={st['iters']} ru={st['reliable_updates']} resid={r:.3e} "
+          f"t={st['seconds']:.3f}s gflops={st['gflops']:.1f}", flush=True)
+    assert res.rc == 0 and r <= TOL
+
+
+def test_cg_batched_full_size_f16(asq):
+    # 20^3 x 64 with several RHS x masses, FP16-with-norm vectors, FP32 18-real links
+    w = synth.WORKLOADS["batched_20x20x20x64"]
+    dims = w["dims"]
+    fat, lng = gauge_arrays(dims, w["eps"], synth.gauge_seed(w["index"]))
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    masses = list(w["masses"]) * 2
+    b = synth.make_sources(dims, len(masses), synth.source_seed(w["index"]))
+    x, res = _solve(asq, g, masses, b, "mixed16", maxiter=20000)
+    r = oracle_resid_cols(dims, fat, lng, masses, b, x)
+    print(f"batched f16 iters={[s['iters'] for s in res.stats]} resid max={r.max():.3e}", flush=True)
+    assert res.rc == 0 and np.all(r <= TOL)
