@@ -43,7 +43,36 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound on the oracle sample")
     ap.add_argument("--dslash-launches", type=int, default=200)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only launch the Dslash tiers and a 1 GiB copy probe (for hardware-counter runs)")
     return ap.parse_args()
+
+
+def kernels_only(args, asq, g, dims):
+    """Fixed launches for counter collection: each Dslash tier 20 times, then the copy probe."""
+    import torch
+
+    half = int(np.prod(dims)) // 2
+    stream = torch.cuda.Stream()
+    res = {}
+    for prec in ("f32", "f64", "f16"):
+        dt = time_dslash(asq, g, prec, 1, 20, stream)
+        key = prec
+        res[prec] = {"us": dt * 1e6, "alg_bytes": BYTES_PER_SITE[key] * half}
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        asq.check(asq.asq_copy_probe(dst.data_ptr(), src.data_ptr(), n, asq.stream_ptr(stream)), "copy")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        asq.check(asq.asq_copy_probe(dst.data_ptr(), src.data_ptr(), n, asq.stream_ptr(stream)), "copy")
+    e1.record(stream)
+    e1.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / 5
+    res["copy"] = {"us": dt * 1e6, "bytes_read": n, "bytes_written": n, "GBps": 2 * n / dt / 1e9}
+    print(json.dumps({"kernels_only": res}), flush=True)
 
 
 def log(msg):
@@ -109,6 +138,9 @@ def main():
     fat, lng = synth.make_gauge(dims, w["eps"], synth.gauge_seed(w["index"]))
     b = synth.make_sources(dims, 1, synth.source_seed(w["index"]))
     g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    if args.kernels_only:
+        kernels_only(args, asq, g, dims)
+        return
     stream = torch.cuda.Stream()
     bd = asq.vec_to_device(b, "f64")
     work = g.workspace(1, args.mode)
