@@ -98,6 +98,26 @@ def time_dslash(asq, g, prec, nrhs, launches, stream):
     return e0.elapsed_time(e1) * 1e-3 / launches
 
 
+def copy_bandwidth(asq, stream, nbytes=1 << 30, reps=10):
+    """Read+write GB/s of the library's plain copy kernel on a buffer far beyond the 256 MB MALL."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    sp = asq.stream_ptr(stream)
+    for _ in range(2):
+        asq.check(asq.asq_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, sp), "asq_copy_probe")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        asq.check(asq.asq_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, sp), "asq_copy_probe")
+    e1.record(stream)
+    e1.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2 * nbytes / dt / 1e9
+
+
 def cpu_baseline(w, fat, lng, b, mass, iters_full, seconds):
     """Oracle CG on the same workload, bounded: time a prefix of iterations, scale to a full solve."""
     import oracle
@@ -184,6 +204,8 @@ def main():
     log(f"dslash {tprec}: {dt * 1e6:.2f} us, {achieved:.0f} GB/s; f64: {dt64 * 1e6:.2f} us, "
         f"{BYTES_PER_SITE['f64'] * half / dt64 / 1e9:.0f} GB/s")
 
+    copy_gbs = copy_bandwidth(asq, stream)
+    log(f"copy probe: {copy_gbs:.0f} GB/s")
     ms = elapsed / args.steps * 1e3
     iters = st["iters"]
     flops = half * ((2 * 1146 + 72) * iters + (2 * 1146 + 36) * st["reliable_updates"])
@@ -214,6 +236,7 @@ def main():
         "speedup_vs_f64_cg": t64 * 1e3 / ms,
         "dslash_gbs": achieved,
         "dslash_f64_gbs": BYTES_PER_SITE["f64"] * half / dt64 / 1e9,
+        "copy_probe_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "kernel": f"dslash_kernel {tprec} 18-real, 1 RHS", "us_per_launch": dt * 1e6,

@@ -15,12 +15,15 @@ struct Batch {
   int link = 0;        // link tier of the iterated Dslash
   int rt_sloppy_plain = 1, rt_sloppy_xpay = 1, rt64_plain = 1, rt64_resid = 1;
   ColState* st = nullptr;
-  double* partials = nullptr;
+  double* partials = nullptr;    // [ncol][nblk] partials of |r|^2 (update, residual, init)
+  double* partials_a = nullptr;  // [ncol][nblk] partials of <p, A p> (D_eo)
   double* b = nullptr;  // F64 [ncol][3][half][2]
   double* x = nullptr;
   void* r = nullptr;
-  void* p = nullptr;
+  void* p = nullptr;      // two direction buffers; ColState::pbuf selects the current one
+  void* p_alt = nullptr;
   void* Ap = nullptr;
+
   void* t = nullptr;
   void* t64 = nullptr;
 };

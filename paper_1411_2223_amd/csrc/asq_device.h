@@ -323,6 +323,7 @@ struct VecF64 {
     }
     return v;
   }
+  __device__ __forceinline__ static Vec3<double> quantize(const Vec3<double>& v) { return v; }
   // Stores v; returns the value a later load gives back.
   __device__ __forceinline__ static Vec3<double> store(void* base, int half, int col, int i, const Vec3<double>& v) {
     double2* q = reinterpret_cast<double2*>(base) + (size_t)col * 3 * half + i;
@@ -346,6 +347,7 @@ struct VecF32 {
     }
     return v;
   }
+  __device__ __forceinline__ static Vec3<float> quantize(const Vec3<float>& v) { return v; }
   __device__ __forceinline__ static Vec3<float> store(void* base, int half, int col, int i, const Vec3<float>& v) {
     float2* q = reinterpret_cast<float2*>(base) + (size_t)col * 3 * half + i;
 #pragma unroll
@@ -379,7 +381,7 @@ struct VecF16 {
     const unsigned hi = __half_as_ushort(__float2half_rn(b));
     return lo | (hi << 16);
   }
-  __device__ __forceinline__ static Vec3<float> store(void* base, int half, int col, int i, const Vec3<float>& v) {
+  __device__ __forceinline__ static uint4 encode(const Vec3<float>& v) {
     float nu = fabsf(v.c[0].re);
     nu = fmaxf(nu, fabsf(v.c[0].im));
     nu = fmaxf(nu, fabsf(v.c[1].re));
@@ -392,6 +394,12 @@ struct VecF16 {
     w.y = pack2(v.c[1].re * inv, v.c[1].im * inv);
     w.z = pack2(v.c[2].re * inv, v.c[2].im * inv);
     w.w = __float_as_uint(nu);
+    return w;
+  }
+  // The value a store followed by a load gives back.
+  __device__ __forceinline__ static Vec3<float> quantize(const Vec3<float>& v) { return unpack(encode(v)); }
+  __device__ __forceinline__ static Vec3<float> store(void* base, int half, int col, int i, const Vec3<float>& v) {
+    const uint4 w = encode(v);
     reinterpret_cast<uint4*>(base)[(size_t)col * half + i] = w;
     return unpack(w);
   }

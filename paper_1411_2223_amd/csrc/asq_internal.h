@@ -60,8 +60,9 @@ struct alignas(128) ColState {
   double a;        // 4 m^2
   double bb;       // |b|^2
   double rr;       // |r|^2 of the iterated residual
+  double rr_old;   // the previous rr (denominator of beta)
   double alpha;
-  double beta;
+  double beta;     // applied by the next iteration's fused p = r + beta p
   double maxr;     // max |r| since the last reliable update
   double true_rr;  // |b - A x|^2 from the last FP64 residual
   double pAp;
@@ -75,7 +76,12 @@ struct alignas(128) ColState {
   int converged;
   int frozen;      // sloppy residual met tol: skip iterations until the FP64 check
   int status;      // 0 ok, ASQ_ENAN on a non-finite or non-positive reduction
+  int pbuf;        // which of the two p buffers holds the current direction
 };
+static_assert(sizeof(ColState) == 128, "ColState layout");
+
+// Scalar updates applied to a column from its reduced sums (see asq_reduce.h).
+enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_FINAL = 4, OP_STEP = 5 };
 
 struct DslashArgs {
   Geom g;
@@ -83,11 +89,17 @@ struct DslashArgs {
   int ncol;
   int ntiles;
   const void* links;
-  const void* in;
+  const void* in;       // input vector (other parity)
+  const void* in_alt;   // second p buffer: with in_sel = 1 the input is the column's current p
+  int in_sel;
+  const void* rfuse;    // fused direction update: input = r + beta * p (p = in / in_alt), the new p
+                        // is written by the owning thread into the other p buffer
   void* out;
   const void* y;        // XPAY / RESID: the vector multiplied by a = 4 m^2
+  const void* y_alt;    // with y_sel = 1: y is the column's new p (y if pbuf == 1, else y_alt)
+  int y_sel;
   const double* b;      // RESID: right-hand side (F64)
-  const ColState* st;   // per-column a and masks (nullptr: a = 0, all columns)
+  ColState* st;         // per-column a and masks (nullptr: a = 0, all columns)
   int mask;
   double* partials;     // [ncol][nblk] FP64 block partials (XPAY_DOT, RESID)
   int nblk;
@@ -96,8 +108,9 @@ struct DslashArgs {
 };
 
 // Launch one Dslash; link_kind / in_kind / out_kind select the template.
+// fuse_rt >= 0 selects the fused direction update with r stored in tier fuse_rt.
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
-                  hipStream_t s);
+                  hipStream_t s, int fuse_rt = -1);
 
 // Tuned RHS tile (columns per thread) for a Dslash configuration.
 int tuned_rtile(const asq_gauge* g, int link_kind, int in_kind, int out_kind, int epi, int ncol);

@@ -1,0 +1,115 @@
+// asq_reduce.h -- deterministic per-column reductions and the scalar updates
+// of CG.  Producers write one FP64 partial per (column, site block); a
+// consumer sums a column's partials in block order with a fixed tree, so the
+// result is bitwise reproducible and independent of the other columns.  No
+// block waits on another inside a kernel: on a multi-XCD part that would need
+// device-scope release/acquire fences, which write back and invalidate the
+// XCD's L2 and with it the cached neighbour vectors of every other block.
+#pragma once
+#include <math.h>
+
+#include "asq_internal.h"
+
+namespace asq {
+
+// alpha = rr / <p, A p> exactly as the update kernel and the scalar kernel both form it.
+__device__ inline bool alpha_of(const ColState& S, double pAp, double* alpha) {
+  if (!isfinite(pAp) || !(pAp > 0)) return false;
+  *alpha = S.rr / pAp;
+  return true;
+}
+
+// Scalar update of one column from its reduced sum s (thread 0 of one block).
+__device__ inline void finalize_column(ColState& S, double s, int op) {
+  const bool finite = isfinite(s);
+  switch (op) {
+    case OP_INIT:
+      S.bb = s;
+      S.rr = s;
+      S.rr_old = s;
+      S.true_rr = s;
+      S.maxr = sqrt(s);
+      S.alpha = 0;
+      S.beta = 0;
+      S.iters = 0;
+      S.n_ru = 0;
+      S.want_ru = 0;
+      S.frozen = 0;
+      S.pbuf = 0;
+      S.status = finite ? 0 : ASQ_ENAN;
+      S.converged = finite && s == 0;
+      S.active = finite && s > 0;
+      break;
+    case OP_ALPHA:
+      S.pAp = s;
+      if (!finite || !(s > 0)) {
+        S.status = ASQ_ENAN;
+        S.active = 0;
+      } else {
+        S.alpha = S.rr / s;
+      }
+      break;
+    case OP_BETA: {
+      if (!S.active) break;  // stopped by OP_ALPHA
+      S.iters += 1;
+      S.pbuf ^= 1;  // the new direction becomes current
+      if (!finite) {
+        S.status = ASQ_ENAN;
+        S.active = 0;
+        break;
+      }
+      S.rr_old = S.rr;
+      S.rr = s;
+      S.beta = s / S.rr_old;
+      const double r = sqrt(s);
+      if (r <= S.tol * sqrt(S.bb) || S.iters >= S.maxiter) {
+        // iterated residual met tol (or the budget is spent): decide on the FP64 residual
+        S.frozen = 1;
+        S.want_ru = 1;
+      } else if (S.delta > 0 && r < S.delta * S.maxr) {
+        S.want_ru = 1;
+      }
+      S.maxr = fmax(S.maxr, r);
+      break;
+    }
+    case OP_RU:
+      S.true_rr = s;
+      S.n_ru += 1;
+      if (!finite) {
+        S.status = ASQ_ENAN;
+        S.active = 0;
+      } else if (sqrt(s) <= S.tol * sqrt(S.bb)) {
+        S.converged = 1;
+        S.active = 0;
+      } else if (S.iters >= S.maxiter) {
+        S.status = ASQ_ENOCONV;
+        S.active = 0;
+      } else {
+        // r was replaced by the true residual: restart the norm history from it
+        S.rr = s;
+        S.beta = s / S.rr_old;
+        S.maxr = sqrt(s);
+        S.want_ru = 0;
+        S.frozen = 0;
+      }
+      break;
+    case OP_FINAL:
+      S.true_rr = s;
+      break;
+  }
+}
+
+// Fixed-order sum of partials[0..nblk) over the block; valid in every thread.
+// sh: kBlock/64 + 1 doubles of LDS.
+__device__ inline double column_sum(const double* partials, int nblk, double* sh) {
+  double v = 0;
+  for (int k = (int)threadIdx.x; k < nblk; k += kBlock) v += partials[k];
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) sh[kBlock / 64] = s;
+  __syncthreads();
+  const double r = sh[kBlock / 64];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace asq

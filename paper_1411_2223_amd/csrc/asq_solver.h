@@ -4,8 +4,7 @@
 
 namespace asq {
 
-enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_FINAL = 4 };
-enum VecKernel { VK_INIT = 0, VK_XR = 1, VK_P = 2 };
+enum VecKernel { VK_INIT = 0, VK_XR = 1 };
 
 struct VecArgs {
   int half;
@@ -13,13 +12,15 @@ struct VecArgs {
   const double* b;  // F64 right-hand sides
   double* x;        // F64 solutions
   void* r;          // iterated residual (RT tier)
-  void* p;          // search direction (PT tier)
+  void* p;          // search directions (PT tier): two buffers, ColState::pbuf picks
+  void* p_alt;
   void* Ap;         // A p (PT tier)
   ColState* st;
-  double* partials;
+  double* partials;          // this kernel's partials ([ncol][nblk])
+  const double* partials_a;  // update: the D_eo <p, A p> partials
 };
 
 int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hipStream_t s);
-int launch_reduce(int op, ColState* st, const double* partials, int nblk, int ncol, hipStream_t s);
+int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s);
 
 }  // namespace asq

@@ -1,14 +1,14 @@
 // blas.hip -- CG vector updates and deterministic FP64 reductions.
 //
 // Every vector kernel runs on a (site block, column) grid and writes one FP64
-// partial per block and column; the reduction kernels sum the partials of a
-// column in a fixed order and update that column's scalars on the device
-// (alpha, beta, reliable-update and convergence decisions), so no scalar ever
-// travels to the host inside the iteration and a column's arithmetic never
-// depends on the other columns of the batch.
+// partial per block and column; the last block of a column sums the partials
+// in a fixed order and updates that column's scalars on the device (alpha,
+// beta, reliable-update and convergence decisions), so no scalar ever travels
+// to the host inside the iteration and a column's arithmetic never depends on
+// the other columns of the batch.
 #include <math.h>
 
-#include "asq_internal.h"
+#include "asq_reduce.h"
 #include "asq_solver.h"
 
 namespace asq {
@@ -47,18 +47,27 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const VecArgs A) {
   if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
 }
 
-// x += alpha p (FP64); r -= alpha A p; partial |r|^2 of the stored r.
+// x += alpha p (FP64); r -= alpha A p; block partials of |r|^2 of the stored r.
+// Every block forms alpha = rr / <p, A p> itself from the D_eo partials (the
+// same fixed-order sum the scalar kernel does), so no scalar kernel sits
+// between D_eo and this update.  p is the direction the fused D_oe just wrote:
+// the buffer other than pbuf.
 template <class PT, class RT>
 __global__ void __launch_bounds__(kBlock) update_xr_kernel(const VecArgs A) {
   const int c = blockIdx.y, sblk = blockIdx.x;
-  if (!state_on(A.st[c], MASK_ACTIVE)) return;
+  const ColState& S = A.st[c];
+  if (!state_on(S, MASK_ACTIVE)) return;
+  __shared__ double sh[kBlock / 64 + 1];
+  const double pAp = column_sum(A.partials_a + (size_t)c * A.nblk, A.nblk, sh);
+  double alpha;
+  if (!alpha_of(S, pAp, &alpha)) return;  // uniform; the scalar kernel flags the column
   using rr = typename RT::real;
   const int half = A.half;
   const int i = sblk * kBlock + (int)threadIdx.x;
+  const void* pnew = S.pbuf ? A.p : A.p_alt;
   double d = 0;
   if (i < half) {
-    const double alpha = A.st[c].alpha;
-    const Vec3<double> p = convert<double>(PT::load(A.p, half, c, i));
+    const Vec3<double> p = convert<double>(PT::load(pnew, half, c, i));
     const Vec3<rr> ap = convert<rr>(PT::load(A.Ap, half, c, i));
     Vec3<double> x = VecF64::load(A.x, half, c, i);
     Vec3<rr> r = RT::load(A.r, half, c, i);
@@ -73,122 +82,57 @@ __global__ void __launch_bounds__(kBlock) update_xr_kernel(const VecArgs A) {
     VecF64::store(A.x, half, c, i, x);
     d = norm2_d(RT::store(A.r, half, c, i, r));
   }
-  __shared__ double sh[kBlock / 64];
   const double tot = block_sum(d, sh);
   if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
 }
 
-// p = r + beta p.
-template <class PT, class RT>
-__global__ void __launch_bounds__(kBlock) update_p_kernel(const VecArgs A) {
-  const int c = blockIdx.y, sblk = blockIdx.x;
-  if (!state_on(A.st[c], MASK_ACTIVE)) return;
-  using pr = typename PT::real;
-  const int half = A.half;
-  const int i = sblk * kBlock + (int)threadIdx.x;
-  if (i >= half) return;
-  const pr beta = (pr)A.st[c].beta;
-  const Vec3<pr> r = convert<pr>(RT::load(A.r, half, c, i));
-  Vec3<pr> p = PT::load(A.p, half, c, i);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    p.c[a].re = fmaR(beta, p.c[a].re, r.c[a].re);
-    p.c[a].im = fmaR(beta, p.c[a].im, r.c[a].im);
-  }
-  PT::store(A.p, half, c, i, p);
-}
-
-// Fixed-order sum of a column's block partials, then the scalar update.
-__global__ void __launch_bounds__(kBlock) reduce_kernel(ColState* st, const double* partials, int nblk, int op) {
+// Scalar kernel: fixed-order sums of a column's partials, then its update.
+// OP_STEP closes a CG iteration (alpha from the D_eo partials, then beta,
+// triggers and the p buffer swap from the |r|^2 partials); OP_INIT, OP_RU and
+// OP_FINAL use the one sum in `pb`.
+__global__ void __launch_bounds__(kBlock) reduce_kernel(ColState* st, const double* pa, const double* pb, int nblk,
+                                                        int op) {
   const int c = blockIdx.x;
   ColState& S = st[c];
-  const int mask = op == OP_ALPHA || op == OP_BETA ? MASK_ACTIVE : (op == OP_RU ? MASK_RELIABLE : MASK_ALL);
+  const int mask = op == OP_STEP ? MASK_ACTIVE : (op == OP_RU ? MASK_RELIABLE : MASK_ALL);
   if (!state_on(S, mask)) return;
-  double v = 0;
-  for (int k = (int)threadIdx.x; k < nblk; k += kBlock) v += partials[(size_t)c * nblk + k];
-  __shared__ double sh[kBlock / 64];
-  const double s = block_sum(v, sh);
-  if (threadIdx.x != 0) return;
-  const bool finite = isfinite(s);
-  switch (op) {
-    case OP_INIT:
-      S.bb = s;
-      S.rr = s;
-      S.true_rr = s;
-      S.maxr = sqrt(s);
-      S.iters = 0;
-      S.n_ru = 0;
-      S.want_ru = 0;
-      S.frozen = 0;
-      S.status = finite ? 0 : ASQ_ENAN;
-      S.converged = finite && s == 0;
-      S.active = finite && s > 0;
-      break;
-    case OP_ALPHA:
-      S.pAp = s;
-      if (!finite || !(s > 0)) {
-        S.status = ASQ_ENAN;
-        S.active = 0;
-      } else {
-        S.alpha = S.rr / s;
-      }
-      break;
-    case OP_BETA: {
-      S.iters += 1;
-      if (!finite) {
-        S.status = ASQ_ENAN;
-        S.active = 0;
-        break;
-      }
-      S.beta = s / S.rr;
-      S.rr = s;
-      const double r = sqrt(s);
-      if (r <= S.tol * sqrt(S.bb) || S.iters >= S.maxiter) {
-        // iterated residual met tol (or the budget is spent): check in FP64
-        S.frozen = 1;
-        S.want_ru = 1;
-      } else if (S.delta > 0 && r < S.delta * S.maxr) {
-        S.want_ru = 1;
-      }
-      S.maxr = fmax(S.maxr, r);
-      break;
+  __shared__ double sh[kBlock / 64 + 1];
+  const double s = column_sum(pb + (size_t)c * nblk, nblk, sh);
+  if (op == OP_STEP) {
+    const double pAp = column_sum(pa + (size_t)c * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+      finalize_column(S, pAp, OP_ALPHA);
+      finalize_column(S, s, OP_BETA);
     }
-    case OP_RU:
-      S.true_rr = s;
-      S.n_ru += 1;
-      if (!finite) {
-        S.status = ASQ_ENAN;
-        S.active = 0;
-      } else if (sqrt(s) <= S.tol * sqrt(S.bb)) {
-        S.converged = 1;
-        S.active = 0;
-      } else if (S.iters >= S.maxiter) {
-        S.status = ASQ_ENOCONV;
-        S.active = 0;
-      } else {
-        S.rr = s;
-        S.maxr = sqrt(s);
-        S.want_ru = 0;
-        S.frozen = 0;
-      }
-      break;
-    case OP_FINAL:
-      S.true_rr = s;
-      break;
+  } else if (threadIdx.x == 0) {
+    finalize_column(S, s, op);
   }
 }
 
-__global__ void copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n) {
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-    dst[k] = src[k];
+// dst = src in 16-byte words; four independent loads in flight per thread.
+__global__ void __launch_bounds__(256) copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; k + 3 * stride < n; k += 4 * stride) {
+    const uint4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
+    dst[k] = a;
+    dst[k + stride] = b;
+    dst[k + 2 * stride] = c;
+    dst[k + 3 * stride] = d;
+  }
+  for (; k < n; k += stride) dst[k] = src[k];
 }
 
 template <class PT, class RT>
 int launch_vec(int which, const VecArgs& a, int ncol, hipStream_t s) {
   const dim3 grid((unsigned)a.nblk, (unsigned)ncol);
-  if (which == VK_INIT) init_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
-  else if (which == VK_XR) update_xr_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
-  else update_p_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
+  if (which == VK_INIT) {
+    init_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
+  } else if (which == VK_XR) {
+    update_xr_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
+  } else {
+    return ASQ_EINVAL;
+  }
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }
 
@@ -201,8 +145,9 @@ int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hip
   return ASQ_EINVAL;
 }
 
-int launch_reduce(int op, ColState* st, const double* partials, int nblk, int ncol, hipStream_t s) {
-  reduce_kernel<<<(unsigned)ncol, kBlock, 0, s>>>(st, partials, nblk, op);
+int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s) {
+  if (op == OP_ALPHA || op == OP_BETA) return ASQ_EINVAL;
+  reduce_kernel<<<(unsigned)ncol, kBlock, 0, s>>>(st, pa, pb, nblk, op);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }
 
@@ -222,8 +167,8 @@ extern "C" int asq_copy_probe(void* dst_dev, const void* src_dev, size_t n, void
     return ASQ_EINVAL;
   const size_t n16 = n / 16;
   if (n16 == 0) return ASQ_OK;
-  size_t blocks = (n16 + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  size_t blocks = (n16 + 1023) / 1024;
+  if (blocks > 4096) blocks = 4096;
   asq::copy_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)hip_stream>>>((uint4*)dst_dev, (const uint4*)src_dev, n16);
   ASQ_HIP_TRY(hipGetLastError());
   return ASQ_OK;

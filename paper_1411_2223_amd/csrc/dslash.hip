@@ -9,12 +9,17 @@
 // applied to R colour vectors.  Links and vectors are site-fastest structures
 // of arrays, so each wavefront load is one contiguous run; neighbour vectors
 // come through L2 (blocks are remapped so each XCD walks a contiguous slab).
-// Epilogues fuse the CG arithmetic that touches the same sites:
+//
+// Fused CG work:
+//   FUSEP        the input is the CG direction p = r + beta p_old, formed on the
+//                fly at every neighbour; the thread of site x writes the new p of
+//                its -x neighbour (each site of the other parity has exactly one
+//                such owner) into the second p buffer.
 //   EPI_PLAIN    out = D in
 //   EPI_XPAY_DOT out = a_c y - D in, block partials of Re<y, out>   (A p and <p, A p>)
-//   EPI_RESID    out = b - a_c y + D in (FP64), block partials of |out|^2,
-//                stored in the output tier (true residual + sloppy copy)
-#include "asq_internal.h"
+//   EPI_RESID    out = b - a_c y + D in (FP64), block partials of |out|^2 (the true
+//                residual, also stored in the output tier as the new iterated r)
+#include "asq_reduce.h"
 
 namespace asq {
 namespace {
@@ -27,9 +32,39 @@ __device__ __forceinline__ bool col_on(const DslashArgs& A, int c) {
   return s.active != 0 && s.want_ru != 0;
 }
 
+template <class InT, int R>
+struct Cols {
+  using real = typename InT::real;
+  bool on[R];
+  const void* in[R];  // input (or p_old) base of each column
+  void* pnew[R];      // FUSEP: where the owner writes the new p
+  real beta[R];
+};
+
+// Neighbour vector of column r at site j, with the fused direction update.
+template <class InT, class RT, int R, bool FUSEP>
+__device__ __forceinline__ Vec3<typename InT::real> fetch(const DslashArgs& A, const Cols<InT, R>& C, int r, int c,
+                                                          int j) {
+  using real = typename InT::real;
+  const int half = A.g.half;
+  if constexpr (!FUSEP) {
+    return InT::load(C.in[r], half, c, j);
+  } else {
+    const Vec3<real> p = InT::load(C.in[r], half, c, j);
+    const Vec3<real> rv = convert<real>(RT::load(A.rfuse, half, c, j));
+    Vec3<real> v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      v.c[a].re = fmaR(C.beta[r], p.c[a].re, rv.c[a].re);
+      v.c[a].im = fmaR(C.beta[r], p.c[a].im, rv.c[a].im);
+    }
+    return InT::quantize(v);  // exactly the value the owner stores
+  }
+}
+
 // The four terms of direction MU for output site i, accumulated into R columns.
-template <class Link, class InT, int R, int MU>
-__device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, int c0, const bool (&on)[R],
+template <class Link, class InT, class RT, int R, bool FUSEP, int MU>
+__device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, int c0, const Cols<InT, R>& C,
                                         Vec3<typename InT::real> (&acc)[R]) {
   using real = typename InT::real;
   static_assert(sizeof(typename Link::real) == sizeof(real), "link and vector arithmetic must match");
@@ -60,8 +95,8 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
     const Mat3<real> U = Link::load(A.links, half, p, MU, i);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (on[r]) {
-        const Vec3<real> v = InT::load(A.in, half, c0 + r, jf1);
+      if (C.on[r]) {
+        const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c0 + r, jf1);
         if constexpr (Link::folded) add3(acc[r], mul(U, v));
         else axpy3(acc[r], sf1, mul(U, v));
       }
@@ -70,8 +105,9 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
     const Mat3<real> U = Link::load(A.links, half, 1 - p, MU, jb1);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (on[r]) {
-        const Vec3<real> v = InT::load(A.in, half, c0 + r, jb1);
+      if (C.on[r]) {
+        const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c0 + r, jb1);
+        if constexpr (FUSEP && MU == 0) InT::store(C.pnew[r], half, c0 + r, jb1, v);  // owner of site x - x^
         if constexpr (Link::folded) sub3(acc[r], mul_adj(U, v));
         else axpy3(acc[r], sb1, mul_adj(U, v));
       }
@@ -80,8 +116,8 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
     const Mat3<real> U = Link::load(A.links, half, p, 4 + MU, i);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (on[r]) {
-        const Vec3<real> v = InT::load(A.in, half, c0 + r, jf3);
+      if (C.on[r]) {
+        const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c0 + r, jf3);
         if constexpr (Link::folded) add3(acc[r], mul(U, v));
         else axpy3(acc[r], sf3, mul(U, v));
       }
@@ -90,27 +126,32 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
     const Mat3<real> U = Link::load(A.links, half, 1 - p, 4 + MU, jb3);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (on[r]) {
-        const Vec3<real> v = InT::load(A.in, half, c0 + r, jb3);
+      if (C.on[r]) {
+        const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c0 + r, jb3);
         if constexpr (Link::folded) sub3(acc[r], mul_adj(U, v));
         else axpy3(acc[r], sb3, mul_adj(U, v));
       }
   }
 }
 
-template <class Link, class InT, class OutT, int R, int EPI>
+template <class Link, class InT, class OutT, class RT, int R, int EPI, bool FUSEP>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   using real = typename InT::real;
   const int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const int tile = lin % A.ntiles;  // column tiles of the same sites are neighbours in dispatch order
   const int sblk = lin / A.ntiles;
   const int c0 = tile * R;
-  bool on[R];
+  Cols<InT, R> C;
   bool any = false;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    on[r] = col_on(A, c0 + r);
-    any |= on[r];
+    const int c = c0 + r;
+    C.on[r] = col_on(A, c);
+    any |= C.on[r];
+    const int pb = (C.on[r] && A.in_sel) ? A.st[c].pbuf : 0;
+    C.in[r] = pb ? A.in_alt : A.in;
+    C.pnew[r] = const_cast<void*>(pb ? A.in : A.in_alt);
+    C.beta[r] = (FUSEP && C.on[r]) ? (real)A.st[c].beta : (real)0;
   }
   if (!any) return;  // uniform over the block
   const int half = A.g.half;
@@ -125,30 +166,32 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
 
   if (valid) {
     const Site s = decode(A.g, i, A.out_parity);
-    hop_dir<Link, InT, R, 0>(A, i, s, c0, on, acc);
-    hop_dir<Link, InT, R, 1>(A, i, s, c0, on, acc);
-    hop_dir<Link, InT, R, 2>(A, i, s, c0, on, acc);
-    hop_dir<Link, InT, R, 3>(A, i, s, c0, on, acc);
+    hop_dir<Link, InT, RT, R, FUSEP, 0>(A, i, s, c0, C, acc);
+    hop_dir<Link, InT, RT, R, FUSEP, 1>(A, i, s, c0, C, acc);
+    hop_dir<Link, InT, RT, R, FUSEP, 2>(A, i, s, c0, C, acc);
+    hop_dir<Link, InT, RT, R, FUSEP, 3>(A, i, s, c0, C, acc);
   }
 
   if constexpr (EPI == EPI_PLAIN) {
     if (valid) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (on[r]) OutT::store(A.out, half, c0 + r, i, convert<typename OutT::real>(acc[r]));
+        if (C.on[r]) OutT::store(A.out, half, c0 + r, i, convert<typename OutT::real>(acc[r]));
     }
   } else {
     __shared__ double sh[kBlock / 64];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (!on[r]) continue;  // uniform over the block
+      if (!C.on[r]) continue;  // uniform over the block
       const int c = c0 + r;
       double d = 0;
       if (valid) {
         if constexpr (EPI == EPI_XPAY_DOT) {
           // out = a y - D in;  d = Re<y, out>
           const real a = (real)A.st[c].a;
-          const Vec3<real> y = InT::load(A.y, half, c, i);
+          const void* yb = A.y;
+          if (A.y_sel) yb = A.st[c].pbuf ? A.y : A.y_alt;
+          const Vec3<real> y = InT::load(yb, half, c, i);
           Vec3<real> o;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
@@ -180,58 +223,66 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   }
 }
 
-template <class Link, class InT, class OutT, int R, int EPI>
+template <class Link, class InT, class OutT, class RT, int R, int EPI, bool FUSEP>
 int go(const DslashArgs& a0, hipStream_t s) {
   DslashArgs a = a0;
   a.ntiles = (a.ncol + R - 1) / R;
   const long nb = (long)a.nblk * a.ntiles;
   if (nb <= 0) return ASQ_OK;
   if (nb >= (1L << 31)) return ASQ_EINVAL;
-  dslash_kernel<Link, InT, OutT, R, EPI><<<(unsigned)nb, kBlock, 0, s>>>(a);
+  dslash_kernel<Link, InT, OutT, RT, R, EPI, FUSEP><<<(unsigned)nb, kBlock, 0, s>>>(a);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }
 
-template <class Link, class InT, class OutT, int EPI>
+template <class Link, class InT, class OutT, class RT, int EPI, bool FUSEP>
 int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
   switch (rtile) {
-    case 1: return go<Link, InT, OutT, 1, EPI>(a, s);
-    case 2: return go<Link, InT, OutT, 2, EPI>(a, s);
-    case 4: return go<Link, InT, OutT, 4, EPI>(a, s);
-    case 8: return go<Link, InT, OutT, 8, EPI>(a, s);
+    case 1: return go<Link, InT, OutT, RT, 1, EPI, FUSEP>(a, s);
+    case 2: return go<Link, InT, OutT, RT, 2, EPI, FUSEP>(a, s);
+    case 4: return go<Link, InT, OutT, RT, 4, EPI, FUSEP>(a, s);
+    case 8: return go<Link, InT, OutT, RT, 8, EPI, FUSEP>(a, s);
   }
   return ASQ_EINVAL;
 }
 
-template <class Link, class V>
-int pick_epi_sloppy(int epi, int rtile, const DslashArgs& a, hipStream_t s) {
-  if (epi == EPI_PLAIN) return pick_r<Link, V, V, EPI_PLAIN>(rtile, a, s);
-  if (epi == EPI_XPAY_DOT) return pick_r<Link, V, V, EPI_XPAY_DOT>(rtile, a, s);
+// Iterated tiers: PLAIN (optionally with the fused direction update) and XPAY_DOT.
+template <class Link, class V, class RT>
+int pick_sloppy(int epi, int rtile, const DslashArgs& a, hipStream_t s, bool fuse) {
+  if (epi == EPI_PLAIN) {
+    if (fuse) return pick_r<Link, V, V, RT, EPI_PLAIN, true>(rtile, a, s);
+    return pick_r<Link, V, V, RT, EPI_PLAIN, false>(rtile, a, s);
+  }
+  if (epi == EPI_XPAY_DOT && !fuse) return pick_r<Link, V, V, RT, EPI_XPAY_DOT, false>(rtile, a, s);
   return ASQ_EINVAL;
 }
 
 }  // namespace
 
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
-                  hipStream_t s) {
+                  hipStream_t s, int fuse_rt) {
+  const bool fuse = fuse_rt >= 0;
+  if (fuse && !a.rfuse) return ASQ_EINVAL;
   if (link_kind == LINK_F64_R18) {
     if (in_kind != VEC_F64) return ASQ_EINVAL;
     if (epi == EPI_RESID) {
-      if (out_kind == VEC_F64) return pick_r<LinkF64R18, VecF64, VecF64, EPI_RESID>(rtile, a, s);
-      if (out_kind == VEC_F32) return pick_r<LinkF64R18, VecF64, VecF32, EPI_RESID>(rtile, a, s);
+      if (fuse) return ASQ_EINVAL;
+      if (out_kind == VEC_F64) return pick_r<LinkF64R18, VecF64, VecF64, VecF64, EPI_RESID, false>(rtile, a, s);
+      if (out_kind == VEC_F32) return pick_r<LinkF64R18, VecF64, VecF32, VecF64, EPI_RESID, false>(rtile, a, s);
       return ASQ_EINVAL;
     }
-    if (out_kind != VEC_F64) return ASQ_EINVAL;
-    return pick_epi_sloppy<LinkF64R18, VecF64>(epi, rtile, a, s);
+    if (out_kind != VEC_F64 || (fuse && fuse_rt != VEC_F64)) return ASQ_EINVAL;
+    return pick_sloppy<LinkF64R18, VecF64, VecF64>(epi, rtile, a, s, fuse);
   }
   if (epi == EPI_RESID || in_kind != out_kind) return ASQ_EINVAL;
+  if (fuse && fuse_rt != VEC_F32) return ASQ_EINVAL;
   if (link_kind == LINK_F32_R18) {
-    if (in_kind == VEC_F32) return pick_epi_sloppy<LinkF32R18, VecF32>(epi, rtile, a, s);
-    if (in_kind == VEC_F16) return pick_epi_sloppy<LinkF32R18, VecF16>(epi, rtile, a, s);
+    if (in_kind == VEC_F32) return pick_sloppy<LinkF32R18, VecF32, VecF32>(epi, rtile, a, s, fuse);
+    if (in_kind == VEC_F16) return pick_sloppy<LinkF32R18, VecF16, VecF32>(epi, rtile, a, s, fuse);
   } else if (link_kind == LINK_F32_R12) {
-    if (in_kind == VEC_F32) return pick_epi_sloppy<LinkF32R12, VecF32>(epi, rtile, a, s);
-    if (in_kind == VEC_F16) return pick_epi_sloppy<LinkF32R12, VecF16>(epi, rtile, a, s);
+    if (in_kind == VEC_F32) return pick_sloppy<LinkF32R12, VecF32, VecF32>(epi, rtile, a, s, fuse);
+    if (in_kind == VEC_F16) return pick_sloppy<LinkF32R12, VecF16, VecF32>(epi, rtile, a, s, fuse);
   } else if (link_kind == LINK_I16_R12) {
-    if (in_kind == VEC_F16) return pick_epi_sloppy<LinkI16R12, VecF16>(epi, rtile, a, s);
+    if (in_kind == VEC_F16) return pick_sloppy<LinkI16R12, VecF16, VecF32>(epi, rtile, a, s, fuse);
   }
   return ASQ_EINVAL;
 }

@@ -58,9 +58,9 @@ size_t batch_bytes(const asq_gauge* g, int ncol, int mode, bool with_bx) {
   const int pt = mode_pt(mode), rt = mode_rt(mode);
   size_t n = 0;
   n += align_up((size_t)ncol * sizeof(ColState), 256);
-  n += align_up((size_t)ncol * g->nblk * sizeof(double), 256);
+  n += 2 * align_up((size_t)ncol * g->nblk * sizeof(double), 256);  // partials (two sets)
   n += align_up((size_t)ncol * half * vec_site_bytes(rt), 256);      // r
-  n += 3 * align_up((size_t)ncol * half * vec_site_bytes(pt), 256);  // p, Ap, t
+  n += 4 * align_up((size_t)ncol * half * vec_site_bytes(pt), 256);  // p, p_alt, Ap, t
   if (mode != ASQ_MODE_F64) n += align_up((size_t)ncol * half * 48, 256);  // t64
   if (with_bx) n += 2 * align_up((size_t)ncol * half * 48, 256);         // b, x
   return n;
@@ -85,8 +85,10 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
   B.rt = rt;
   B.st = (ColState*)take((size_t)ncol * sizeof(ColState));
   B.partials = (double*)take((size_t)ncol * g->nblk * sizeof(double));
+  B.partials_a = (double*)take((size_t)ncol * g->nblk * sizeof(double));
   B.r = take((size_t)ncol * half * vec_site_bytes(rt));
   B.p = take((size_t)ncol * half * vec_site_bytes(pt));
+  B.p_alt = take((size_t)ncol * half * vec_site_bytes(pt));
   B.Ap = take((size_t)ncol * half * vec_site_bytes(pt));
   B.t = take((size_t)ncol * half * vec_site_bytes(pt));
   B.t64 = mode == ASQ_MODE_F64 ? B.t : take((size_t)ncol * half * 48);
@@ -148,6 +150,8 @@ static VecArgs vargs(const Batch& B, int c0) {
   v.x = B.x + (size_t)c0 * half * 6;
   v.r = (char*)B.r + (size_t)c0 * half * vec_site_bytes(B.rt);
   v.p = (char*)B.p + (size_t)c0 * half * vec_site_bytes(B.pt);
+  v.p_alt = (char*)B.p_alt + (size_t)c0 * half * vec_site_bytes(B.pt);
+  v.partials_a = B.partials_a + (size_t)c0 * B.g->nblk;
   v.Ap = (char*)B.Ap + (size_t)c0 * half * vec_site_bytes(B.pt);
   v.st = B.st + c0;
   v.partials = B.partials + (size_t)c0 * B.g->nblk;
@@ -158,32 +162,39 @@ int enqueue_init(const Batch& B, int c0, int n, hipStream_t s) {
   VecArgs v = vargs(B, c0);
   int rc = launch_vec_kernel(VK_INIT, B.pt, B.rt, v, n, s);
   if (rc) return rc;
-  return launch_reduce(OP_INIT, v.st, v.partials, v.nblk, n, s);
+  return launch_reduce(OP_INIT, v.st, nullptr, v.partials, v.nblk, n, s);
 }
 
 int enqueue_iteration(const Batch& B, hipStream_t s) {
   const Gauge_t* g = B.g;
   const void* L = g->links[B.link];
+  // t = D_oe p with p = r + beta p_old formed in the gather (new p -> the other buffer)
   DslashArgs d1 = dargs(B, 1, B.p, B.t, MASK_ACTIVE);
   d1.links = L;
-  int rc = launch_dslash(B.link, B.pt, B.pt, EPI_PLAIN, B.rt_sloppy_plain, d1, s);
+  d1.in_alt = B.p_alt;
+  d1.in_sel = 1;
+  d1.rfuse = B.r;
+  int rc = launch_dslash(B.link, B.pt, B.pt, EPI_PLAIN, B.rt_sloppy_plain, d1, s, B.rt);
   if (rc) return rc;
+  // Ap = a p - D_eo t, partials of <p, Ap>
   DslashArgs d2 = dargs(B, 0, B.t, B.Ap, MASK_ACTIVE);
   d2.links = L;
   d2.y = B.p;
+  d2.y_alt = B.p_alt;
+  d2.y_sel = 1;
+  d2.partials = B.partials_a;
   rc = launch_dslash(B.link, B.pt, B.pt, EPI_XPAY_DOT, B.rt_sloppy_xpay, d2, s);
   if (rc) return rc;
-  rc = launch_reduce(OP_ALPHA, B.st, B.partials, g->nblk, B.ncol, s);
-  if (rc) return rc;
+  // alpha; x += alpha p, r -= alpha Ap, partials of |r|^2
   VecArgs v = vargs(B, 0);
   rc = launch_vec_kernel(VK_XR, B.pt, B.rt, v, B.ncol, s);
   if (rc) return rc;
-  rc = launch_reduce(OP_BETA, B.st, B.partials, g->nblk, B.ncol, s);
-  if (rc) return rc;
-  return launch_vec_kernel(VK_P, B.pt, B.rt, v, B.ncol, s);
+  // alpha, beta, triggers, p buffer swap
+  return launch_reduce(OP_STEP, B.st, B.partials_a, B.partials, g->nblk, B.ncol, s);
 }
 
-// r = b - A x with FP64 links and vectors for the columns that asked for it.
+// r = b - A x with FP64 links and vectors for the columns that asked for it,
+// then the decision on the true residual.
 int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s) {
   const Gauge_t* g = B.g;
   const void* L = g->links[LINK_F64_R18];
@@ -197,7 +208,7 @@ int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s) {
   d2.b = B.b;
   rc = launch_dslash(LINK_F64_R18, VEC_F64, B.rt, EPI_RESID, B.rt64_resid, d2, s);
   if (rc) return rc;
-  return launch_reduce(op, B.st, B.partials, g->nblk, B.ncol, s);
+  return launch_reduce(op, B.st, nullptr, B.partials, g->nblk, B.ncol, s);
 }
 
 int enqueue_block(const Batch& B, int iters, hipStream_t s) {
