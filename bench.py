@@ -1,20 +1,24 @@
 """Benchmark of the even-odd asqtad CG on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single_20x20x20x64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]             # the headline line
+    python bench.py --workload batched_20x20x20x64                  # 24 RHS x 4 masses, FP16 vectors
+    python bench.py --workload threelevel_48x48x48x96               # 12 RHS, 12-real 16-bit links
+    python bench.py --workload serving [--requests N]               # Poisson request stream
+    python bench.py --kernels-only                                  # fixed launches for counter runs
 
-A step is one complete solve of A x = b (A = 4m^2 - D_eo D_oe, even sites) to a
-relative FP64 true residual of 1e-10 with the mixed-precision reliable-update
-CG, on synthetic fields shaped like the paper's 20^3 x 64 lattice (inputs
-already resident in HBM).  Rank 0 prints one JSON line with solves/s, the
-time-to-1e-10, CG GFLOPS (1146 flops per site per Dslash), the speed-up over the
-plain FP64 GPU CG, the Dslash HBM roofline (HIP events on the launch stream) and
-the CPU oracle baseline on a bounded sample.
+Headline step: one complete solve of A x = b (A = 4m^2 - D_eo D_oe, even
+sites) to a relative FP64 true residual of 1e-10 with the mixed-precision
+reliable-update CG, on synthetic fields shaped like the paper's 20^3 x 64
+lattice, inputs already resident in HBM.  Rank 0 prints one JSON line with
+solves/s, the time-to-1e-10, CG GFLOPS (1146 flops per site per Dslash), the
+speed-up over the plain FP64 GPU CG, the Dslash HBM roofline (HIP events on
+the launch stream) and the CPU oracle baseline on a bounded sample.  The other
+workloads print their own JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,10 +31,20 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes per output site of one half-Dslash at 1 RHS: 16 links + one
-# input vector + one output vector (each input read once, the output written once)
-BYTES_PER_SITE = {"f64": 16 * 144 + 2 * 48, "f32": 16 * 72 + 2 * 24, "f32r12": 16 * 48 + 2 * 24,
-                  "f16": 16 * 72 + 2 * 16, "f16r12": 16 * 24 + 2 * 16}
+# FP32 vector peak of MI355X with packed FP32 (157.3 TFLOP/s) and without it: the
+# library is built without packed-FP32 instructions, so 256 CU x 2.4 GHz x 128
+# FP32 flop/clk = 78.6 TFLOP/s is the arithmetic ceiling of its kernels.
+PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_FP32_TFLOPS = 78.6
+METRIC = "asqtad Dslash HBM GB/s; CG time-to-1e-10 at 20^3x64; solves/s + p99 latency"
+
+LINK_BYTES = {"f64": 144, "f32": 72, "f32r12": 48, "f16r12": 24}
+VEC_BYTES = {"f64": 48, "f32": 24, "f16": 16}
+
+
+def dslash_bytes_per_site(link, vec, nrhs):
+    """Algorithmic bytes of one half-Dslash per output site: 16 links, nrhs input and output vectors."""
+    return 16 * LINK_BYTES[link] + nrhs * 2 * VEC_BYTES[vec]
 
 
 def parse():
@@ -38,41 +52,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="single_20x20x20x64")
+    ap.add_argument("--workload", default="single_20x20x20x64",
+                    choices=["single_20x20x20x64", "batched_20x20x20x64", "threelevel_48x48x48x96", "serving"])
     ap.add_argument("--mode", default="mixed32", choices=["f64", "mixed32", "mixed16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound on the oracle sample")
     ap.add_argument("--dslash-launches", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=600, help="serving: measured requests (after warm-up)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch the Dslash tiers and a 1 GiB copy probe (for hardware-counter runs)")
     return ap.parse_args()
-
-
-def kernels_only(args, asq, g, dims):
-    """Fixed launches for counter collection: each Dslash tier 20 times, then the copy probe."""
-    import torch
-
-    half = int(np.prod(dims)) // 2
-    stream = torch.cuda.Stream()
-    res = {}
-    for prec in ("f32", "f64", "f16"):
-        dt = time_dslash(asq, g, prec, 1, 20, stream)
-        key = prec
-        res[prec] = {"us": dt * 1e6, "alg_bytes": BYTES_PER_SITE[key] * half}
-    n = 1 << 30
-    src = torch.empty(n, dtype=torch.uint8, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        asq.check(asq.asq_copy_probe(dst.data_ptr(), src.data_ptr(), n, asq.stream_ptr(stream)), "copy")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(5):
-        asq.check(asq.asq_copy_probe(dst.data_ptr(), src.data_ptr(), n, asq.stream_ptr(stream)), "copy")
-    e1.record(stream)
-    e1.synchronize()
-    dt = e0.elapsed_time(e1) * 1e-3 / 5
-    res["copy"] = {"us": dt * 1e6, "bytes_read": n, "bytes_written": n, "GBps": 2 * n / dt / 1e9}
-    print(json.dumps({"kernels_only": res}), flush=True)
 
 
 def log(msg):
@@ -140,78 +129,92 @@ def cpu_baseline(w, fat, lng, b, mass, iters_full, seconds):
             "seconds_per_solve": t_solve}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
+def kernels_only(asq, g, dims):
+    """Fixed launches for counter collection: each Dslash tier 20 times, then the copy probe."""
     import torch
 
-    import paper_1411_2223_amd as asq
+    half = int(np.prod(dims)) // 2
+    stream = torch.cuda.Stream()
+    res = {}
+    for prec, link in (("f32", "f32"), ("f64", "f64"), ("f16", "f32")):
+        dt = time_dslash(asq, g, prec, 1, 20, stream)
+        res[prec] = {"us": dt * 1e6, "alg_bytes": dslash_bytes_per_site(link, prec, 1) * half}
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        asq.check(asq.asq_copy_probe(dst.data_ptr(), src.data_ptr(), n, asq.stream_ptr(stream)), "copy")
+    torch.cuda.synchronize()
+    res["copy"] = {"bytes_read": n, "bytes_written": n}
+    print(json.dumps({"kernels_only": res}), flush=True)
 
-    asq.load()
-    w = synth.WORKLOADS[args.workload]
+
+def solve_series(g, masses, bd, mode, tol, steps, warmup, stream, work=None, x=None):
+    """warm-up + timed solves; returns (seconds per solve, last SolveResult)."""
+    import torch
+
+    for k in range(warmup):
+        r = g.solve(masses, bd, mode=mode, tol=tol, maxiter=50000, work=work, x=x, stream=stream)
+        s0 = r.stats[0]
+        log(f"warmup {k}: rc={r.rc} iters={s0['iters']} ru={s0['reliable_updates']} "
+            f"resid={max(s['true_resid'] for s in r.stats):.3e} {s0['seconds'] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        last = g.solve(masses, bd, mode=mode, tol=tol, maxiter=50000, work=work, x=x, stream=stream)
+        if last.rc != 0:
+            raise SystemExit(f"solve failed rc={last.rc}")
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, last
+
+
+# ---------------------------------------------------------------------------
+
+
+def run_single(args, asq, torch):
+    w = synth.WORKLOADS["single_20x20x20x64"]
     dims, mass = w["dims"], w["masses"][0]
     half = int(np.prod(dims)) // 2
-    log(f"workload {args.workload} dims={dims} m={mass} mode={args.mode}")
+    log(f"workload single_20x20x20x64 dims={dims} m={mass} mode={args.mode}")
     fat, lng = synth.make_gauge(dims, w["eps"], synth.gauge_seed(w["index"]))
     b = synth.make_sources(dims, 1, synth.source_seed(w["index"]))
     g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
     if args.kernels_only:
-        kernels_only(args, asq, g, dims)
+        kernels_only(asq, g, dims)
         return
     stream = torch.cuda.Stream()
     bd = asq.vec_to_device(b, "f64")
     work = g.workspace(1, args.mode)
     x = torch.empty_like(bd)
     torch.cuda.synchronize()
-
-    def step(mode, wk):
-        return g.solve([mass], bd, mode=mode, tol=w["tol"], maxiter=50000, work=wk, x=x, stream=stream)
-
-    for k in range(args.warmup):
-        r = step(args.mode, work)
-        log(f"warmup {k}: iters={r.stats[0]['iters']} ru={r.stats[0]['reliable_updates']} "
-            f"resid={r.stats[0]['true_resid']:.3e} {r.stats[0]['seconds'] * 1e3:.1f} ms")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last = None
-    for k in range(args.steps):
-        last = step(args.mode, work)
-        if last.rc != 0:
-            raise SystemExit(f"solve failed rc={last.rc}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    secs, last = solve_series(g, [mass], bd, args.mode, w["tol"], args.steps, args.warmup, stream, work, x)
     st = last.stats[0]
-    log(f"timed {args.steps} solves in {elapsed:.3f} s; iters={st['iters']} ru={st['reliable_updates']} "
+    log(f"timed {args.steps} solves: {secs * 1e3:.2f} ms each; iters={st['iters']} ru={st['reliable_updates']} "
         f"resid={st['true_resid']:.3e}")
-
     # plain FP64 GPU CG at the same accuracy (speed-up reference), outside the timed region
     work64 = g.workspace(1, "f64")
-    r64 = step("f64", work64)
-    r64 = step("f64", work64)
-    t64 = r64.stats[0]["seconds"]
+    t64, r64 = solve_series(g, [mass], bd, "f64", w["tol"], 2, 1, stream, work64, x)
     log(f"f64 CG: iters={r64.stats[0]['iters']} resid={r64.stats[0]['true_resid']:.3e} {t64 * 1e3:.1f} ms")
 
-    # dominant kernel: the sloppy single-RHS Dslash (FP32 vectors, FP32 18-real links)
-    prec_key = "f32" if args.mode == "mixed32" else ("f64" if args.mode == "f64" else "f16")
+    # dominant kernel: the sloppy single-RHS Dslash
     tprec = {"mixed32": "f32", "f64": "f64", "mixed16": "f16"}[args.mode]
+    link = "f64" if tprec == "f64" else "f32"
     dt = time_dslash(asq, g, tprec, 1, args.dslash_launches, stream)
-    bytes_launch = BYTES_PER_SITE[prec_key] * half
+    bytes_launch = dslash_bytes_per_site(link, tprec, 1) * half
     achieved = bytes_launch / dt / 1e9
     dt64 = time_dslash(asq, g, "f64", 1, max(20, args.dslash_launches // 4), stream)
-    log(f"dslash {tprec}: {dt * 1e6:.2f} us, {achieved:.0f} GB/s; f64: {dt64 * 1e6:.2f} us, "
-        f"{BYTES_PER_SITE['f64'] * half / dt64 / 1e9:.0f} GB/s")
-
+    f64_gbs = dslash_bytes_per_site("f64", "f64", 1) * half / dt64 / 1e9
+    log(f"dslash {tprec}: {dt * 1e6:.2f} us, {achieved:.0f} GB/s; f64: {dt64 * 1e6:.2f} us, {f64_gbs:.0f} GB/s")
     copy_gbs = copy_bandwidth(asq, stream)
     log(f"copy probe: {copy_gbs:.0f} GB/s")
-    ms = elapsed / args.steps * 1e3
+
+    ms = secs * 1e3
     iters = st["iters"]
     flops = half * ((2 * 1146 + 72) * iters + (2 * 1146 + 36) * st["reliable_updates"])
     out = {
-        "metric": "asqtad Dslash HBM GB/s; CG time-to-1e-10 at 20^3x64; solves/s + p99 latency",
-        "value": args.steps / elapsed,
+        "metric": METRIC,
+        "value": 1.0 / secs,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -220,33 +223,197 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.mode == "mixed32" else ("f64" if args.mode == "f64" else "f16"),
+        "dtype": {"mixed32": "f32", "f64": "f64", "mixed16": "f16"}[args.mode],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} even-odd asqtad CG, "
-                               f"1 RHS, m={mass}, eps={w['eps']}, tol 1e-10 true residual, {args.mode} "
-                               f"reliable-update CG, FP32/FP64 18-real links",
+        "config": {"workload": f"single_20x20x20x64: 20x20x20x64 even-odd asqtad CG, 1 RHS, m={mass}, "
+                               f"eps={w['eps']} SU(3) links, tol 1e-10 FP64 true residual, {args.mode} "
+                               f"reliable-update CG, FP32 and FP64 18-real links",
                    "global_batch": 1, "parallelism": "single GPU"},
         "time_to_solution_ms": ms,
         "iterations": iters,
         "reliable_updates": st["reliable_updates"],
         "true_resid": st["true_resid"],
-        "cg_gflops": flops / (ms * 1e-3) / 1e9,
+        "cg_gflops": flops / secs / 1e9,
         "f64_cg_ms": t64 * 1e3,
         "f64_cg_iterations": r64.stats[0]["iters"],
-        "speedup_vs_f64_cg": t64 * 1e3 / ms,
+        "speedup_vs_f64_cg": t64 / secs,
         "dslash_gbs": achieved,
-        "dslash_f64_gbs": BYTES_PER_SITE["f64"] * half / dt64 / 1e9,
+        "dslash_f64_gbs": f64_gbs,
         "copy_probe_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": f"dslash_kernel {tprec} 18-real, 1 RHS", "us_per_launch": dt * 1e6,
-                     "bytes_per_launch": bytes_launch},
-        "paper_context": {"cg_gflops_titan_black_mixed": 46.48, "note": "other hardware, real MILC ensemble"},
+                     "kernel": f"dslash_kernel {tprec} vectors, {link} 18-real links, 1 RHS",
+                     "us_per_launch": dt * 1e6, "bytes_per_launch": bytes_launch},
+        "paper_context": {"cg_gflops_titan_black_mixed_own_code": 46.48, "cg_gflops_titan_black_quda": 97.86,
+                          "note": "other hardware, real MILC ensemble, flop convention unstated"},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, fat, lng, b[0], mass, r64.stats[0]["iters"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def run_batched(args, asq, torch):
+    """24 Gaussian RHS x 4 masses = 96 columns in one batch, FP16-with-norm vectors, FP32 18-real links."""
+    w = synth.WORKLOADS["batched_20x20x20x64"]
+    dims = w["dims"]
+    half = int(np.prod(dims)) // 2
+    nsrc, masses_u = w["nrhs"], list(w["masses"])
+    masses = [m for m in masses_u for _ in range(nsrc)]
+    ncol = len(masses)
+    log(f"workload batched dims={dims} columns={ncol}")
+    fat, lng = synth.make_gauge(dims, w["eps"], synth.gauge_seed(w["index"]))
+    src = synth.make_sources(dims, nsrc, synth.source_seed(w["index"]))
+    b = np.concatenate([src] * len(masses_u), axis=0)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    stream = torch.cuda.Stream()
+    bd = asq.vec_to_device(b, "f64")
+    mode = "mixed16" if args.mode == "mixed32" else args.mode
+    work = g.workspace(ncol, mode)
+    x = torch.empty_like(bd)
+    steps = max(1, min(args.steps, 3))
+    secs, last = solve_series(g, masses, bd, mode, w["tol"], steps, 1, stream, work, x)
+    its = [s["iters"] for s in last.stats]
+    res = [s["true_resid"] for s in last.stats]
+    log(f"batched {ncol} columns: {secs:.3f} s; iters min/max {min(its)}/{max(its)}; resid max {max(res):.3e}")
+    tprec = "f16" if mode == "mixed16" else ("f32" if mode == "mixed32" else "f64")
+    link = "f64" if tprec == "f64" else "f32"
+    dt = time_dslash(asq, g, tprec, ncol, 20, stream)
+    bytes_launch = dslash_bytes_per_site(link, tprec, ncol) * half
+    flops_launch = 1146.0 * half * ncol
+    gbs = bytes_launch / dt / 1e9
+    tf = flops_launch / dt / 1e12
+    log(f"dslash {tprec} x{ncol}: {dt * 1e6:.1f} us, {gbs:.0f} GB/s, {tf:.1f} TFLOP/s")
+    flops = half * sum((2 * 1146 + 72) * s["iters"] + (2 * 1146 + 36) * s["reliable_updates"] for s in last.stats)
+    out = {"metric": METRIC, "workload": "batched_20x20x20x64", "value": ncol / secs, "unit": "RHS-solves/s",
+           "columns": ncol, "masses": masses_u, "seconds_per_batch": secs, "mode": mode,
+           "iters_min": min(its), "iters_max": max(its), "true_resid_max": max(res),
+           "cg_gflops": flops / secs / 1e9,
+           "dslash": {"us": dt * 1e6, "GBps": gbs, "TFLOPs": tf, "bytes_per_site": bytes_launch / half,
+                      "flop_per_byte": flops_launch / bytes_launch,
+                      "frac_hbm": gbs / PEAK_HBM_GBS, "frac_fp32_alu": tf / PEAK_FP32_TFLOPS,
+                      "frac_fp32_packed_peak": tf / PEAK_FP32_PACKED_TFLOPS}}
+    print(json.dumps(out), flush=True)
+
+
+def run_threelevel(args, asq, torch):
+    """48^3 x 96, 12 RHS, m = 0.005: FP16-with-norm vectors and 16-bit 12-real links in the iteration,
+    FP32 arithmetic and residual, FP64 solution and true residual."""
+    w = synth.WORKLOADS["threelevel_48x48x48x96"]
+    dims, mass, ncol = w["dims"], w["masses"][0], w["nrhs"]
+    half = int(np.prod(dims)) // 2
+    log(f"workload threelevel dims={dims} columns={ncol} (gauge generation takes a while)")
+    t0 = time.perf_counter()
+    fat, lng = synth.make_gauge(dims, w["eps"], synth.gauge_seed(w["index"]))
+    log(f"gauge generated in {time.perf_counter() - t0:.0f} s")
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
+    del fat, lng
+    b = synth.make_sources(dims, ncol, synth.source_seed(w["index"]))
+    stream = torch.cuda.Stream()
+    bd = asq.vec_to_device(b, "f64")
+    del b
+    work = g.workspace(ncol, "mixed16")
+    x = torch.empty_like(bd)
+    secs, last = solve_series(g, [mass] * ncol, bd, "mixed16", w["tol"], 1, 1, stream, work, x)
+    its = [s["iters"] for s in last.stats]
+    res = [s["true_resid"] for s in last.stats]
+    log(f"three-level {ncol} columns: {secs:.3f} s; iters {max(its)}; resid max {max(res):.3e}")
+    dt = time_dslash(asq, g, "f16", ncol, 10, stream)
+    bytes_launch = dslash_bytes_per_site("f16r12", "f16", ncol) * half
+    gbs = bytes_launch / dt / 1e9
+    tf = 1146.0 * half * ncol / dt / 1e12
+    dt1 = time_dslash(asq, g, "f16", 1, 10, stream)
+    gbs1 = dslash_bytes_per_site("f16r12", "f16", 1) * half / dt1 / 1e9
+    log(f"dslash f16 r12 x{ncol}: {dt * 1e6:.0f} us, {gbs:.0f} GB/s, {tf:.1f} TFLOP/s; 1 RHS {gbs1:.0f} GB/s")
+    out = {"metric": METRIC, "workload": "threelevel_48x48x48x96", "value": secs * 1e3, "unit": "ms to 1e-10",
+           "columns": ncol, "mass": mass, "iters_max": max(its), "true_resid_max": max(res),
+           "reliable_updates": max(s["reliable_updates"] for s in last.stats),
+           "dslash_12rhs": {"us": dt * 1e6, "GBps": gbs, "TFLOPs": tf, "frac_hbm": gbs / PEAK_HBM_GBS,
+                            "frac_fp32_alu": tf / PEAK_FP32_TFLOPS},
+           "dslash_1rhs_GBps": gbs1}
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args, asq, torch):
+    """Poisson stream of solves on four resident lattices (continuous batching, HBM budget)."""
+    lattices = synth.SERVING_LATTICES
+    n_warm = 50
+    trace = synth.serving_trace(args.requests + n_warm)
+    gauges, pools = [], []
+    for k, dims in enumerate(lattices):
+        fat, lng = synth.make_gauge(dims, 0.3, synth.BASE_SEED + 10 + k)
+        gauges.append(asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18))
+        pools.append(asq.vec_to_device(synth.make_sources(dims, 12, synth.BASE_SEED + 20 + k), "f64"))
+        del fat, lng
+    budget = 48 << 30
+    srv = asq.Server(budget, max_streams=4, max_cols=16)
+    gids = [srv.register(gg) for gg in gauges]
+    torch.cuda.synchronize()
+    log(f"serving {len(trace)} requests ({n_warm} warm-up), budget {budget >> 30} GiB")
+    pending = {}
+    done = []
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(trace) or pending:
+        now = time.perf_counter() - t0
+        while k < len(trace) and trace[k]["arrival"] <= now:
+            q = trace[k]
+            lat = q["lattice"]
+            n = q["nrhs"]
+            b = pools[lat][:n]
+            x = torch.empty_like(b)
+            t = srv.submit(gids[lat], [q["mass"]] * n, b, x, mode="mixed32")
+            pending[t] = (k, n, x)
+            k += 1
+        for t in list(pending):
+            kk, n, x = pending[t]
+            r = srv.poll(t, n)
+            if r is not None:
+                rc, stats, latency = r
+                done.append((kk, rc, latency, n, trace[kk]["lattice"], max(s["true_resid"] for s in stats)))
+                del pending[t]
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    srv.close()
+    meas = [d for d in done if d[0] >= n_warm]
+    lats = np.array([d[2] for d in meas])
+    rhs = sum(d[3] for d in meas)
+    bad = [d for d in meas if d[1] != 0]
+    span = trace[-1]["arrival"] - trace[n_warm]["arrival"]
+    per_lat = {}
+    for i in range(len(lattices)):
+        li = [d[2] for d in meas if d[4] == i]
+        if li:
+            per_lat["x".join(map(str, lattices[i]))] = {"n": len(li), "p50_ms": float(np.percentile(li, 50) * 1e3),
+                                                        "p99_ms": float(np.percentile(li, 99) * 1e3)}
+    out = {"metric": METRIC, "workload": "serving", "value": len(meas) / wall, "unit": "requests/s",
+           "requests": len(meas), "rhs_solves": rhs, "wall_s": wall, "offered_requests_per_s": len(meas) / span,
+           "achieved_rhs_per_s": rhs / wall, "p50_latency_ms": float(np.percentile(lats, 50) * 1e3),
+           "p99_latency_ms": float(np.percentile(lats, 99) * 1e3), "failed": len(bad),
+           "true_resid_max": max(d[5] for d in meas), "per_lattice": per_lat}
+    log(f"serving: {out['value']:.1f} req/s, p50 {out['p50_latency_ms']:.1f} ms, p99 {out['p99_latency_ms']:.1f} ms")
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_1411_2223_amd as asq
+
+    asq.load()
+    if args.workload == "single_20x20x20x64":
+        run_single(args, asq, torch)
+    elif args.workload == "batched_20x20x20x64":
+        run_batched(args, asq, torch)
+    elif args.workload == "threelevel_48x48x48x96":
+        run_threelevel(args, asq, torch)
+    else:
+        run_serving(args, asq, torch)
 
 
 if __name__ == "__main__":

@@ -276,3 +276,56 @@ class Gauge:
         if rc < 0 and rc not in (ASQ_ENOCONV,):
             check(rc, "cg_solve_batch")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
+
+
+class Server:
+    """Continuous-batching solve server over a caller-owned arena (the HBM budget)."""
+
+    def __init__(self, arena_bytes, max_streams=4, max_cols=16, device="cuda"):
+        load()
+        self.arena = empty_bytes(int(arena_bytes), device)
+        h = ctypes.c_void_p()
+        check(serve_create(self.arena.data_ptr(), int(arena_bytes), int(max_streams), int(max_cols),
+                           ctypes.byref(h)), "serve_create")
+        self.handle = h
+        self.gauges = []
+
+    def register(self, gauge):
+        gid = ctypes.c_int()
+        check(serve_register_gauge(self.handle, gauge.handle, ctypes.byref(gid)), "serve_register_gauge")
+        self.gauges.append(gauge)
+        return gid.value
+
+    def submit(self, gauge_id, masses, b, x, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.1, poll_iters=8,
+               use_graph=True):
+        masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
+        n = len(masses)
+        params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
+                               1 if use_graph else 0)
+        t = ctypes.c_uint64()
+        rc = serve_submit(self.handle, int(gauge_id), n, (ctypes.c_double * n)(*masses), b.data_ptr(), x.data_ptr(),
+                          ctypes.byref(params), ctypes.byref(t))
+        check(rc, "serve_submit")
+        return t.value
+
+    def poll(self, ticket, nrhs):
+        """None while pending; else (rc, per-column stats, latency seconds)."""
+        stats = (asq_cg_stats * int(nrhs))()
+        lat = ctypes.c_double()
+        rc = serve_poll(self.handle, ctypes.c_uint64(ticket), stats, ctypes.byref(lat))
+        if rc == ASQ_PENDING:
+            return None
+        if rc == ASQ_EINVAL:
+            check(rc, "serve_poll")
+        return rc, [s.as_dict() for s in stats], lat.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

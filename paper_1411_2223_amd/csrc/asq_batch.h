@@ -14,6 +14,8 @@ struct Batch {
   int pt = 0, rt = 0;  // storage tiers of p/Ap/t and of r
   int link = 0;        // link tier of the iterated Dslash
   int rt_sloppy_plain = 1, rt_sloppy_xpay = 1, rt64_plain = 1, rt64_resid = 1;
+  bool fuse_p = true;  // direction update inside the D_oe gather (else its own kernel)
+  bool sweep = true;   // D_eo walks the lattice backwards (MALL reuse of the links)
   ColState* st = nullptr;
   double* partials = nullptr;    // [ncol][nblk] partials of |r|^2 (update, residual, init)
   double* partials_a = nullptr;  // [ncol][nblk] partials of <p, A p> (D_eo)

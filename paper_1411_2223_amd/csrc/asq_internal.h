@@ -90,8 +90,8 @@ struct DslashArgs {
   int ntiles;
   const void* links;
   const void* in;       // input vector (other parity)
-  const void* in_alt;   // second p buffer: with in_sel = 1 the input is the column's current p
-  int in_sel;
+  const void* in_alt;   // second p buffer: in_sel = 1 reads the column's current p
+  int in_sel;           // (in if pbuf == 0), in_sel = 2 the new one (in_alt if pbuf == 0)
   const void* rfuse;    // fused direction update: input = r + beta * p (p = in / in_alt), the new p
                         // is written by the owning thread into the other p buffer
   void* out;
@@ -105,6 +105,7 @@ struct DslashArgs {
   int nblk;
   double coeff_fat;     // 12-real tiers: fat / long coefficients re-applied in-kernel
   double coeff_long;
+  int reverse;          // walk the lattice from the last site block to the first
 };
 
 // Launch one Dslash; link_kind / in_kind / out_kind select the template.

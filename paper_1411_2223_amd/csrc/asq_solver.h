@@ -4,7 +4,7 @@
 
 namespace asq {
 
-enum VecKernel { VK_INIT = 0, VK_XR = 1 };
+enum VecKernel { VK_INIT = 0, VK_XR = 1, VK_P = 2 };
 
 struct VecArgs {
   int half;

@@ -86,6 +86,31 @@ __global__ void __launch_bounds__(kBlock) update_xr_kernel(const VecArgs A) {
   if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
 }
 
+// p_new = r + beta p into the buffer that is not current (the unfused form of
+// the direction update; the fused form lives in the D_oe gather).
+template <class PT, class RT>
+__global__ void __launch_bounds__(kBlock) update_p_kernel(const VecArgs A) {
+  const int c = blockIdx.y, sblk = blockIdx.x;
+  const ColState& S = A.st[c];
+  if (!state_on(S, MASK_ACTIVE)) return;
+  using pr = typename PT::real;
+  const int half = A.half;
+  const int i = sblk * kBlock + (int)threadIdx.x;
+  if (i >= half) return;
+  const void* pcur = S.pbuf ? A.p_alt : A.p;
+  void* pnew = S.pbuf ? A.p : A.p_alt;
+  const pr beta = (pr)S.beta;
+  const Vec3<pr> r = convert<pr>(RT::load(A.r, half, c, i));
+  const Vec3<pr> p = PT::load(pcur, half, c, i);
+  Vec3<pr> v;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    v.c[a].re = fmaR(beta, p.c[a].re, r.c[a].re);
+    v.c[a].im = fmaR(beta, p.c[a].im, r.c[a].im);
+  }
+  PT::store(pnew, half, c, i, v);
+}
+
 // Scalar kernel: fixed-order sums of a column's partials, then its update.
 // OP_STEP closes a CG iteration (alpha from the D_eo partials, then beta,
 // triggers and the p buffer swap from the |r|^2 partials); OP_INIT, OP_RU and
@@ -130,6 +155,8 @@ int launch_vec(int which, const VecArgs& a, int ncol, hipStream_t s) {
     init_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
   } else if (which == VK_XR) {
     update_xr_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
+  } else if (which == VK_P) {
+    update_p_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
   } else {
     return ASQ_EINVAL;
   }

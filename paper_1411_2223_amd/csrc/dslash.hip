@@ -137,7 +137,10 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
 template <class Link, class InT, class OutT, class RT, int R, int EPI, bool FUSEP>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   using real = typename InT::real;
-  const int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  // Alternate sweeps start on the links the previous sweep read last, which the
+  // memory-side cache (MALL) still holds.
+  if (A.reverse) lin = (int)gridDim.x - 1 - lin;
   const int tile = lin % A.ntiles;  // column tiles of the same sites are neighbours in dispatch order
   const int sblk = lin / A.ntiles;
   const int c0 = tile * R;
@@ -148,7 +151,8 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     const int c = c0 + r;
     C.on[r] = col_on(A, c);
     any |= C.on[r];
-    const int pb = (C.on[r] && A.in_sel) ? A.st[c].pbuf : 0;
+    int pb = (C.on[r] && A.in_sel) ? A.st[c].pbuf : 0;
+    if (A.in_sel == 2) pb ^= 1;
     C.in[r] = pb ? A.in_alt : A.in;
     C.pnew[r] = const_cast<void*>(pb ? A.in : A.in_alt);
     C.beta[r] = (FUSEP && C.on[r]) ? (real)A.st[c].beta : (real)0;

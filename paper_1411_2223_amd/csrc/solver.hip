@@ -44,6 +44,12 @@ bool log_enabled() {
   return on == 1;
 }
 
+bool env_flag(const char* name, bool dflt) {
+  const char* e = getenv(name);
+  if (!e || !*e) return dflt;
+  return *e != '0';
+}
+
 int mode_pt(int mode) { return mode == ASQ_MODE_F64 ? VEC_F64 : (mode == ASQ_MODE_MIXED32 ? VEC_F32 : VEC_F16); }
 int mode_rt(int mode) { return mode == ASQ_MODE_F64 ? VEC_F64 : VEC_F32; }
 
@@ -100,6 +106,8 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
     B.x = x;
   }
   B.link = sloppy_link(g, mode);
+  B.fuse_p = env_flag("ASQ_FUSE_P", false);
+  B.sweep = env_flag("ASQ_SWEEP", true);
   batch_pick_tiles(B);
   return ASQ_OK;
 }
@@ -168,13 +176,23 @@ int enqueue_init(const Batch& B, int c0, int n, hipStream_t s) {
 int enqueue_iteration(const Batch& B, hipStream_t s) {
   const Gauge_t* g = B.g;
   const void* L = g->links[B.link];
-  // t = D_oe p with p = r + beta p_old formed in the gather (new p -> the other buffer)
+  VecArgs v = vargs(B, 0);
+  int rc;
   DslashArgs d1 = dargs(B, 1, B.p, B.t, MASK_ACTIVE);
   d1.links = L;
   d1.in_alt = B.p_alt;
-  d1.in_sel = 1;
-  d1.rfuse = B.r;
-  int rc = launch_dslash(B.link, B.pt, B.pt, EPI_PLAIN, B.rt_sloppy_plain, d1, s, B.rt);
+  if (B.fuse_p) {
+    // t = D_oe p with p = r + beta p_old formed in the gather (new p -> the other buffer)
+    d1.in_sel = 1;
+    d1.rfuse = B.r;
+    rc = launch_dslash(B.link, B.pt, B.pt, EPI_PLAIN, B.rt_sloppy_plain, d1, s, B.rt);
+  } else {
+    // p_new = r + beta p, then t = D_oe p_new
+    rc = launch_vec_kernel(VK_P, B.pt, B.rt, v, B.ncol, s);
+    if (rc) return rc;
+    d1.in_sel = 2;
+    rc = launch_dslash(B.link, B.pt, B.pt, EPI_PLAIN, B.rt_sloppy_plain, d1, s);
+  }
   if (rc) return rc;
   // Ap = a p - D_eo t, partials of <p, Ap>
   DslashArgs d2 = dargs(B, 0, B.t, B.Ap, MASK_ACTIVE);
@@ -183,10 +201,10 @@ int enqueue_iteration(const Batch& B, hipStream_t s) {
   d2.y_alt = B.p_alt;
   d2.y_sel = 1;
   d2.partials = B.partials_a;
+  d2.reverse = B.sweep ? 1 : 0;
   rc = launch_dslash(B.link, B.pt, B.pt, EPI_XPAY_DOT, B.rt_sloppy_xpay, d2, s);
   if (rc) return rc;
   // alpha; x += alpha p, r -= alpha Ap, partials of |r|^2
-  VecArgs v = vargs(B, 0);
   rc = launch_vec_kernel(VK_XR, B.pt, B.rt, v, B.ncol, s);
   if (rc) return rc;
   // alpha, beta, triggers, p buffer swap
@@ -206,6 +224,7 @@ int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s) {
   d2.links = L;
   d2.y = B.x;
   d2.b = B.b;
+  d2.reverse = B.sweep ? 1 : 0;
   rc = launch_dslash(LINK_F64_R18, VEC_F64, B.rt, EPI_RESID, B.rt64_resid, d2, s);
   if (rc) return rc;
   return launch_reduce(op, B.st, nullptr, B.partials, g->nblk, B.ncol, s);
