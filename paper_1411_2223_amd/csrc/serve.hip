@@ -49,6 +49,7 @@ struct Request {
   Run* run = nullptr;
   hipEvent_t done_ev = nullptr;
   std::vector<asq_cg_stats> stats;
+  std::vector<char> col_done;
 };
 
 struct Run {
@@ -236,6 +237,7 @@ bool admit(asq_server* S, Request* q) {
   q->slot0 = c0;
   q->cols_left = q->nrhs;
   q->stats.assign(q->nrhs, asq_cg_stats{});
+  q->col_done.assign(q->nrhs, 0);
   q->state = 1;
   return true;
 }
@@ -249,27 +251,32 @@ void launch_block(Run* r) {
   r->t_block = clk::now();
 }
 
-// Retire finished columns of a run whose block has completed.
+// Retire finished columns of a run whose block has completed.  A finished
+// column keeps its slot (its x is still in the batch) until every column of
+// its request is done; then x is copied out and all the request's slots are
+// released together (later work on this stream is ordered after the copy).
 void harvest(asq_server* S, Run* r) {
   const size_t half = (size_t)r->g->geom.half;
   for (int c = 0; c < r->cap; ++c) {
     Request* q = r->owner[c];
     if (!q || q->state != 1) continue;
+    const int k = c - q->slot0;
+    if (q->col_done[k]) continue;
     const ColState& st = r->pinned[c];
     if (st.active) continue;
-    const int k = c - q->slot0;
     int worst = ASQ_OK;
     Batch one = r->B;
     one.ncol = 1;
     fill_stats(one, &st, 0.0, &q->stats[k], &worst);
     if (worst != ASQ_OK && (q->rc == ASQ_OK || worst == ASQ_ENAN)) q->rc = worst;
-    r->owner[c] = nullptr;  // slot reusable: later work on this stream is ordered after the copy-out
+    q->col_done[k] = 1;
     if (--q->cols_left == 0) {
       hipMemcpyAsync(q->x, r->B.x + (size_t)q->slot0 * half * 6, (size_t)q->nrhs * half * 48,
                      hipMemcpyDeviceToDevice, r->stream);
       hipEventCreateWithFlags(&q->done_ev, hipEventDisableTiming);
       hipEventRecord(q->done_ev, r->stream);
       q->state = 2;
+      for (int j = 0; j < q->nrhs; ++j) r->owner[q->slot0 + j] = nullptr;
     }
   }
   (void)S;
