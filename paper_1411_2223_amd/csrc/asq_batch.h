@@ -21,6 +21,7 @@ struct Batch {
   double* partials_a = nullptr;  // [ncol][nblk] partials of <p, A p> (D_eo)
   double* b = nullptr;  // F64 [ncol][3][half][2]
   double* x = nullptr;
+  void* xs = nullptr;  // F32 accumulator of x between reliable updates (mixed modes)
   void* r = nullptr;
   void* p = nullptr;      // two direction buffers; ColState::pbuf selects the current one
   void* p_alt = nullptr;

@@ -365,6 +365,19 @@ struct VecF16 {
   __device__ __forceinline__ static Vec3<float> load(const void* base, int half, int col, int i) {
     return unpack(reinterpret_cast<const uint4*>(base)[(size_t)col * half + i]);
   }
+  // The six stored binary16 values as floats, without the norm: psi = nu * h.
+  __device__ __forceinline__ static Vec3<float> load_raw(const void* base, int half, int col, int i, float* nu) {
+    const uint4 w = reinterpret_cast<const uint4*>(base)[(size_t)col * half + i];
+    *nu = __uint_as_float(w.w);
+    Vec3<float> h;
+    h.c[0].re = h2f(w.x & 0xffffu);
+    h.c[0].im = h2f(w.x >> 16);
+    h.c[1].re = h2f(w.y & 0xffffu);
+    h.c[1].im = h2f(w.y >> 16);
+    h.c[2].re = h2f(w.z & 0xffffu);
+    h.c[2].im = h2f(w.z >> 16);
+    return h;
+  }
   __device__ __forceinline__ static Vec3<float> unpack(const uint4 w) {
     const float nu = __uint_as_float(w.w);
     Vec3<float> v;

@@ -4,13 +4,14 @@
 
 namespace asq {
 
-enum VecKernel { VK_INIT = 0, VK_XR = 1, VK_P = 2 };
+enum VecKernel { VK_INIT = 0, VK_XR = 1, VK_P = 2, VK_FLUSH = 3 };
 
 struct VecArgs {
   int half;
   int nblk;
   const double* b;  // F64 right-hand sides
   double* x;        // F64 solutions
+  void* xs;         // F32 accumulator of the current reliable-update segment (nullptr: update x)
   void* r;          // iterated residual (RT tier)
   void* p;          // search directions (PT tier): two buffers, ColState::pbuf picks
   void* p_alt;

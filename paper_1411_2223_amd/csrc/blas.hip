@@ -38,6 +38,7 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const VecArgs A) {
   if (i < half) {
     const Vec3<double> b = VecF64::load(A.b, half, c, i);
     VecF64::store(A.x, half, c, i, zero3<double>());
+    if (A.xs) VecF32::store(A.xs, half, c, i, zero3<float>());
     RT::store(A.r, half, c, i, convert<typename RT::real>(b));
     PT::store(A.p, half, c, i, convert<typename PT::real>(b));
     d = norm2_d(b);
@@ -52,7 +53,7 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const VecArgs A) {
 // same fixed-order sum the scalar kernel does), so no scalar kernel sits
 // between D_eo and this update.  p is the direction the fused D_oe just wrote:
 // the buffer other than pbuf.
-template <class PT, class RT>
+template <class PT, class RT, bool XS>
 __global__ void __launch_bounds__(kBlock) update_xr_kernel(const VecArgs A) {
   const int c = blockIdx.y, sblk = blockIdx.x;
   const ColState& S = A.st[c];
@@ -67,23 +68,57 @@ __global__ void __launch_bounds__(kBlock) update_xr_kernel(const VecArgs A) {
   const void* pnew = S.pbuf ? A.p : A.p_alt;
   double d = 0;
   if (i < half) {
-    const Vec3<double> p = convert<double>(PT::load(pnew, half, c, i));
     const Vec3<rr> ap = convert<rr>(PT::load(A.Ap, half, c, i));
-    Vec3<double> x = VecF64::load(A.x, half, c, i);
     Vec3<rr> r = RT::load(A.r, half, c, i);
     const rr ar = (rr)alpha;
+    if constexpr (XS) {
+      // x_s += alpha p in FP32; flushed into the FP64 x at the next reliable update
+      const Vec3<float> p = convert<float>(PT::load(pnew, half, c, i));
+      Vec3<float> x = VecF32::load(A.xs, half, c, i);
+      const float af = (float)alpha;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        x.c[a].re = fmaR(af, p.c[a].re, x.c[a].re);
+        x.c[a].im = fmaR(af, p.c[a].im, x.c[a].im);
+      }
+      VecF32::store(A.xs, half, c, i, x);
+    } else {
+      const Vec3<double> p = convert<double>(PT::load(pnew, half, c, i));
+      Vec3<double> x = VecF64::load(A.x, half, c, i);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        x.c[a].re = __builtin_fma(alpha, p.c[a].re, x.c[a].re);
+        x.c[a].im = __builtin_fma(alpha, p.c[a].im, x.c[a].im);
+      }
+      VecF64::store(A.x, half, c, i, x);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      x.c[a].re = __builtin_fma(alpha, p.c[a].re, x.c[a].re);
-      x.c[a].im = __builtin_fma(alpha, p.c[a].im, x.c[a].im);
       r.c[a].re = fmaR(-ar, ap.c[a].re, r.c[a].re);
       r.c[a].im = fmaR(-ar, ap.c[a].im, r.c[a].im);
     }
-    VecF64::store(A.x, half, c, i, x);
     d = norm2_d(RT::store(A.r, half, c, i, r));
   }
   const double tot = block_sum(d, sh);
   if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
+}
+
+// x += x_s (FP64), x_s = 0: start of a reliable update.
+__global__ void __launch_bounds__(kBlock) flush_x_kernel(const VecArgs A) {
+  const int c = blockIdx.y, sblk = blockIdx.x;
+  if (!state_on(A.st[c], MASK_RELIABLE)) return;
+  const int half = A.half;
+  const int i = sblk * kBlock + (int)threadIdx.x;
+  if (i >= half) return;
+  const Vec3<double> xs = convert<double>(VecF32::load(A.xs, half, c, i));
+  Vec3<double> x = VecF64::load(A.x, half, c, i);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    x.c[a].re += xs.c[a].re;
+    x.c[a].im += xs.c[a].im;
+  }
+  VecF64::store(A.x, half, c, i, x);
+  VecF32::store(A.xs, half, c, i, zero3<float>());
 }
 
 // p_new = r + beta p into the buffer that is not current (the unfused form of
@@ -154,7 +189,11 @@ int launch_vec(int which, const VecArgs& a, int ncol, hipStream_t s) {
   if (which == VK_INIT) {
     init_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
   } else if (which == VK_XR) {
-    update_xr_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
+    if (a.xs) update_xr_kernel<PT, RT, true><<<grid, kBlock, 0, s>>>(a);
+    else update_xr_kernel<PT, RT, false><<<grid, kBlock, 0, s>>>(a);
+  } else if (which == VK_FLUSH) {
+    if (!a.xs) return ASQ_EINVAL;
+    flush_x_kernel<<<grid, kBlock, 0, s>>>(a);
   } else if (which == VK_P) {
     update_p_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
   } else {

@@ -62,6 +62,35 @@ __device__ __forceinline__ Vec3<typename InT::real> fetch(const DslashArgs& A, c
   }
 }
 
+// acc += sgn * (U or U^dag) psi_r(j) for one column.  Folded links carry their
+// sign (sgn = +-1 is applied by add/sub); 12-real links pass the full scale.
+// FP16 inputs keep the norm out of the product, acc += (sgn nu) (U h), so the
+// binary16 values feed the FMAs directly and the per-element rescale is saved.
+template <class Link, class InT, class RT, int R, bool FUSEP, bool ADJ>
+__device__ __forceinline__ void term(const DslashArgs& A, const Cols<InT, R>& C, int r, int c, int j,
+                                     const Mat3<typename InT::real>& U, typename InT::real scale, bool neg,
+                                     Vec3<typename InT::real>& acc, void* owner_out) {
+  using real = typename InT::real;
+  if constexpr (InT::kind == VEC_F16 && !FUSEP) {
+    float nu;
+    const Vec3<float> h = VecF16::load_raw(C.in[r], A.g.half, c, j, &nu);
+    const Vec3<float> u = ADJ ? mul_adj(U, h) : mul(U, h);
+    float sc = Link::folded ? nu : nu * scale;
+    if (neg) sc = -sc;
+    axpy3(acc, sc, u);
+  } else {
+    const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c, j);
+    if (owner_out) InT::store(owner_out, A.g.half, c, j, v);
+    const Vec3<real> u = ADJ ? mul_adj(U, v) : mul(U, v);
+    if constexpr (Link::folded) {
+      if (neg) sub3(acc, u);
+      else add3(acc, u);
+    } else {
+      axpy3(acc, neg ? -scale : scale, u);
+    }
+  }
+}
+
 // The four terms of direction MU for output site i, accumulated into R columns.
 template <class Link, class InT, class RT, int R, bool FUSEP, int MU>
 __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, int c0, const Cols<InT, R>& C,
@@ -81,9 +110,9 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
     const real e = (real)eta_sign<MU>(s);
     const real cf = (real)A.coeff_fat, cl = (real)A.coeff_long;
     sf1 = e * cf;
-    sb1 = -e * cf;
+    sb1 = e * cf;
     sf3 = e * cl;
-    sb3 = -e * cl;
+    sb3 = e * cl;
     if constexpr (MU == 3) {
       if (s.t == g.T - 1) sf1 = -sf1;
       if (s.t == 0) sb1 = -sb1;
@@ -95,42 +124,29 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
     const Mat3<real> U = Link::load(A.links, half, p, MU, i);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (C.on[r]) {
-        const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c0 + r, jf1);
-        if constexpr (Link::folded) add3(acc[r], mul(U, v));
-        else axpy3(acc[r], sf1, mul(U, v));
-      }
+      if (C.on[r]) term<Link, InT, RT, R, FUSEP, false>(A, C, r, c0 + r, jf1, U, sf1, false, acc[r], nullptr);
   }
   {
     const Mat3<real> U = Link::load(A.links, half, 1 - p, MU, jb1);
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (C.on[r]) {
-        const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c0 + r, jb1);
-        if constexpr (FUSEP && MU == 0) InT::store(C.pnew[r], half, c0 + r, jb1, v);  // owner of site x - x^
-        if constexpr (Link::folded) sub3(acc[r], mul_adj(U, v));
-        else axpy3(acc[r], sb1, mul_adj(U, v));
+        // owner of site x - x^: writes the new direction there (fused update only)
+        void* own = (FUSEP && MU == 0) ? C.pnew[r] : nullptr;
+        term<Link, InT, RT, R, FUSEP, true>(A, C, r, c0 + r, jb1, U, sb1, true, acc[r], own);
       }
   }
   {
     const Mat3<real> U = Link::load(A.links, half, p, 4 + MU, i);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (C.on[r]) {
-        const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c0 + r, jf3);
-        if constexpr (Link::folded) add3(acc[r], mul(U, v));
-        else axpy3(acc[r], sf3, mul(U, v));
-      }
+      if (C.on[r]) term<Link, InT, RT, R, FUSEP, false>(A, C, r, c0 + r, jf3, U, sf3, false, acc[r], nullptr);
   }
   {
     const Mat3<real> U = Link::load(A.links, half, 1 - p, 4 + MU, jb3);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (C.on[r]) {
-        const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c0 + r, jb3);
-        if constexpr (Link::folded) sub3(acc[r], mul_adj(U, v));
-        else axpy3(acc[r], sb3, mul_adj(U, v));
-      }
+      if (C.on[r]) term<Link, InT, RT, R, FUSEP, true>(A, C, r, c0 + r, jb3, U, sb3, true, acc[r], nullptr);
   }
 }
 

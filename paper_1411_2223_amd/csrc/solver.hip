@@ -68,6 +68,7 @@ size_t batch_bytes(const asq_gauge* g, int ncol, int mode, bool with_bx) {
   n += align_up((size_t)ncol * half * vec_site_bytes(rt), 256);      // r
   n += 4 * align_up((size_t)ncol * half * vec_site_bytes(pt), 256);  // p, p_alt, Ap, t
   if (mode != ASQ_MODE_F64) n += align_up((size_t)ncol * half * 48, 256);  // t64
+  if (mode != ASQ_MODE_F64) n += align_up((size_t)ncol * half * 24, 256);  // x_s
   if (with_bx) n += 2 * align_up((size_t)ncol * half * 48, 256);         // b, x
   return n;
 }
@@ -98,6 +99,7 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
   B.Ap = take((size_t)ncol * half * vec_site_bytes(pt));
   B.t = take((size_t)ncol * half * vec_site_bytes(pt));
   B.t64 = mode == ASQ_MODE_F64 ? B.t : take((size_t)ncol * half * 48);
+  B.xs = mode == ASQ_MODE_F64 ? nullptr : take((size_t)ncol * half * 24);
   if (b == nullptr) {
     B.b = (double*)take((size_t)ncol * half * 48);
     B.x = (double*)take((size_t)ncol * half * 48);
@@ -156,6 +158,7 @@ static VecArgs vargs(const Batch& B, int c0) {
   // column offset c0: shift every per-column pointer
   v.b = B.b + (size_t)c0 * half * 6;
   v.x = B.x + (size_t)c0 * half * 6;
+  v.xs = B.xs ? (char*)B.xs + (size_t)c0 * half * 24 : nullptr;
   v.r = (char*)B.r + (size_t)c0 * half * vec_site_bytes(B.rt);
   v.p = (char*)B.p + (size_t)c0 * half * vec_site_bytes(B.pt);
   v.p_alt = (char*)B.p_alt + (size_t)c0 * half * vec_site_bytes(B.pt);
@@ -216,6 +219,13 @@ int enqueue_iteration(const Batch& B, hipStream_t s) {
 int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s) {
   const Gauge_t* g = B.g;
   const void* L = g->links[LINK_F64_R18];
+  if (B.xs) {
+    // fold the segment's FP32 accumulator into the FP64 solution first
+    VecArgs v = vargs(B, 0);
+    v.st = B.st;
+    const int rc0 = launch_vec_kernel(VK_FLUSH, B.pt, B.rt, v, B.ncol, s);
+    if (rc0) return rc0;
+  }
   DslashArgs d1 = dargs(B, 1, B.x, B.t64, mask);
   d1.links = L;
   int rc = launch_dslash(LINK_F64_R18, VEC_F64, VEC_F64, EPI_PLAIN, B.rt64_plain, d1, s);
