@@ -42,6 +42,24 @@ LINK_BYTES = {"f64": 144, "f32": 72, "f32r12": 48, "f16r12": 24}
 VEC_BYTES = {"f64": 48, "f32": 24, "f16": 16}
 
 
+def measured_traffic(kernel_key, launches_bytes_alg):
+    """HBM bytes per launch from the committed counter run, or None when the Dslash
+    sources changed since the counters were taken (or none were taken)."""
+    from paper_1411_2223_amd import profiling
+
+    try:
+        with open(profiling.COUNTERS_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha") != profiling.kernel_source_hash():
+        return None
+    k = c.get("kernels", {}).get(kernel_key)
+    if not k:
+        return None
+    return 1024.0 * (c["fetch_factor"] * k["FETCH_SIZE_KiB"] + c["write_factor"] * k["WRITE_SIZE_KiB"])
+
+
 def dslash_bytes_per_site(link, vec, nrhs):
     """Algorithmic bytes of one half-Dslash per output site: 16 links, nrhs input and output vectors."""
     return 16 * LINK_BYTES[link] + nrhs * 2 * VEC_BYTES[vec]
@@ -241,7 +259,8 @@ def run_single(args, asq, torch):
         "dslash_f64_gbs": f64_gbs,
         "copy_probe_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(f"{tprec}_{link}_1rhs", bytes_launch),
                      "kernel": f"dslash_kernel {tprec} vectors, {link} 18-real links, 1 RHS",
                      "us_per_launch": dt * 1e6, "bytes_per_launch": bytes_launch},
         "paper_context": {"cg_gflops_titan_black_mixed_own_code": 46.48, "cg_gflops_titan_black_quda": 97.86,
