@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound on the oracle sample")
     ap.add_argument("--dslash-launches", type=int, default=200)
     ap.add_argument("--requests", type=int, default=600, help="serving: measured requests (after warm-up)")
+    ap.add_argument("--rate", type=float, default=50.0, help="serving: Poisson arrival rate (requests/s)")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="three-level: skip the host FP64 oracle residual of every column")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch the Dslash tiers and a 1 GiB copy probe (for hardware-counter runs)")
     return ap.parse_args()
@@ -344,8 +347,18 @@ def run_threelevel(args, asq, torch):
     dt1 = time_dslash(asq, g, "f16", 1, 10, stream)
     gbs1 = dslash_bytes_per_site("f16r12", "f16", 1) * half / dt1 / 1e9
     log(f"dslash f16 r12 x{ncol}: {dt * 1e6:.0f} us, {gbs:.0f} GB/s, {tf:.1f} TFLOP/s; 1 RHS {gbs1:.0f} GB/s")
+    oracle_resid = None
+    if not args.no_oracle_check:
+        import oracle
+
+        fat, lng = synth.make_gauge(dims, w["eps"], synth.gauge_seed(w["index"]))
+        b = synth.make_sources(dims, ncol, synth.source_seed(w["index"]))
+        xs = asq.vec_from_device(x, ncol, half, "f64")
+        oracle_resid = [oracle.true_residual(dims, fat, lng, mass, b[c], xs[c]) for c in range(ncol)]
+        log(f"oracle FP64 true residual of every column: max {max(oracle_resid):.3e}")
     out = {"metric": METRIC, "workload": "threelevel_48x48x48x96", "value": secs * 1e3, "unit": "ms to 1e-10",
            "columns": ncol, "mass": mass, "iters_max": max(its), "true_resid_max": max(res),
+           "oracle_true_resid_max": max(oracle_resid) if oracle_resid else None,
            "reliable_updates": max(s["reliable_updates"] for s in last.stats),
            "dslash_12rhs": {"us": dt * 1e6, "GBps": gbs, "TFLOPs": tf, "frac_hbm": gbs / PEAK_HBM_GBS,
                             "frac_fp32_alu": tf / PEAK_FP32_TFLOPS},
@@ -357,7 +370,8 @@ def run_serving(args, asq, torch):
     """Poisson stream of solves on four resident lattices (continuous batching, HBM budget)."""
     lattices = synth.SERVING_LATTICES
     n_warm = 50
-    trace = synth.serving_trace(args.requests + n_warm)
+    trace = synth.serving_trace(args.requests + n_warm, rate=args.rate)
+    mode = "mixed16" if args.mode == "mixed32" else args.mode
     gauges, pools = [], []
     for k, dims in enumerate(lattices):
         fat, lng = synth.make_gauge(dims, 0.3, synth.BASE_SEED + 10 + k)
@@ -381,7 +395,7 @@ def run_serving(args, asq, torch):
             n = q["nrhs"]
             b = pools[lat][:n]
             x = torch.empty_like(b)
-            t = srv.submit(gids[lat], [q["mass"]] * n, b, x, mode="mixed32")
+            t = srv.submit(gids[lat], [q["mass"]] * n, b, x, mode=mode)
             pending[t] = (k, n, x)
             k += 1
         for t in list(pending):
@@ -406,6 +420,7 @@ def run_serving(args, asq, torch):
             per_lat["x".join(map(str, lattices[i]))] = {"n": len(li), "p50_ms": float(np.percentile(li, 50) * 1e3),
                                                         "p99_ms": float(np.percentile(li, 99) * 1e3)}
     out = {"metric": METRIC, "workload": "serving", "value": len(meas) / wall, "unit": "requests/s",
+           "rate": args.rate, "mode": mode, "stable": len(meas) / wall >= 0.95 * len(meas) / span,
            "requests": len(meas), "rhs_solves": rhs, "wall_s": wall, "offered_requests_per_s": len(meas) / span,
            "achieved_rhs_per_s": rhs / wall, "p50_latency_ms": float(np.percentile(lats, 50) * 1e3),
            "p99_latency_ms": float(np.percentile(lats, 99) * 1e3), "failed": len(bad),

@@ -130,3 +130,28 @@ def test_cg_batched_full_size_f16(asq):
     r = oracle_resid_cols(dims, fat, lng, masses, b, x)
     print(f"batched f16 iters={[s['iters'] for s in res.stats]} resid max={r.max():.3e}", flush=True)
     assert res.rc == 0 and np.all(r <= TOL)
+
+
+def test_three_level_mid_size(asq):
+    # the three-level tier (FP16-with-norm vectors, 16-bit 12-real links, FP32 residual, FP64 x) at
+    # 16^3 x 32 with the eps = 0.2 links and m = 0.005 of the 48^3 x 96 workload, 12 columns
+    dims, m, eps = (16, 16, 16, 32), 0.005, 0.2
+    fat, lng = gauge_arrays(dims, eps, 77)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
+    b = synth.make_sources(dims, 12, 78)
+    x, res = _solve(asq, g, [m] * 12, b, "mixed16", maxiter=20000)
+    r = oracle_resid_cols(dims, fat, lng, [m] * 12, b, x)
+    print(f"three-level 16^3x32 iters={[s['iters'] for s in res.stats]} resid max={r.max():.3e}", flush=True)
+    assert res.rc == 0 and np.all(r <= TOL)
+
+
+def test_recon12_mixed32_matches_tolerance(asq):
+    # FP32 12-real links in the iteration (reconstructed in-kernel), FP64 18-real for the residual
+    dims = (8, 6, 4, 12)
+    fat, lng = gauge_arrays(dims, 0.2, 6)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=12)
+    b = synth.make_sources(dims, 3, 79)
+    masses = [0.01, 0.03, 0.1]
+    x, res = _solve(asq, g, masses, b, "mixed32")
+    r = oracle_resid_cols(dims, fat, lng, masses, b, x)
+    assert res.rc == 0 and np.all(r <= TOL)
