@@ -11,21 +11,20 @@ struct Batch {
   const asq_gauge* g = nullptr;
   int ncol = 0;
   int mode = 0;
-  int pt = 0, rt = 0;  // storage tiers of p/Ap/t and of r
+  int pt = 0, rt = 0;  // storage tiers of p and t, and of r
   int link = 0;        // link tier of the iterated Dslash
-  int rt_sloppy_plain = 1, rt_sloppy_xpay = 1, rt64_plain = 1, rt64_resid = 1;
-  bool fuse_p = true;  // direction update inside the D_oe gather (else its own kernel)
+  int rt_sloppy_norm = 1, rt_sloppy_update = 1, rt64_plain = 1, rt64_resid = 1;
   bool sweep = true;   // D_eo walks the lattice backwards (MALL reuse of the links)
   ColState* st = nullptr;
-  double* partials = nullptr;    // [ncol][nblk] partials of |r|^2 (update, residual, init)
-  double* partials_a = nullptr;  // [ncol][nblk] partials of <p, A p> (D_eo)
+  double* partials = nullptr;    // [ncol][nblk] partials of |r|^2 (D_eo update, residual, init)
+  double* partials_p = nullptr;  // [ncol][nblk] partials of |p|^2 (direction update)
+  double* partials_t = nullptr;  // [ncol][nblk] partials of |D_oe p|^2
   double* b = nullptr;  // F64 [ncol][3][half][2]
   double* x = nullptr;
   void* xs = nullptr;  // F32 accumulator of x between reliable updates (mixed modes)
   void* r = nullptr;
   void* p = nullptr;      // two direction buffers; ColState::pbuf selects the current one
   void* p_alt = nullptr;
-  void* Ap = nullptr;
 
   void* t = nullptr;
   void* t64 = nullptr;

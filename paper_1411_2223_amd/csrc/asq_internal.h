@@ -51,7 +51,11 @@ struct asq_gauge {
 namespace asq {
 
 // Dslash epilogues.
-enum Epi { EPI_PLAIN = 0, EPI_XPAY_DOT = 1, EPI_RESID = 2 };
+//   PLAIN   out = D in
+//   NORM    out = D in, block partials of |out|^2 (as stored)
+//   UPDATE  Ap = a y - D in in registers; r -= alpha Ap, x += alpha y; partials of |r|^2
+//   RESID   out = b - a y + D in in FP64, stored in the output tier; partials of |out|^2
+enum Epi { EPI_PLAIN = 0, EPI_NORM = 1, EPI_UPDATE = 2, EPI_RESID = 3 };
 // Column masks (read from the per-column solver state).
 enum Mask { MASK_ALL = 0, MASK_ACTIVE = 1, MASK_RELIABLE = 2 };
 
@@ -81,7 +85,7 @@ struct alignas(128) ColState {
 static_assert(sizeof(ColState) == 128, "ColState layout");
 
 // Scalar updates applied to a column from its reduced sums (see asq_reduce.h).
-enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_FINAL = 4, OP_STEP = 5 };
+enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_FINAL = 4 };
 
 struct DslashArgs {
   Geom g;
@@ -90,29 +94,28 @@ struct DslashArgs {
   int ntiles;
   const void* links;
   const void* in;       // input vector (other parity)
-  const void* in_alt;   // second p buffer: in_sel = 1 reads the column's current p
-  int in_sel;           // (in if pbuf == 0), in_sel = 2 the new one (in_alt if pbuf == 0)
-  const void* rfuse;    // fused direction update: input = r + beta * p (p = in / in_alt), the new p
-                        // is written by the owning thread into the other p buffer
-  void* out;
-  const void* y;        // XPAY / RESID: the vector multiplied by a = 4 m^2
-  const void* y_alt;    // with y_sel = 1: y is the column's new p (y if pbuf == 1, else y_alt)
+  const void* in_alt;   // second p buffer: in_sel = 1 reads the column's new direction
+  int in_sel;           // (in_alt if pbuf == 0, else in)
+  void* out;            // PLAIN / NORM / RESID output
+  const void* y;        // UPDATE / RESID: the vector multiplied by a = 4 m^2
+  const void* y_alt;    // with y_sel = 1: y is the column's new direction (y_alt if pbuf == 0)
   int y_sel;
   const double* b;      // RESID: right-hand side (F64)
-  ColState* st;         // per-column a and masks (nullptr: a = 0, all columns)
+  void* r;              // UPDATE: iterated residual (r tier), read and written
+  void* x;              // UPDATE: solution accumulator (F32 segment sum, or the F64 x in FP64 mode)
+  ColState* st;         // per-column a, alpha and masks (nullptr: all columns)
   int mask;
-  double* partials;     // [ncol][nblk] FP64 block partials (XPAY_DOT, RESID)
+  double* partials;     // [ncol][nblk] FP64 block partials (NORM, UPDATE, RESID)
   int nblk;
   double coeff_fat;     // 12-real tiers: fat / long coefficients re-applied in-kernel
   double coeff_long;
   int reverse;          // walk the lattice from the last site block to the first
 };
 
-// Launch one Dslash; link_kind / in_kind / out_kind select the template.
-// fuse_rt >= 0 selects the fused direction update with r stored in tier fuse_rt.
+// Launch one Dslash.  link_kind / in_kind select the template; out_kind is the
+// output tier (PLAIN, NORM, RESID) or the residual tier (UPDATE).
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
-                  hipStream_t s, int fuse_rt = -1);
-
+                  hipStream_t s);
 // Tuned RHS tile (columns per thread) for a Dslash configuration.
 int tuned_rtile(const asq_gauge* g, int link_kind, int in_kind, int out_kind, int epi, int ncol);
 // Time the candidate tiles once per configuration (in_buf read, out_buf scratch).

@@ -12,13 +12,6 @@
 
 namespace asq {
 
-// alpha = rr / <p, A p> exactly as the update kernel and the scalar kernel both form it.
-__device__ inline bool alpha_of(const ColState& S, double pAp, double* alpha) {
-  if (!isfinite(pAp) || !(pAp > 0)) return false;
-  *alpha = S.rr / pAp;
-  return true;
-}
-
 // Scalar update of one column from its reduced sum s (thread 0 of one block).
 __device__ inline void finalize_column(ColState& S, double s, int op) {
   const bool finite = isfinite(s);

@@ -4,7 +4,7 @@
 
 namespace asq {
 
-enum VecKernel { VK_INIT = 0, VK_XR = 1, VK_P = 2, VK_FLUSH = 3 };
+enum VecKernel { VK_INIT = 0, VK_P = 2, VK_FLUSH = 3 };
 
 struct VecArgs {
   int half;
@@ -15,10 +15,8 @@ struct VecArgs {
   void* r;          // iterated residual (RT tier)
   void* p;          // search directions (PT tier): two buffers, ColState::pbuf picks
   void* p_alt;
-  void* Ap;         // A p (PT tier)
   ColState* st;
-  double* partials;          // this kernel's partials ([ncol][nblk])
-  const double* partials_a;  // update: the D_eo <p, A p> partials
+  double* partials;  // this kernel's partials ([ncol][nblk])
 };
 
 int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hipStream_t s);

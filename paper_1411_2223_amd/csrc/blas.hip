@@ -1,11 +1,11 @@
 // blas.hip -- CG vector updates and deterministic FP64 reductions.
 //
 // Every vector kernel runs on a (site block, column) grid and writes one FP64
-// partial per block and column; the last block of a column sums the partials
-// in a fixed order and updates that column's scalars on the device (alpha,
-// beta, reliable-update and convergence decisions), so no scalar ever travels
-// to the host inside the iteration and a column's arithmetic never depends on
-// the other columns of the batch.
+// partial per block and column.  A one-block-per-column scalar kernel sums a
+// column's partials in a fixed order and updates that column's scalars on the
+// device (alpha, beta, reliable-update and convergence decisions), so no scalar
+// travels to the host inside the iteration and a column's arithmetic never
+// depends on the other columns of the batch.
 #include <math.h>
 
 #include "asq_reduce.h"
@@ -28,7 +28,7 @@ __device__ __forceinline__ Vec3<R> zero3() {
   return v;
 }
 
-// x = 0, r = b, p = b; partial |b|^2.
+// x = 0, x_s = 0, r = b, p = b (first buffer); partials of |b|^2.
 template <class PT, class RT>
 __global__ void __launch_bounds__(kBlock) init_kernel(const VecArgs A) {
   const int c = blockIdx.y, sblk = blockIdx.x;
@@ -48,57 +48,32 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const VecArgs A) {
   if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
 }
 
-// x += alpha p (FP64); r -= alpha A p; block partials of |r|^2 of the stored r.
-// Every block forms alpha = rr / <p, A p> itself from the D_eo partials (the
-// same fixed-order sum the scalar kernel does), so no scalar kernel sits
-// between D_eo and this update.  p is the direction the fused D_oe just wrote:
-// the buffer other than pbuf.
-template <class PT, class RT, bool XS>
-__global__ void __launch_bounds__(kBlock) update_xr_kernel(const VecArgs A) {
+// p_new = r + beta p into the buffer that is not current; partials of |p_new|^2
+// (as stored), which give <p, A p> = a |p|^2 + |D_oe p|^2 without a dot with A p.
+template <class PT, class RT>
+__global__ void __launch_bounds__(kBlock) update_p_kernel(const VecArgs A) {
   const int c = blockIdx.y, sblk = blockIdx.x;
   const ColState& S = A.st[c];
   if (!state_on(S, MASK_ACTIVE)) return;
-  __shared__ double sh[kBlock / 64 + 1];
-  const double pAp = column_sum(A.partials_a + (size_t)c * A.nblk, A.nblk, sh);
-  double alpha;
-  if (!alpha_of(S, pAp, &alpha)) return;  // uniform; the scalar kernel flags the column
-  using rr = typename RT::real;
+  using pr = typename PT::real;
   const int half = A.half;
   const int i = sblk * kBlock + (int)threadIdx.x;
-  const void* pnew = S.pbuf ? A.p : A.p_alt;
   double d = 0;
   if (i < half) {
-    const Vec3<rr> ap = convert<rr>(PT::load(A.Ap, half, c, i));
-    Vec3<rr> r = RT::load(A.r, half, c, i);
-    const rr ar = (rr)alpha;
-    if constexpr (XS) {
-      // x_s += alpha p in FP32; flushed into the FP64 x at the next reliable update
-      const Vec3<float> p = convert<float>(PT::load(pnew, half, c, i));
-      Vec3<float> x = VecF32::load(A.xs, half, c, i);
-      const float af = (float)alpha;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        x.c[a].re = fmaR(af, p.c[a].re, x.c[a].re);
-        x.c[a].im = fmaR(af, p.c[a].im, x.c[a].im);
-      }
-      VecF32::store(A.xs, half, c, i, x);
-    } else {
-      const Vec3<double> p = convert<double>(PT::load(pnew, half, c, i));
-      Vec3<double> x = VecF64::load(A.x, half, c, i);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        x.c[a].re = __builtin_fma(alpha, p.c[a].re, x.c[a].re);
-        x.c[a].im = __builtin_fma(alpha, p.c[a].im, x.c[a].im);
-      }
-      VecF64::store(A.x, half, c, i, x);
-    }
+    const void* pcur = S.pbuf ? A.p_alt : A.p;
+    void* pnew = S.pbuf ? A.p : A.p_alt;
+    const pr beta = (pr)S.beta;
+    const Vec3<pr> r = convert<pr>(RT::load(A.r, half, c, i));
+    const Vec3<pr> p = PT::load(pcur, half, c, i);
+    Vec3<pr> v;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      r.c[a].re = fmaR(-ar, ap.c[a].re, r.c[a].re);
-      r.c[a].im = fmaR(-ar, ap.c[a].im, r.c[a].im);
+      v.c[a].re = fmaR(beta, p.c[a].re, r.c[a].re);
+      v.c[a].im = fmaR(beta, p.c[a].im, r.c[a].im);
     }
-    d = norm2_d(RT::store(A.r, half, c, i, r));
+    d = norm2_d(PT::store(pnew, half, c, i, v));
   }
+  __shared__ double sh[kBlock / 64];
   const double tot = block_sum(d, sh);
   if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
 }
@@ -121,49 +96,20 @@ __global__ void __launch_bounds__(kBlock) flush_x_kernel(const VecArgs A) {
   VecF32::store(A.xs, half, c, i, zero3<float>());
 }
 
-// p_new = r + beta p into the buffer that is not current (the unfused form of
-// the direction update; the fused form lives in the D_oe gather).
-template <class PT, class RT>
-__global__ void __launch_bounds__(kBlock) update_p_kernel(const VecArgs A) {
-  const int c = blockIdx.y, sblk = blockIdx.x;
-  const ColState& S = A.st[c];
-  if (!state_on(S, MASK_ACTIVE)) return;
-  using pr = typename PT::real;
-  const int half = A.half;
-  const int i = sblk * kBlock + (int)threadIdx.x;
-  if (i >= half) return;
-  const void* pcur = S.pbuf ? A.p_alt : A.p;
-  void* pnew = S.pbuf ? A.p : A.p_alt;
-  const pr beta = (pr)S.beta;
-  const Vec3<pr> r = convert<pr>(RT::load(A.r, half, c, i));
-  const Vec3<pr> p = PT::load(pcur, half, c, i);
-  Vec3<pr> v;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    v.c[a].re = fmaR(beta, p.c[a].re, r.c[a].re);
-    v.c[a].im = fmaR(beta, p.c[a].im, r.c[a].im);
-  }
-  PT::store(pnew, half, c, i, v);
-}
-
 // Scalar kernel: fixed-order sums of a column's partials, then its update.
-// OP_STEP closes a CG iteration (alpha from the D_eo partials, then beta,
-// triggers and the p buffer swap from the |r|^2 partials); OP_INIT, OP_RU and
-// OP_FINAL use the one sum in `pb`.
+// OP_ALPHA: <p, A p> = a * sum(pa) + sum(pb) (|p|^2 and |D_oe p|^2 partials);
+// OP_BETA, OP_RU, OP_INIT, OP_FINAL: the one sum of pb.
 __global__ void __launch_bounds__(kBlock) reduce_kernel(ColState* st, const double* pa, const double* pb, int nblk,
                                                         int op) {
   const int c = blockIdx.x;
   ColState& S = st[c];
-  const int mask = op == OP_STEP ? MASK_ACTIVE : (op == OP_RU ? MASK_RELIABLE : MASK_ALL);
+  const int mask = (op == OP_ALPHA || op == OP_BETA) ? MASK_ACTIVE : (op == OP_RU ? MASK_RELIABLE : MASK_ALL);
   if (!state_on(S, mask)) return;
   __shared__ double sh[kBlock / 64 + 1];
   const double s = column_sum(pb + (size_t)c * nblk, nblk, sh);
-  if (op == OP_STEP) {
-    const double pAp = column_sum(pa + (size_t)c * nblk, nblk, sh);
-    if (threadIdx.x == 0) {
-      finalize_column(S, pAp, OP_ALPHA);
-      finalize_column(S, s, OP_BETA);
-    }
+  if (op == OP_ALPHA) {
+    const double pp = column_sum(pa + (size_t)c * nblk, nblk, sh);
+    if (threadIdx.x == 0) finalize_column(S, S.a * pp + s, OP_ALPHA);
   } else if (threadIdx.x == 0) {
     finalize_column(S, s, op);
   }
@@ -188,14 +134,11 @@ int launch_vec(int which, const VecArgs& a, int ncol, hipStream_t s) {
   const dim3 grid((unsigned)a.nblk, (unsigned)ncol);
   if (which == VK_INIT) {
     init_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
-  } else if (which == VK_XR) {
-    if (a.xs) update_xr_kernel<PT, RT, true><<<grid, kBlock, 0, s>>>(a);
-    else update_xr_kernel<PT, RT, false><<<grid, kBlock, 0, s>>>(a);
+  } else if (which == VK_P) {
+    update_p_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
   } else if (which == VK_FLUSH) {
     if (!a.xs) return ASQ_EINVAL;
     flush_x_kernel<<<grid, kBlock, 0, s>>>(a);
-  } else if (which == VK_P) {
-    update_p_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
   } else {
     return ASQ_EINVAL;
   }
@@ -212,7 +155,7 @@ int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hip
 }
 
 int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s) {
-  if (op == OP_ALPHA || op == OP_BETA) return ASQ_EINVAL;
+  if (op == OP_ALPHA && !pa) return ASQ_EINVAL;
   reduce_kernel<<<(unsigned)ncol, kBlock, 0, s>>>(st, pa, pb, nblk, op);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }

@@ -10,15 +10,14 @@
 // of arrays, so each wavefront load is one contiguous run; neighbour vectors
 // come through L2 (blocks are remapped so each XCD walks a contiguous slab).
 //
-// Fused CG work:
-//   FUSEP        the input is the CG direction p = r + beta p_old, formed on the
-//                fly at every neighbour; the thread of site x writes the new p of
-//                its -x neighbour (each site of the other parity has exactly one
-//                such owner) into the second p buffer.
-//   EPI_PLAIN    out = D in
-//   EPI_XPAY_DOT out = a_c y - D in, block partials of Re<y, out>   (A p and <p, A p>)
-//   EPI_RESID    out = b - a_c y + D in (FP64), block partials of |out|^2 (the true
-//                residual, also stored in the output tier as the new iterated r)
+// Epilogues (the CG arithmetic that touches the same output sites):
+//   EPI_PLAIN   out = D in
+//   EPI_NORM    out = D in and block partials of |out|^2: with t = D_oe p this
+//               gives <p, A p> = a |p|^2 + |t|^2, since D_eo = -D_oe^dag
+//   EPI_UPDATE  Ap = a p - D_eo t kept in registers; r -= alpha Ap and
+//               x += alpha p at the site; block partials of |r|^2
+//   EPI_RESID   out = b - a y + D in in FP64 (the true residual), stored in the
+//               output tier as the new iterated r; block partials of |out|^2
 #include "asq_reduce.h"
 
 namespace asq {
@@ -32,55 +31,23 @@ __device__ __forceinline__ bool col_on(const DslashArgs& A, int c) {
   return s.active != 0 && s.want_ru != 0;
 }
 
-template <class InT, int R>
-struct Cols {
+// acc += sgn * (U or U^dag) in_c(j) for one column.  Folded 18-real links carry
+// their sign (add or subtract); 12-real links pass their full scale.  FP16
+// inputs keep the norm out of the product, acc += (sgn nu) (U h), so the
+// binary16 values feed mixed-precision FMAs directly.
+template <class Link, class InT, bool ADJ>
+__device__ __forceinline__ void term(const void* in, int half, int c, int j, const Mat3<typename InT::real>& U,
+                                     typename InT::real scale, bool neg, Vec3<typename InT::real>& acc) {
   using real = typename InT::real;
-  bool on[R];
-  const void* in[R];  // input (or p_old) base of each column
-  void* pnew[R];      // FUSEP: where the owner writes the new p
-  real beta[R];
-};
-
-// Neighbour vector of column r at site j, with the fused direction update.
-template <class InT, class RT, int R, bool FUSEP>
-__device__ __forceinline__ Vec3<typename InT::real> fetch(const DslashArgs& A, const Cols<InT, R>& C, int r, int c,
-                                                          int j) {
-  using real = typename InT::real;
-  const int half = A.g.half;
-  if constexpr (!FUSEP) {
-    return InT::load(C.in[r], half, c, j);
-  } else {
-    const Vec3<real> p = InT::load(C.in[r], half, c, j);
-    const Vec3<real> rv = convert<real>(RT::load(A.rfuse, half, c, j));
-    Vec3<real> v;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      v.c[a].re = fmaR(C.beta[r], p.c[a].re, rv.c[a].re);
-      v.c[a].im = fmaR(C.beta[r], p.c[a].im, rv.c[a].im);
-    }
-    return InT::quantize(v);  // exactly the value the owner stores
-  }
-}
-
-// acc += sgn * (U or U^dag) psi_r(j) for one column.  Folded links carry their
-// sign (sgn = +-1 is applied by add/sub); 12-real links pass the full scale.
-// FP16 inputs keep the norm out of the product, acc += (sgn nu) (U h), so the
-// binary16 values feed the FMAs directly and the per-element rescale is saved.
-template <class Link, class InT, class RT, int R, bool FUSEP, bool ADJ>
-__device__ __forceinline__ void term(const DslashArgs& A, const Cols<InT, R>& C, int r, int c, int j,
-                                     const Mat3<typename InT::real>& U, typename InT::real scale, bool neg,
-                                     Vec3<typename InT::real>& acc, void* owner_out) {
-  using real = typename InT::real;
-  if constexpr (InT::kind == VEC_F16 && !FUSEP) {
+  if constexpr (InT::kind == VEC_F16) {
     float nu;
-    const Vec3<float> h = VecF16::load_raw(C.in[r], A.g.half, c, j, &nu);
+    const Vec3<float> h = VecF16::load_raw(in, half, c, j, &nu);
     const Vec3<float> u = ADJ ? mul_adj(U, h) : mul(U, h);
     float sc = Link::folded ? nu : nu * scale;
     if (neg) sc = -sc;
     axpy3(acc, sc, u);
   } else {
-    const Vec3<real> v = fetch<InT, RT, R, FUSEP>(A, C, r, c, j);
-    if (owner_out) InT::store(owner_out, A.g.half, c, j, v);
+    const Vec3<real> v = InT::load(in, half, c, j);
     const Vec3<real> u = ADJ ? mul_adj(U, v) : mul(U, v);
     if constexpr (Link::folded) {
       if (neg) sub3(acc, u);
@@ -92,9 +59,9 @@ __device__ __forceinline__ void term(const DslashArgs& A, const Cols<InT, R>& C,
 }
 
 // The four terms of direction MU for output site i, accumulated into R columns.
-template <class Link, class InT, class RT, int R, bool FUSEP, int MU>
-__device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, int c0, const Cols<InT, R>& C,
-                                        Vec3<typename InT::real> (&acc)[R]) {
+template <class Link, class InT, int R, int MU>
+__device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, int c0, const bool (&on)[R],
+                                        const void* const (&in)[R], Vec3<typename InT::real> (&acc)[R]) {
   using real = typename InT::real;
   static_assert(sizeof(typename Link::real) == sizeof(real), "link and vector arithmetic must match");
   const Geom& g = A.g;
@@ -124,33 +91,34 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
     const Mat3<real> U = Link::load(A.links, half, p, MU, i);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (C.on[r]) term<Link, InT, RT, R, FUSEP, false>(A, C, r, c0 + r, jf1, U, sf1, false, acc[r], nullptr);
+      if (on[r]) term<Link, InT, false>(in[r], half, c0 + r, jf1, U, sf1, false, acc[r]);
   }
   {
     const Mat3<real> U = Link::load(A.links, half, 1 - p, MU, jb1);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (C.on[r]) {
-        // owner of site x - x^: writes the new direction there (fused update only)
-        void* own = (FUSEP && MU == 0) ? C.pnew[r] : nullptr;
-        term<Link, InT, RT, R, FUSEP, true>(A, C, r, c0 + r, jb1, U, sb1, true, acc[r], own);
-      }
+      if (on[r]) term<Link, InT, true>(in[r], half, c0 + r, jb1, U, sb1, true, acc[r]);
   }
   {
     const Mat3<real> U = Link::load(A.links, half, p, 4 + MU, i);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (C.on[r]) term<Link, InT, RT, R, FUSEP, false>(A, C, r, c0 + r, jf3, U, sf3, false, acc[r], nullptr);
+      if (on[r]) term<Link, InT, false>(in[r], half, c0 + r, jf3, U, sf3, false, acc[r]);
   }
   {
     const Mat3<real> U = Link::load(A.links, half, 1 - p, 4 + MU, jb3);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (C.on[r]) term<Link, InT, RT, R, FUSEP, true>(A, C, r, c0 + r, jb3, U, sb3, true, acc[r], nullptr);
+      if (on[r]) term<Link, InT, true>(in[r], half, c0 + r, jb3, U, sb3, true, acc[r]);
   }
 }
 
-template <class Link, class InT, class OutT, class RT, int R, int EPI, bool FUSEP>
+// The column's new direction buffer (pbuf == 0: the alternate one).
+__device__ __forceinline__ const void* pick_new(const DslashArgs& A, const void* base, const void* alt, int c) {
+  return A.st[c].pbuf ? base : alt;
+}
+
+template <class Link, class InT, class OutT, int R, int EPI>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   using real = typename InT::real;
   int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
@@ -160,18 +128,15 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   const int tile = lin % A.ntiles;  // column tiles of the same sites are neighbours in dispatch order
   const int sblk = lin / A.ntiles;
   const int c0 = tile * R;
-  Cols<InT, R> C;
+  bool on[R];
+  const void* in[R];
   bool any = false;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int c = c0 + r;
-    C.on[r] = col_on(A, c);
-    any |= C.on[r];
-    int pb = (C.on[r] && A.in_sel) ? A.st[c].pbuf : 0;
-    if (A.in_sel == 2) pb ^= 1;
-    C.in[r] = pb ? A.in_alt : A.in;
-    C.pnew[r] = const_cast<void*>(pb ? A.in : A.in_alt);
-    C.beta[r] = (FUSEP && C.on[r]) ? (real)A.st[c].beta : (real)0;
+    on[r] = col_on(A, c);
+    any |= on[r];
+    in[r] = (on[r] && A.in_sel) ? pick_new(A, A.in, A.in_alt, c) : A.in;
   }
   if (!any) return;  // uniform over the block
   const int half = A.g.half;
@@ -186,41 +151,70 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
 
   if (valid) {
     const Site s = decode(A.g, i, A.out_parity);
-    hop_dir<Link, InT, RT, R, FUSEP, 0>(A, i, s, c0, C, acc);
-    hop_dir<Link, InT, RT, R, FUSEP, 1>(A, i, s, c0, C, acc);
-    hop_dir<Link, InT, RT, R, FUSEP, 2>(A, i, s, c0, C, acc);
-    hop_dir<Link, InT, RT, R, FUSEP, 3>(A, i, s, c0, C, acc);
+    hop_dir<Link, InT, R, 0>(A, i, s, c0, on, in, acc);
+    hop_dir<Link, InT, R, 1>(A, i, s, c0, on, in, acc);
+    hop_dir<Link, InT, R, 2>(A, i, s, c0, on, in, acc);
+    hop_dir<Link, InT, R, 3>(A, i, s, c0, on, in, acc);
   }
 
   if constexpr (EPI == EPI_PLAIN) {
     if (valid) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (C.on[r]) OutT::store(A.out, half, c0 + r, i, convert<typename OutT::real>(acc[r]));
+        if (on[r]) OutT::store(A.out, half, c0 + r, i, convert<typename OutT::real>(acc[r]));
     }
   } else {
     __shared__ double sh[kBlock / 64];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (!C.on[r]) continue;  // uniform over the block
+      if (!on[r]) continue;  // uniform over the block
       const int c = c0 + r;
       double d = 0;
       if (valid) {
-        if constexpr (EPI == EPI_XPAY_DOT) {
-          // out = a y - D in;  d = Re<y, out>
-          const real a = (real)A.st[c].a;
-          const void* yb = A.y;
-          if (A.y_sel) yb = A.st[c].pbuf ? A.y : A.y_alt;
-          const Vec3<real> y = InT::load(yb, half, c, i);
-          Vec3<real> o;
+        if constexpr (EPI == EPI_NORM) {
+          d = norm2_d(OutT::store(A.out, half, c, i, convert<typename OutT::real>(acc[r])));
+        } else if constexpr (EPI == EPI_UPDATE) {
+          // OutT is the residual tier.  Ap = a p - D t; r -= alpha Ap; x += alpha p
+          using rr = typename OutT::real;
+          const ColState& S = A.st[c];
+          const void* pb = A.y_sel ? pick_new(A, A.y, A.y_alt, c) : A.y;
+          const Vec3<real> y = InT::load(pb, half, c, i);
+          const real a = (real)S.a;
+          Vec3<rr> ap;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            o.c[k].re = fmaR(a, y.c[k].re, -acc[r].c[k].re);
-            o.c[k].im = fmaR(a, y.c[k].im, -acc[r].c[k].im);
+            ap.c[k].re = (rr)fmaR(a, y.c[k].re, -acc[r].c[k].re);
+            ap.c[k].im = (rr)fmaR(a, y.c[k].im, -acc[r].c[k].im);
           }
-          // the dot uses the stored (possibly 16-bit) A p, the value the update reads back
-          const Vec3<real> os = OutT::store(A.out, half, c, i, convert<typename OutT::real>(o));
-          d = redot_d(y, os);
+          Vec3<rr> rv = OutT::load(A.r, half, c, i);
+          const rr ar = (rr)S.alpha;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            rv.c[k].re = fmaR(-ar, ap.c[k].re, rv.c[k].re);
+            rv.c[k].im = fmaR(-ar, ap.c[k].im, rv.c[k].im);
+          }
+          d = norm2_d(OutT::store(A.r, half, c, i, rv));
+          if constexpr (InT::kind == VEC_F64) {
+            // FP64 mode: x itself
+            Vec3<double> x = VecF64::load(A.x, half, c, i);
+            const double al = S.alpha;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              x.c[k].re = __builtin_fma(al, (double)y.c[k].re, x.c[k].re);
+              x.c[k].im = __builtin_fma(al, (double)y.c[k].im, x.c[k].im);
+            }
+            VecF64::store(A.x, half, c, i, x);
+          } else {
+            // FP32 accumulator of the reliable-update segment
+            Vec3<float> x = VecF32::load(A.x, half, c, i);
+            const float al = (float)S.alpha;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              x.c[k].re = fmaR(al, (float)y.c[k].re, x.c[k].re);
+              x.c[k].im = fmaR(al, (float)y.c[k].im, x.c[k].im);
+            }
+            VecF32::store(A.x, half, c, i, x);
+          }
         } else {
           // out = b - a y + D in  (FP64);  d = |out|^2
           const double a = A.st[c].a;
@@ -243,66 +237,63 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   }
 }
 
-template <class Link, class InT, class OutT, class RT, int R, int EPI, bool FUSEP>
+template <class Link, class InT, class OutT, int R, int EPI>
 int go(const DslashArgs& a0, hipStream_t s) {
   DslashArgs a = a0;
   a.ntiles = (a.ncol + R - 1) / R;
   const long nb = (long)a.nblk * a.ntiles;
   if (nb <= 0) return ASQ_OK;
   if (nb >= (1L << 31)) return ASQ_EINVAL;
-  dslash_kernel<Link, InT, OutT, RT, R, EPI, FUSEP><<<(unsigned)nb, kBlock, 0, s>>>(a);
+  dslash_kernel<Link, InT, OutT, R, EPI><<<(unsigned)nb, kBlock, 0, s>>>(a);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }
 
-template <class Link, class InT, class OutT, class RT, int EPI, bool FUSEP>
+template <class Link, class InT, class OutT, int EPI>
 int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
   switch (rtile) {
-    case 1: return go<Link, InT, OutT, RT, 1, EPI, FUSEP>(a, s);
-    case 2: return go<Link, InT, OutT, RT, 2, EPI, FUSEP>(a, s);
-    case 4: return go<Link, InT, OutT, RT, 4, EPI, FUSEP>(a, s);
-    case 8: return go<Link, InT, OutT, RT, 8, EPI, FUSEP>(a, s);
+    case 1: return go<Link, InT, OutT, 1, EPI>(a, s);
+    case 2: return go<Link, InT, OutT, 2, EPI>(a, s);
+    case 4: return go<Link, InT, OutT, 4, EPI>(a, s);
+    case 8: return go<Link, InT, OutT, 8, EPI>(a, s);
   }
   return ASQ_EINVAL;
 }
 
-// Iterated tiers: PLAIN (optionally with the fused direction update) and XPAY_DOT.
+// Iterated tiers: PLAIN and NORM write the input tier; UPDATE takes the residual tier.
 template <class Link, class V, class RT>
-int pick_sloppy(int epi, int rtile, const DslashArgs& a, hipStream_t s, bool fuse) {
-  if (epi == EPI_PLAIN) {
-    if (fuse) return pick_r<Link, V, V, RT, EPI_PLAIN, true>(rtile, a, s);
-    return pick_r<Link, V, V, RT, EPI_PLAIN, false>(rtile, a, s);
-  }
-  if (epi == EPI_XPAY_DOT && !fuse) return pick_r<Link, V, V, RT, EPI_XPAY_DOT, false>(rtile, a, s);
+int pick_iter(int epi, int rtile, const DslashArgs& a, hipStream_t s) {
+  if (epi == EPI_PLAIN) return pick_r<Link, V, V, EPI_PLAIN>(rtile, a, s);
+  if (epi == EPI_NORM) return pick_r<Link, V, V, EPI_NORM>(rtile, a, s);
+  if (epi == EPI_UPDATE) return pick_r<Link, V, RT, EPI_UPDATE>(rtile, a, s);
   return ASQ_EINVAL;
 }
 
 }  // namespace
 
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
-                  hipStream_t s, int fuse_rt) {
-  const bool fuse = fuse_rt >= 0;
-  if (fuse && !a.rfuse) return ASQ_EINVAL;
+                  hipStream_t s) {
   if (link_kind == LINK_F64_R18) {
     if (in_kind != VEC_F64) return ASQ_EINVAL;
     if (epi == EPI_RESID) {
-      if (fuse) return ASQ_EINVAL;
-      if (out_kind == VEC_F64) return pick_r<LinkF64R18, VecF64, VecF64, VecF64, EPI_RESID, false>(rtile, a, s);
-      if (out_kind == VEC_F32) return pick_r<LinkF64R18, VecF64, VecF32, VecF64, EPI_RESID, false>(rtile, a, s);
+      if (out_kind == VEC_F64) return pick_r<LinkF64R18, VecF64, VecF64, EPI_RESID>(rtile, a, s);
+      if (out_kind == VEC_F32) return pick_r<LinkF64R18, VecF64, VecF32, EPI_RESID>(rtile, a, s);
       return ASQ_EINVAL;
     }
-    if (out_kind != VEC_F64 || (fuse && fuse_rt != VEC_F64)) return ASQ_EINVAL;
-    return pick_sloppy<LinkF64R18, VecF64, VecF64>(epi, rtile, a, s, fuse);
+    if (out_kind != VEC_F64) return ASQ_EINVAL;
+    return pick_iter<LinkF64R18, VecF64, VecF64>(epi, rtile, a, s);
   }
-  if (epi == EPI_RESID || in_kind != out_kind) return ASQ_EINVAL;
-  if (fuse && fuse_rt != VEC_F32) return ASQ_EINVAL;
+  if (epi == EPI_RESID) return ASQ_EINVAL;
+  // PLAIN / NORM write the input tier; UPDATE keeps r in FP32
+  const int want_out = epi == EPI_UPDATE ? VEC_F32 : in_kind;
+  if (out_kind != want_out) return ASQ_EINVAL;
   if (link_kind == LINK_F32_R18) {
-    if (in_kind == VEC_F32) return pick_sloppy<LinkF32R18, VecF32, VecF32>(epi, rtile, a, s, fuse);
-    if (in_kind == VEC_F16) return pick_sloppy<LinkF32R18, VecF16, VecF32>(epi, rtile, a, s, fuse);
+    if (in_kind == VEC_F32) return pick_iter<LinkF32R18, VecF32, VecF32>(epi, rtile, a, s);
+    if (in_kind == VEC_F16) return pick_iter<LinkF32R18, VecF16, VecF32>(epi, rtile, a, s);
   } else if (link_kind == LINK_F32_R12) {
-    if (in_kind == VEC_F32) return pick_sloppy<LinkF32R12, VecF32, VecF32>(epi, rtile, a, s, fuse);
-    if (in_kind == VEC_F16) return pick_sloppy<LinkF32R12, VecF16, VecF32>(epi, rtile, a, s, fuse);
+    if (in_kind == VEC_F32) return pick_iter<LinkF32R12, VecF32, VecF32>(epi, rtile, a, s);
+    if (in_kind == VEC_F16) return pick_iter<LinkF32R12, VecF16, VecF32>(epi, rtile, a, s);
   } else if (link_kind == LINK_I16_R12) {
-    if (in_kind == VEC_F16) return pick_sloppy<LinkI16R12, VecF16, VecF32>(epi, rtile, a, s, fuse);
+    if (in_kind == VEC_F16) return pick_iter<LinkI16R12, VecF16, VecF32>(epi, rtile, a, s);
   }
   return ASQ_EINVAL;
 }

@@ -4,17 +4,19 @@
 // that it adopts is mixed precision, section "CPS & QUDA").
 //
 // One iteration, all columns at once, all scalars on the device:
-//   t   = D_oe p                      (sloppy Dslash, odd sites)
-//   Ap  = a p - D_eo t, <p, Ap>       (sloppy Dslash with fused xpay + dot)
-//   alpha = rr / <p, Ap>              (fixed-order FP64 reduction)
-//   x  += alpha p (FP64), r -= alpha Ap, |r|^2
-//   beta = |r|^2 / rr; triggers       (fixed-order FP64 reduction)
-//   p   = r + beta p
-// Every `poll` iterations the reliable update runs for the columns that asked
-// for it: r = b - A x with the FP64 operator, which also decides convergence
-// on the true residual.  The host only polls the column flags between blocks
-// (one block ahead, so the GPU never waits on the host); a block can be
-// captured once into a hipGraph and replayed.
+//   p   = r + beta p, |p|^2            (vector kernel, into the other p buffer)
+//   t   = D_oe p, |t|^2                (sloppy Dslash)
+//   alpha = rr / (4m^2 |p|^2 + |t|^2)  (= rr / <p, A p>, since D_eo = -D_oe^dag)
+//   Ap = 4m^2 p - D_eo t in registers; r -= alpha Ap, x += alpha p, |r|^2
+//                                      (sloppy Dslash, update epilogue)
+//   beta = |r|^2 / rr; triggers; p buffer swap
+// The sums are fixed-order FP64 reductions in one-block-per-column scalar
+// kernels.  Every `poll` iterations the reliable update runs for the columns
+// that asked for it: the FP32 x accumulator is folded into the FP64 x, and
+// r = b - A x is recomputed with the FP64 operator, which also decides
+// convergence on the true residual.  The host only polls the column flags
+// between blocks (one block ahead, so the GPU never waits on the host); a
+// block can be captured once into a hipGraph and replayed.
 #include <math.h>
 #include <string.h>
 
@@ -64,9 +66,9 @@ size_t batch_bytes(const asq_gauge* g, int ncol, int mode, bool with_bx) {
   const int pt = mode_pt(mode), rt = mode_rt(mode);
   size_t n = 0;
   n += align_up((size_t)ncol * sizeof(ColState), 256);
-  n += 2 * align_up((size_t)ncol * g->nblk * sizeof(double), 256);  // partials (two sets)
+  n += 3 * align_up((size_t)ncol * g->nblk * sizeof(double), 256);  // partials (three sets)
   n += align_up((size_t)ncol * half * vec_site_bytes(rt), 256);      // r
-  n += 4 * align_up((size_t)ncol * half * vec_site_bytes(pt), 256);  // p, p_alt, Ap, t
+  n += 3 * align_up((size_t)ncol * half * vec_site_bytes(pt), 256);  // p, p_alt, t
   if (mode != ASQ_MODE_F64) n += align_up((size_t)ncol * half * 48, 256);  // t64
   if (mode != ASQ_MODE_F64) n += align_up((size_t)ncol * half * 24, 256);  // x_s
   if (with_bx) n += 2 * align_up((size_t)ncol * half * 48, 256);         // b, x
@@ -92,11 +94,11 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
   B.rt = rt;
   B.st = (ColState*)take((size_t)ncol * sizeof(ColState));
   B.partials = (double*)take((size_t)ncol * g->nblk * sizeof(double));
-  B.partials_a = (double*)take((size_t)ncol * g->nblk * sizeof(double));
+  B.partials_p = (double*)take((size_t)ncol * g->nblk * sizeof(double));
+  B.partials_t = (double*)take((size_t)ncol * g->nblk * sizeof(double));
   B.r = take((size_t)ncol * half * vec_site_bytes(rt));
   B.p = take((size_t)ncol * half * vec_site_bytes(pt));
   B.p_alt = take((size_t)ncol * half * vec_site_bytes(pt));
-  B.Ap = take((size_t)ncol * half * vec_site_bytes(pt));
   B.t = take((size_t)ncol * half * vec_site_bytes(pt));
   B.t64 = mode == ASQ_MODE_F64 ? B.t : take((size_t)ncol * half * 48);
   B.xs = mode == ASQ_MODE_F64 ? nullptr : take((size_t)ncol * half * 24);
@@ -108,7 +110,6 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
     B.x = x;
   }
   B.link = sloppy_link(g, mode);
-  B.fuse_p = env_flag("ASQ_FUSE_P", false);
   B.sweep = env_flag("ASQ_SWEEP", true);
   batch_pick_tiles(B);
   return ASQ_OK;
@@ -116,8 +117,8 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
 
 void batch_pick_tiles(Batch& B) {
   const asq_gauge* g = B.g;
-  B.rt_sloppy_xpay = tuned_rtile(g, B.link, B.pt, B.pt, EPI_XPAY_DOT, B.ncol);
-  B.rt_sloppy_plain = tuned_rtile(g, B.link, B.pt, B.pt, EPI_PLAIN, B.ncol);
+  B.rt_sloppy_norm = tuned_rtile(g, B.link, B.pt, B.pt, EPI_NORM, B.ncol);
+  B.rt_sloppy_update = tuned_rtile(g, B.link, B.pt, B.rt, EPI_UPDATE, B.ncol);
   B.rt64_plain = tuned_rtile(g, LINK_F64_R18, VEC_F64, VEC_F64, EPI_PLAIN, B.ncol);
   B.rt64_resid = tuned_rtile(g, LINK_F64_R18, VEC_F64, B.rt, EPI_RESID, B.ncol);
 }
@@ -162,8 +163,6 @@ static VecArgs vargs(const Batch& B, int c0) {
   v.r = (char*)B.r + (size_t)c0 * half * vec_site_bytes(B.rt);
   v.p = (char*)B.p + (size_t)c0 * half * vec_site_bytes(B.pt);
   v.p_alt = (char*)B.p_alt + (size_t)c0 * half * vec_site_bytes(B.pt);
-  v.partials_a = B.partials_a + (size_t)c0 * B.g->nblk;
-  v.Ap = (char*)B.Ap + (size_t)c0 * half * vec_site_bytes(B.pt);
   v.st = B.st + c0;
   v.partials = B.partials + (size_t)c0 * B.g->nblk;
   return v;
@@ -179,39 +178,35 @@ int enqueue_init(const Batch& B, int c0, int n, hipStream_t s) {
 int enqueue_iteration(const Batch& B, hipStream_t s) {
   const Gauge_t* g = B.g;
   const void* L = g->links[B.link];
+  // p_new = r + beta p, partials of |p_new|^2
   VecArgs v = vargs(B, 0);
-  int rc;
+  v.partials = B.partials_p;
+  int rc = launch_vec_kernel(VK_P, B.pt, B.rt, v, B.ncol, s);
+  if (rc) return rc;
+  // t = D_oe p_new, partials of |t|^2
   DslashArgs d1 = dargs(B, 1, B.p, B.t, MASK_ACTIVE);
   d1.links = L;
   d1.in_alt = B.p_alt;
-  if (B.fuse_p) {
-    // t = D_oe p with p = r + beta p_old formed in the gather (new p -> the other buffer)
-    d1.in_sel = 1;
-    d1.rfuse = B.r;
-    rc = launch_dslash(B.link, B.pt, B.pt, EPI_PLAIN, B.rt_sloppy_plain, d1, s, B.rt);
-  } else {
-    // p_new = r + beta p, then t = D_oe p_new
-    rc = launch_vec_kernel(VK_P, B.pt, B.rt, v, B.ncol, s);
-    if (rc) return rc;
-    d1.in_sel = 2;
-    rc = launch_dslash(B.link, B.pt, B.pt, EPI_PLAIN, B.rt_sloppy_plain, d1, s);
-  }
+  d1.in_sel = 1;
+  d1.partials = B.partials_t;
+  rc = launch_dslash(B.link, B.pt, B.pt, EPI_NORM, B.rt_sloppy_norm, d1, s);
   if (rc) return rc;
-  // Ap = a p - D_eo t, partials of <p, Ap>
-  DslashArgs d2 = dargs(B, 0, B.t, B.Ap, MASK_ACTIVE);
+  // alpha = rr / (a |p|^2 + |t|^2)
+  rc = launch_reduce(OP_ALPHA, B.st, B.partials_p, B.partials_t, g->nblk, B.ncol, s);
+  if (rc) return rc;
+  // Ap = a p - D_eo t; r -= alpha Ap; x += alpha p; partials of |r|^2 (backward sweep)
+  DslashArgs d2 = dargs(B, 0, B.t, nullptr, MASK_ACTIVE);
   d2.links = L;
   d2.y = B.p;
   d2.y_alt = B.p_alt;
   d2.y_sel = 1;
-  d2.partials = B.partials_a;
+  d2.r = B.r;
+  d2.x = B.xs ? B.xs : (void*)B.x;
   d2.reverse = B.sweep ? 1 : 0;
-  rc = launch_dslash(B.link, B.pt, B.pt, EPI_XPAY_DOT, B.rt_sloppy_xpay, d2, s);
+  rc = launch_dslash(B.link, B.pt, B.rt, EPI_UPDATE, B.rt_sloppy_update, d2, s);
   if (rc) return rc;
-  // alpha; x += alpha p, r -= alpha Ap, partials of |r|^2
-  rc = launch_vec_kernel(VK_XR, B.pt, B.rt, v, B.ncol, s);
-  if (rc) return rc;
-  // alpha, beta, triggers, p buffer swap
-  return launch_reduce(OP_STEP, B.st, B.partials_a, B.partials, g->nblk, B.ncol, s);
+  // beta, triggers, p buffer swap
+  return launch_reduce(OP_BETA, B.st, nullptr, B.partials, g->nblk, B.ncol, s);
 }
 
 // r = b - A x with FP64 links and vectors for the columns that asked for it,

@@ -75,6 +75,8 @@ def test_same_alone_and_in_the_mix(asq, max_cols, max_streams):
         li, masses, b = reqs[k]
         dims, fat, lng = arrays[li]
         assert rc == 0 and all(s["converged"] for s in stats) and latency > 0
+        print(f"request {k}: iters {[s['iters'] for s in stats]} resid {[s['true_resid'] for s in stats]}", flush=True)
+        assert all(0 < s["true_resid"] <= 1e-10 for s in stats)
         xm = asq.vec_from_device(x, len(masses), gauges[li].half, "f64")
         r = oracle_resid_cols(dims, fat, lng, masses, b, xm)
         assert np.all(r <= 1e-10)
