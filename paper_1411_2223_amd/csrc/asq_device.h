@@ -311,6 +311,7 @@ enum VecKind { VEC_F64 = 0, VEC_F32 = 1, VEC_F16 = 2 };
 
 struct VecF64 {
   using real = double;
+  using raw = Vec3<double>;
   static constexpr int kind = VEC_F64;
   __device__ __forceinline__ static Vec3<double> load(const void* base, int half, int col, int i) {
     const double2* q = reinterpret_cast<const double2*>(base) + (size_t)col * 3 * half + i;
@@ -335,6 +336,7 @@ struct VecF64 {
 
 struct VecF32 {
   using real = float;
+  using raw = Vec3<float>;
   static constexpr int kind = VEC_F32;
   __device__ __forceinline__ static Vec3<float> load(const void* base, int half, int col, int i) {
     const float2* q = reinterpret_cast<const float2*>(base) + (size_t)col * 3 * half + i;
@@ -358,7 +360,22 @@ struct VecF32 {
 
 struct VecF16 {
   using real = float;
+  using raw = uint4;
   static constexpr int kind = VEC_F16;
+  __device__ __forceinline__ static uint4 load_rec(const void* base, int half, int col, int i) {
+    return reinterpret_cast<const uint4*>(base)[(size_t)col * half + i];
+  }
+  // The six stored binary16 values as floats (without the norm) of a record.
+  __device__ __forceinline__ static Vec3<float> halves(const uint4 w) {
+    Vec3<float> h;
+    h.c[0].re = h2f(w.x & 0xffffu);
+    h.c[0].im = h2f(w.x >> 16);
+    h.c[1].re = h2f(w.y & 0xffffu);
+    h.c[1].im = h2f(w.y >> 16);
+    h.c[2].re = h2f(w.z & 0xffffu);
+    h.c[2].im = h2f(w.z >> 16);
+    return h;
+  }
   __device__ __forceinline__ static float h2f(unsigned short u) {
     return __half2float(__ushort_as_half(u));
   }

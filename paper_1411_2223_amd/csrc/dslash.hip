@@ -31,24 +31,31 @@ __device__ __forceinline__ bool col_on(const DslashArgs& A, int c) {
   return s.active != 0 && s.want_ru != 0;
 }
 
-// acc += sgn * (U or U^dag) in_c(j) for one column.  Folded 18-real links carry
-// their sign (add or subtract); 12-real links pass their full scale.  FP16
-// inputs keep the norm out of the product, acc += (sgn nu) (U h), so the
-// binary16 values feed mixed-precision FMAs directly.
+// Raw neighbour record of one column: FP16 keeps the 16-byte record (halves and
+// norm), the other tiers the colour vector.
+template <class InT>
+__device__ __forceinline__ typename InT::raw fetch(const void* in, int half, int c, int j) {
+  if constexpr (InT::kind == VEC_F16) return VecF16::load_rec(in, half, c, j);
+  else return InT::load(in, half, c, j);
+}
+
+// acc += sgn * (U or U^dag) v for one column.  Folded 18-real links carry their
+// sign (add or subtract); 12-real links pass their full scale.  FP16 records
+// keep the norm out of the product, acc += (sgn nu) (U h), so the binary16
+// values feed mixed-precision FMAs directly.
 template <class Link, class InT, bool ADJ>
-__device__ __forceinline__ void term(const void* in, int half, int c, int j, const Mat3<typename InT::real>& U,
+__device__ __forceinline__ void term(const typename InT::raw& w, const Mat3<typename InT::real>& U,
                                      typename InT::real scale, bool neg, Vec3<typename InT::real>& acc) {
   using real = typename InT::real;
   if constexpr (InT::kind == VEC_F16) {
-    float nu;
-    const Vec3<float> h = VecF16::load_raw(in, half, c, j, &nu);
+    const float nu = __uint_as_float(w.w);
+    const Vec3<float> h = VecF16::halves(w);
     const Vec3<float> u = ADJ ? mul_adj(U, h) : mul(U, h);
     float sc = Link::folded ? nu : nu * scale;
     if (neg) sc = -sc;
     axpy3(acc, sc, u);
   } else {
-    const Vec3<real> v = InT::load(in, half, c, j);
-    const Vec3<real> u = ADJ ? mul_adj(U, v) : mul(U, v);
+    const Vec3<real> u = ADJ ? mul_adj(U, w) : mul(U, w);
     if constexpr (Link::folded) {
       if (neg) sub3(acc, u);
       else add3(acc, u);
@@ -58,10 +65,28 @@ __device__ __forceinline__ void term(const void* in, int half, int c, int j, con
   }
 }
 
+// One link term for R columns: all R neighbour loads are issued together
+// (columns past the batch read its last column, so no branch is needed), then
+// each active column accumulates under its own uniform branch.
+template <class Link, class InT, int R, bool ADJ>
+__device__ __forceinline__ void link_term(const DslashArgs& A, int p, int slot, int site, int j, int half,
+                                          const bool (&on)[R], const int (&col)[R], const void* const (&in)[R],
+                                          typename InT::real scale, bool neg, Vec3<typename InT::real> (&acc)[R]) {
+  using real = typename InT::real;
+  const Mat3<real> U = Link::load(A.links, half, p, slot, site);
+  typename InT::raw w[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) w[r] = fetch<InT>(in[r], half, col[r], j);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (on[r]) term<Link, InT, ADJ>(w[r], U, scale, neg, acc[r]);
+}
+
 // The four terms of direction MU for output site i, accumulated into R columns.
 template <class Link, class InT, int R, int MU>
-__device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, int c0, const bool (&on)[R],
-                                        const void* const (&in)[R], Vec3<typename InT::real> (&acc)[R]) {
+__device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, const bool (&on)[R],
+                                        const int (&col)[R], const void* const (&in)[R],
+                                        Vec3<typename InT::real> (&acc)[R]) {
   using real = typename InT::real;
   static_assert(sizeof(typename Link::real) == sizeof(real), "link and vector arithmetic must match");
   const Geom& g = A.g;
@@ -87,30 +112,10 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
       if (s.t < 3) sb3 = -sb3;
     }
   }
-  {
-    const Mat3<real> U = Link::load(A.links, half, p, MU, i);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (on[r]) term<Link, InT, false>(in[r], half, c0 + r, jf1, U, sf1, false, acc[r]);
-  }
-  {
-    const Mat3<real> U = Link::load(A.links, half, 1 - p, MU, jb1);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (on[r]) term<Link, InT, true>(in[r], half, c0 + r, jb1, U, sb1, true, acc[r]);
-  }
-  {
-    const Mat3<real> U = Link::load(A.links, half, p, 4 + MU, i);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (on[r]) term<Link, InT, false>(in[r], half, c0 + r, jf3, U, sf3, false, acc[r]);
-  }
-  {
-    const Mat3<real> U = Link::load(A.links, half, 1 - p, 4 + MU, jb3);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (on[r]) term<Link, InT, true>(in[r], half, c0 + r, jb3, U, sb3, true, acc[r]);
-  }
+  link_term<Link, InT, R, false>(A, p, MU, i, jf1, half, on, col, in, sf1, false, acc);
+  link_term<Link, InT, R, true>(A, 1 - p, MU, jb1, jb1, half, on, col, in, sb1, true, acc);
+  link_term<Link, InT, R, false>(A, p, 4 + MU, i, jf3, half, on, col, in, sf3, false, acc);
+  link_term<Link, InT, R, true>(A, 1 - p, 4 + MU, jb3, jb3, half, on, col, in, sb3, true, acc);
 }
 
 // The column's new direction buffer (pbuf == 0: the alternate one).
@@ -129,6 +134,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   const int sblk = lin / A.ntiles;
   const int c0 = tile * R;
   bool on[R];
+  int col[R];
   const void* in[R];
   bool any = false;
 #pragma unroll
@@ -136,6 +142,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     const int c = c0 + r;
     on[r] = col_on(A, c);
     any |= on[r];
+    col[r] = c < A.ncol ? c : A.ncol - 1;  // in-bounds column for the unconditional loads
     in[r] = (on[r] && A.in_sel) ? pick_new(A, A.in, A.in_alt, c) : A.in;
   }
   if (!any) return;  // uniform over the block
@@ -151,10 +158,10 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
 
   if (valid) {
     const Site s = decode(A.g, i, A.out_parity);
-    hop_dir<Link, InT, R, 0>(A, i, s, c0, on, in, acc);
-    hop_dir<Link, InT, R, 1>(A, i, s, c0, on, in, acc);
-    hop_dir<Link, InT, R, 2>(A, i, s, c0, on, in, acc);
-    hop_dir<Link, InT, R, 3>(A, i, s, c0, on, in, acc);
+    hop_dir<Link, InT, R, 0>(A, i, s, on, col, in, acc);
+    hop_dir<Link, InT, R, 1>(A, i, s, on, col, in, acc);
+    hop_dir<Link, InT, R, 2>(A, i, s, on, col, in, acc);
+    hop_dir<Link, InT, R, 3>(A, i, s, on, col, in, acc);
   }
 
   if constexpr (EPI == EPI_PLAIN) {
