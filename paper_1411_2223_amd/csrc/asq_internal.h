@@ -116,7 +116,11 @@ struct DslashArgs {
 // output tier (PLAIN, NORM, RESID) or the residual tier (UPDATE).
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
                   hipStream_t s);
-// Tuned RHS tile (columns per thread) for a Dslash configuration.
+// Launch variant code: columns per thread (1, 2, 4, 8) | kPipeBit for the
+// software-pipelined hop loop.
+constexpr int kPipeBit = 0x100;
+
+// Tuned launch variant for a Dslash configuration.
 int tuned_rtile(const asq_gauge* g, int link_kind, int in_kind, int out_kind, int epi, int ncol);
 // Time the candidate tiles once per configuration (in_buf read, out_buf scratch).
 int tune_dslash(const asq_gauge* g, int link_kind, int in_kind, int ncol, const void* in_buf, void* out_buf,

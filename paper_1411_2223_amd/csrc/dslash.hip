@@ -118,12 +118,70 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
   link_term<Link, InT, R, true>(A, 1 - p, 4 + MU, jb3, jb3, half, on, col, in, sb3, true, acc);
 }
 
+// Software-pipelined form of the 16 terms: the link and the R neighbour records
+// of term K+1 are loaded before the arithmetic of term K, so each wave keeps
+// loads in flight while it computes (two stages of registers).
+template <class Link, class InT, int R>
+struct Stage {
+  Mat3<typename InT::real> U;
+  typename InT::raw w[R];
+};
+
+template <int K>
+struct TermK {
+  static constexpr int MU = K / 4;
+  static constexpr int kind = K % 4;  // +1, -1, +3, -3 hops
+  static constexpr int hop = kind == 0 ? 1 : (kind == 1 ? -1 : (kind == 2 ? 3 : -3));
+  static constexpr int slot = (kind < 2 ? 0 : 4) + MU;
+  static constexpr bool back = (kind & 1) != 0;
+};
+
+template <class Link, class InT, int R, int K>
+__device__ __forceinline__ void stage_load(const DslashArgs& A, int i, const Site& s, const int (&col)[R],
+                                           const void* const (&in)[R], Stage<Link, InT, R>& st) {
+  using T = TermK<K>;
+  const int half = A.g.half;
+  const int p = A.out_parity;
+  const int j = neighbour<T::MU>(A.g, i, s, T::hop);
+  st.U = Link::load(A.links, half, T::back ? 1 - p : p, T::slot, T::back ? j : i);
+#pragma unroll
+  for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, col[r], j);
+}
+
+template <class Link, class InT, int R, int K>
+__device__ __forceinline__ void stage_compute(const DslashArgs& A, const Site& s, const bool (&on)[R],
+                                              const Stage<Link, InT, R>& st, Vec3<typename InT::real> (&acc)[R]) {
+  using T = TermK<K>;
+  using real = typename InT::real;
+  real sc = 1;
+  if constexpr (!Link::folded) {
+    sc = (real)eta_sign<T::MU>(s) * (real)(T::kind < 2 ? A.coeff_fat : A.coeff_long);
+    if constexpr (T::MU == 3) {
+      const int t = s.t, Tn = A.g.T;
+      const bool flip = T::kind == 0 ? (t == Tn - 1) : T::kind == 1 ? (t == 0) : T::kind == 2 ? (t >= Tn - 3) : (t < 3);
+      if (flip) sc = -sc;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (on[r]) term<Link, InT, T::back>(st.w[r], st.U, sc, T::back, acc[r]);
+}
+
+template <class Link, class InT, int R, int K>
+__device__ __forceinline__ void pipe_run(const DslashArgs& A, int i, const Site& s, const bool (&on)[R],
+                                         const int (&col)[R], const void* const (&in)[R],
+                                         Stage<Link, InT, R> (&st)[2], Vec3<typename InT::real> (&acc)[R]) {
+  if constexpr (K + 1 < 16) stage_load<Link, InT, R, K + 1>(A, i, s, col, in, st[(K + 1) & 1]);
+  stage_compute<Link, InT, R, K>(A, s, on, st[K & 1], acc);
+  if constexpr (K + 1 < 16) pipe_run<Link, InT, R, K + 1>(A, i, s, on, col, in, st, acc);
+}
+
 // The column's new direction buffer (pbuf == 0: the alternate one).
 __device__ __forceinline__ const void* pick_new(const DslashArgs& A, const void* base, const void* alt, int c) {
   return A.st[c].pbuf ? base : alt;
 }
 
-template <class Link, class InT, class OutT, int R, int EPI>
+template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   using real = typename InT::real;
   int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
@@ -158,10 +216,16 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
 
   if (valid) {
     const Site s = decode(A.g, i, A.out_parity);
-    hop_dir<Link, InT, R, 0>(A, i, s, on, col, in, acc);
-    hop_dir<Link, InT, R, 1>(A, i, s, on, col, in, acc);
-    hop_dir<Link, InT, R, 2>(A, i, s, on, col, in, acc);
-    hop_dir<Link, InT, R, 3>(A, i, s, on, col, in, acc);
+    if constexpr (PIPE) {
+      Stage<Link, InT, R> st[2];
+      stage_load<Link, InT, R, 0>(A, i, s, col, in, st[0]);
+      pipe_run<Link, InT, R, 0>(A, i, s, on, col, in, st, acc);
+    } else {
+      hop_dir<Link, InT, R, 0>(A, i, s, on, col, in, acc);
+      hop_dir<Link, InT, R, 1>(A, i, s, on, col, in, acc);
+      hop_dir<Link, InT, R, 2>(A, i, s, on, col, in, acc);
+      hop_dir<Link, InT, R, 3>(A, i, s, on, col, in, acc);
+    }
   }
 
   if constexpr (EPI == EPI_PLAIN) {
@@ -244,24 +308,27 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   }
 }
 
-template <class Link, class InT, class OutT, int R, int EPI>
+template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
 int go(const DslashArgs& a0, hipStream_t s) {
   DslashArgs a = a0;
   a.ntiles = (a.ncol + R - 1) / R;
   const long nb = (long)a.nblk * a.ntiles;
   if (nb <= 0) return ASQ_OK;
   if (nb >= (1L << 31)) return ASQ_EINVAL;
-  dslash_kernel<Link, InT, OutT, R, EPI><<<(unsigned)nb, kBlock, 0, s>>>(a);
+  dslash_kernel<Link, InT, OutT, R, EPI, PIPE><<<(unsigned)nb, kBlock, 0, s>>>(a);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }
 
+// rtile encodes the launch variant: columns per thread in the low byte, the
+// software-pipelined form in bit 8 (see tuned_rtile).
 template <class Link, class InT, class OutT, int EPI>
 int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
-  switch (rtile) {
-    case 1: return go<Link, InT, OutT, 1, EPI>(a, s);
-    case 2: return go<Link, InT, OutT, 2, EPI>(a, s);
-    case 4: return go<Link, InT, OutT, 4, EPI>(a, s);
-    case 8: return go<Link, InT, OutT, 8, EPI>(a, s);
+  const bool pipe = (rtile & kPipeBit) != 0;
+  switch (rtile & 0xff) {
+    case 1: return pipe ? go<Link, InT, OutT, 1, EPI, true>(a, s) : go<Link, InT, OutT, 1, EPI, false>(a, s);
+    case 2: return pipe ? go<Link, InT, OutT, 2, EPI, true>(a, s) : go<Link, InT, OutT, 2, EPI, false>(a, s);
+    case 4: return pipe ? go<Link, InT, OutT, 4, EPI, true>(a, s) : go<Link, InT, OutT, 4, EPI, false>(a, s);
+    case 8: return pipe ? go<Link, InT, OutT, 8, EPI, true>(a, s) : go<Link, InT, OutT, 8, EPI, false>(a, s);
   }
   return ASQ_EINVAL;
 }

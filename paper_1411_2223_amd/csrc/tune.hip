@@ -89,7 +89,7 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     if (g_cache.count(kp)) return ASQ_OK;
   }
   int best = default_rtile(link, ncol);
-  if (tuning_on() && ncol > 1) {
+  if (tuning_on()) {
     DslashArgs a;
     memset(&a, 0, sizeof(a));
     a.g = g->geom;
@@ -106,9 +106,10 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     ASQ_HIP_TRY(hipEventCreate(&e0));
     ASQ_HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    const int cands[4] = {1, 2, 4, 8};
+    const int cands[8] = {1, 2, 4, 8, 1 | kPipeBit, 2 | kPipeBit, 4 | kPipeBit, 8 | kPipeBit};
     for (int r : cands) {
-      if (r > 1 && r > 2 * ncol) continue;
+      const int cols = r & 0xff;
+      if (cols > 1 && cols > 2 * ncol) continue;
       if (launch_dslash(link, in, in, EPI_PLAIN, r, a, s)) continue;  // warm-up
       hipEventRecord(e0, s);
       for (int k = 0; k < 3; ++k) launch_dslash(link, in, in, EPI_PLAIN, r, a, s);
