@@ -109,7 +109,7 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     const int cands[8] = {1, 2, 4, 8, 1 | kPipeBit, 2 | kPipeBit, 4 | kPipeBit, 8 | kPipeBit};
     for (int r : cands) {
       const int cols = r & 0xff;
-      if (cols > 1 && cols > 2 * ncol) continue;
+      if (cols > 1 && cols > ncol) continue;  // a wider tile than the batch only wastes lanes
       if (launch_dslash(link, in, in, EPI_PLAIN, r, a, s)) continue;  // warm-up
       hipEventRecord(e0, s);
       for (int k = 0; k < 3; ++k) launch_dslash(link, in, in, EPI_PLAIN, r, a, s);
