@@ -7,6 +7,9 @@ namespace asq {
 
 using Gauge_t = asq_gauge;
 
+// Widest batch whose D_eo launch forms alpha itself instead of a scalar launch.
+constexpr int kFoldAlphaCols = 2;
+
 struct Batch {
   const asq_gauge* g = nullptr;
   int ncol = 0;
@@ -15,6 +18,7 @@ struct Batch {
   int link = 0;        // link tier of the iterated Dslash
   int rt_sloppy_norm = 1, rt_sloppy_update = 1, rt64_plain = 1, rt64_resid = 1;
   bool sweep = true;   // D_eo walks the lattice backwards (MALL reuse of the links)
+  bool fold_alpha = false;  // D_eo forms alpha itself (few columns): no scalar launch between the Dslashes
   ColState* st = nullptr;
   double* partials = nullptr;    // [ncol][nblk] partials of |r|^2 (D_eo update, residual, init)
   double* partials_p = nullptr;  // [ncol][nblk] partials of |p|^2 (direction update)

@@ -107,6 +107,8 @@ struct DslashArgs {
   int mask;
   double* partials;     // [ncol][nblk] FP64 block partials (NORM, UPDATE, RESID)
   int nblk;
+  const double* apa;    // UPDATE, when set: every block forms alpha = rr / (a sum(apa) + sum(apb))
+  const double* apb;    // from the [ncol][nblk] partials of |p|^2 and |D_oe p|^2 itself
   double coeff_fat;     // 12-real tiers: fat / long coefficients re-applied in-kernel
   double coeff_long;
   int reverse;          // walk the lattice from the last site block to the first

@@ -92,11 +92,27 @@ __device__ inline void finalize_column(ColState& S, double s, int op) {
   }
 }
 
-// Fixed-order sum of partials[0..nblk) over the block; valid in every thread.
-// sh: kBlock/64 + 1 doubles of LDS.
-__device__ inline double column_sum(const double* partials, int nblk, double* sh) {
+// This thread's share of a fixed-order sum of partials[0..n): elements
+// threadIdx.x, threadIdx.x + kBlock, ... added in increasing order.  Four loads
+// are issued before the adds (same order, so the same bits) to hide latency.
+__device__ inline double strided_sum(const double* partials, int n) {
   double v = 0;
-  for (int k = (int)threadIdx.x; k < nblk; k += kBlock) v += partials[k];
+  int k = (int)threadIdx.x;
+  for (; k + 3 * kBlock < n; k += 4 * kBlock) {
+    const double a = partials[k], b = partials[k + kBlock], c = partials[k + 2 * kBlock],
+                 d = partials[k + 3 * kBlock];
+    v += a;
+    v += b;
+    v += c;
+    v += d;
+  }
+  for (; k < n; k += kBlock) v += partials[k];
+  return v;
+}
+
+// Sum of v over the block, valid in every thread (the bits of block_sum).
+// sh: kBlock/64 + 1 doubles of LDS.
+__device__ inline double block_sum_all(double v, double* sh) {
   const double s = block_sum(v, sh);
   if (threadIdx.x == 0) sh[kBlock / 64] = s;
   __syncthreads();

@@ -98,17 +98,20 @@ __global__ void __launch_bounds__(kBlock) flush_x_kernel(const VecArgs A) {
 
 // Scalar kernel: fixed-order sums of a column's partials, then its update.
 // OP_ALPHA: <p, A p> = a * sum(pa) + sum(pb) (|p|^2 and |D_oe p|^2 partials);
-// OP_BETA, OP_RU, OP_INIT, OP_FINAL: the one sum of pb.
+// OP_BETA, OP_RU, OP_INIT, OP_FINAL: the one sum of pb.  The partials are
+// loaded before the column state so that the two latencies overlap.
 __global__ void __launch_bounds__(kBlock) reduce_kernel(ColState* st, const double* pa, const double* pb, int nblk,
                                                         int op) {
   const int c = blockIdx.x;
+  const double vb = strided_sum(pb + (size_t)c * nblk, nblk);
+  const double va = op == OP_ALPHA ? strided_sum(pa + (size_t)c * nblk, nblk) : 0.0;
   ColState& S = st[c];
   const int mask = (op == OP_ALPHA || op == OP_BETA) ? MASK_ACTIVE : (op == OP_RU ? MASK_RELIABLE : MASK_ALL);
   if (!state_on(S, mask)) return;
-  __shared__ double sh[kBlock / 64 + 1];
-  const double s = column_sum(pb + (size_t)c * nblk, nblk, sh);
+  __shared__ double sh[2][kBlock / 64];
+  const double s = block_sum(vb, sh[0]);
   if (op == OP_ALPHA) {
-    const double pp = column_sum(pa + (size_t)c * nblk, nblk, sh);
+    const double pp = block_sum(va, sh[1]);
     if (threadIdx.x == 0) finalize_column(S, S.a * pp + s, OP_ALPHA);
   } else if (threadIdx.x == 0) {
     finalize_column(S, s, op);

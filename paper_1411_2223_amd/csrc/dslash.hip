@@ -15,7 +15,10 @@
 //   EPI_NORM    out = D in and block partials of |out|^2: with t = D_oe p this
 //               gives <p, A p> = a |p|^2 + |t|^2, since D_eo = -D_oe^dag
 //   EPI_UPDATE  Ap = a p - D_eo t kept in registers; r -= alpha Ap and
-//               x += alpha p at the site; block partials of |r|^2
+//               x += alpha p at the site; block partials of |r|^2.  With few
+//               columns every block sums the <p, A p> partials itself (same
+//               order and tree as the scalar kernel, so the same alpha) and the
+//               scalar launch between the two Dslash launches disappears
 //   EPI_RESID   out = b - a y + D in in FP64 (the true residual), stored in the
 //               output tier as the new iterated r; block partials of |out|^2
 #include "asq_reduce.h"
@@ -204,6 +207,43 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     in[r] = (on[r] && A.in_sel) ? pick_new(A, A.in, A.in_alt, c) : A.in;
   }
   if (!any) return;  // uniform over the block
+  [[maybe_unused]] double alpha[R];
+  if constexpr (EPI == EPI_UPDATE) {
+    if (A.apa) {
+      // alpha = rr / (a |p|^2 + |t|^2) from the partials of update_p and D_oe; the
+      // loads are issued here so that their latency overlaps the hop loop's start
+      __shared__ double sa[kBlock / 64 + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        alpha[r] = 0;
+        if (!on[r]) continue;  // uniform over the block
+        const int c = c0 + r;
+        const double va = strided_sum(A.apa + (size_t)c * A.nblk, A.nblk);
+        const double vb = strided_sum(A.apb + (size_t)c * A.nblk, A.nblk);
+        const double pp = block_sum_all(va, sa);
+        const double tt = block_sum_all(vb, sa);
+        ColState& S = A.st[c];
+        const double pAp = S.a * pp + tt;
+        const bool ok = isfinite(pAp) && pAp > 0;
+        if (ok) alpha[r] = S.rr / pAp;
+        on[r] = ok;  // every block takes the same decision
+        if (sblk == 0 && threadIdx.x == 0) {
+          // the record the scalar kernel would have left; no block of this
+          // launch reads these fields
+          S.pAp = pAp;
+          if (ok) {
+            S.alpha = alpha[r];
+          } else {
+            S.status = ASQ_ENAN;
+            S.active = 0;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) alpha[r] = on[r] ? A.st[c0 + r].alpha : 0.0;
+    }
+  }
   const int half = A.g.half;
   const int i = sblk * kBlock + (int)threadIdx.x;
   const bool valid = i < half;
@@ -258,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
             ap.c[k].im = (rr)fmaR(a, y.c[k].im, -acc[r].c[k].im);
           }
           Vec3<rr> rv = OutT::load(A.r, half, c, i);
-          const rr ar = (rr)S.alpha;
+          const rr ar = (rr)alpha[r];
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
             rv.c[k].re = fmaR(-ar, ap.c[k].re, rv.c[k].re);
@@ -268,7 +308,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
           if constexpr (InT::kind == VEC_F64) {
             // FP64 mode: x itself
             Vec3<double> x = VecF64::load(A.x, half, c, i);
-            const double al = S.alpha;
+            const double al = alpha[r];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
               x.c[k].re = __builtin_fma(al, (double)y.c[k].re, x.c[k].re);
@@ -278,7 +318,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
           } else {
             // FP32 accumulator of the reliable-update segment
             Vec3<float> x = VecF32::load(A.x, half, c, i);
-            const float al = (float)S.alpha;
+            const float al = (float)alpha[r];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
               x.c[k].re = fmaR(al, (float)y.c[k].re, x.c[k].re);

@@ -111,6 +111,9 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
   }
   B.link = sloppy_link(g, mode);
   B.sweep = env_flag("ASQ_SWEEP", true);
+  // Each D_eo block re-sums 2 x nblk partials per column of its tile, which is
+  // cheap next to the Dslash only for narrow batches.
+  B.fold_alpha = ncol <= kFoldAlphaCols && env_flag("ASQ_FOLD_ALPHA", true);
   batch_pick_tiles(B);
   return ASQ_OK;
 }
@@ -191,11 +194,17 @@ int enqueue_iteration(const Batch& B, hipStream_t s) {
   d1.partials = B.partials_t;
   rc = launch_dslash(B.link, B.pt, B.pt, EPI_NORM, B.rt_sloppy_norm, d1, s);
   if (rc) return rc;
-  // alpha = rr / (a |p|^2 + |t|^2)
-  rc = launch_reduce(OP_ALPHA, B.st, B.partials_p, B.partials_t, g->nblk, B.ncol, s);
-  if (rc) return rc;
+  // alpha = rr / (a |p|^2 + |t|^2): a scalar launch, or inside D_eo
+  if (!B.fold_alpha) {
+    rc = launch_reduce(OP_ALPHA, B.st, B.partials_p, B.partials_t, g->nblk, B.ncol, s);
+    if (rc) return rc;
+  }
   // Ap = a p - D_eo t; r -= alpha Ap; x += alpha p; partials of |r|^2 (backward sweep)
   DslashArgs d2 = dargs(B, 0, B.t, nullptr, MASK_ACTIVE);
+  if (B.fold_alpha) {
+    d2.apa = B.partials_p;
+    d2.apb = B.partials_t;
+  }
   d2.links = L;
   d2.y = B.p;
   d2.y_alt = B.p_alt;
