@@ -42,13 +42,13 @@ LINK_BYTES = {"f64": 144, "f32": 72, "f32r12": 48, "f16r12": 24}
 VEC_BYTES = {"f64": 48, "f32": 24, "f16": 16}
 
 
-def measured_traffic(kernel_key, launches_bytes_alg):
+def measured_traffic(kernel_key, launches_bytes_alg, lattice="20x20x20x64"):
     """HBM bytes per launch from the committed counter run, or None when the Dslash
     sources changed since the counters were taken (or none were taken)."""
     from paper_1411_2223_amd import profiling
 
     try:
-        with open(profiling.COUNTERS_FILE) as f:
+        with open(profiling.counters_file(lattice)) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
@@ -76,7 +76,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound on the oracle sample")
     ap.add_argument("--dslash-launches", type=int, default=200)
-    ap.add_argument("--requests", type=int, default=600, help="serving: measured requests (after warm-up)")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: measured requests (after warm-up)")
+    ap.add_argument("--serve-warmup", type=int, default=100, help="serving: warm-up requests")
+    ap.add_argument("--serve-cols", type=int, default=32, help="serving: column slots per run")
+    ap.add_argument("--serve-streams", type=int, default=4, help="serving: concurrent runs (streams)")
     ap.add_argument("--rate", type=float, default=50.0, help="serving: Poisson arrival rate (requests/s)")
     ap.add_argument("--no-oracle-check", action="store_true",
                     help="three-level: skip the host FP64 oracle residual of every column")
@@ -144,22 +147,33 @@ def cpu_baseline(w, fat, lng, b, mass, iters_full, seconds):
     # the sample includes one extra operator application (its true residual)
     per_iter = max(dt - per_apply, 1e-9) / max(it, 1)
     t_solve = per_iter * iters_full
+    # the oracle's half-Dslash (D_oe on the source), FP64, counted like the GPU's FP64 tier
+    half = int(np.prod(dims)) // 2
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.dslash(dims, fat, lng, 1, b)
+    t_d = (time.perf_counter() - t0) / reps
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"oracle FP64 CG, first {it} of {iters_full} iterations at {dims[0]}^3x{dims[3]} "
                       f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled to the full solve",
-            "seconds_per_solve": t_solve}
+            "seconds_per_solve": t_solve,
+            "dslash_ms": t_d * 1e3,
+            "dslash_gbs_effective": dslash_bytes_per_site("f64", "f64", 1) * half / t_d / 1e9}
 
 
 def kernels_only(asq, g, dims):
-    """Fixed launches for counter collection: each Dslash tier 20 times, then the copy probe."""
+    """Fixed launches for counter collection: each 1-column Dslash tier 20 times, the
+    96-column FP16 Dslash 12 times, then the copy probe."""
     import torch
 
     half = int(np.prod(dims)) // 2
     stream = torch.cuda.Stream()
     res = {}
-    for prec, link in (("f32", "f32"), ("f64", "f64"), ("f16", "f32")):
-        dt = time_dslash(asq, g, prec, 1, 20, stream)
-        res[prec] = {"us": dt * 1e6, "alg_bytes": dslash_bytes_per_site(link, prec, 1) * half}
+    for prec, link, ncol, n in (("f32", "f32", 1, 20), ("f64", "f64", 1, 20), ("f16", "f32", 1, 20),
+                                ("f16", "f32", 96, 12)):
+        dt = time_dslash(asq, g, prec, ncol, n, stream)
+        res[f"{prec}_{ncol}"] = {"us": dt * 1e6, "alg_bytes": dslash_bytes_per_site(link, prec, ncol) * half}
     n = 1 << 30
     src = torch.empty(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -170,8 +184,33 @@ def kernels_only(asq, g, dims):
     print(json.dumps({"kernels_only": res}), flush=True)
 
 
+def kernels_only_threelevel(asq, g, dims, ncol):
+    """Fixed launches at 48^3 x 96 for counter collection: the iterated 12-column Dslash
+    (FP16-with-norm vectors, 16-bit 12-real links) 10 times and the 12-column FP64 Dslash of
+    the reliable update 5 times, then the copy probe."""
+    import torch
+
+    half = int(np.prod(dims)) // 2
+    stream = torch.cuda.Stream()
+    res = {}
+    for prec, link, n in (("f16", "f16r12", 10), ("f64", "f64", 5)):
+        dt = time_dslash(asq, g, prec, ncol, n, stream)
+        res[prec] = {"us": dt * 1e6, "alg_bytes": dslash_bytes_per_site(link, prec, ncol) * half}
+    nb = 1 << 30
+    src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        asq.check(asq.asq_copy_probe(dst.data_ptr(), src.data_ptr(), nb, asq.stream_ptr(stream)), "copy")
+    torch.cuda.synchronize()
+    res["copy"] = {"bytes_read": nb, "bytes_written": nb}
+    print(json.dumps({"kernels_only": res}), flush=True)
+
+
 def solve_series(g, masses, bd, mode, tol, steps, warmup, stream, work=None, x=None):
-    """warm-up + timed solves; returns (seconds per solve, last SolveResult)."""
+    """warm-up + timed solves; returns (seconds per solve over the whole timed region,
+    per-solve seconds, last SolveResult).
+    A solve returns once its FP64 true residual has been decided, so host clock
+    differences between consecutive solves are whole solves."""
     import torch
 
     for k in range(warmup):
@@ -180,14 +219,25 @@ def solve_series(g, masses, bd, mode, tol, steps, warmup, stream, work=None, x=N
         log(f"warmup {k}: rc={r.rc} iters={s0['iters']} ru={s0['reliable_updates']} "
             f"resid={max(s['true_resid'] for s in r.stats):.3e} {s0['seconds'] * 1e3:.1f} ms")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     last = None
+    times = []
+    t_start = time.perf_counter()
     for _ in range(steps):
+        t0 = time.perf_counter()
         last = g.solve(masses, bd, mode=mode, tol=tol, maxiter=50000, work=work, x=x, stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
         if last.rc != 0:
             raise SystemExit(f"solve failed rc={last.rc}")
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, last
+    return (time.perf_counter() - t_start) / steps, times, last
+
+
+def time_stats(times):
+    """mean, median and standard error of the mean, in ms."""
+    t = np.asarray(times) * 1e3
+    se = float(t.std(ddof=1) / np.sqrt(len(t))) if len(t) > 1 else None
+    return {"mean_ms": float(t.mean()), "median_ms": float(np.median(t)), "se_ms": se, "n": len(t)}
 
 
 # ---------------------------------------------------------------------------
@@ -209,13 +259,15 @@ def run_single(args, asq, torch):
     work = g.workspace(1, args.mode)
     x = torch.empty_like(bd)
     torch.cuda.synchronize()
-    secs, last = solve_series(g, [mass], bd, args.mode, w["tol"], args.steps, args.warmup, stream, work, x)
+    secs, times, last = solve_series(g, [mass], bd, args.mode, w["tol"], args.steps, args.warmup, stream, work,
+                                     x)
+    tst = time_stats(times)
     st = last.stats[0]
-    log(f"timed {args.steps} solves: {secs * 1e3:.2f} ms each; iters={st['iters']} ru={st['reliable_updates']} "
-        f"resid={st['true_resid']:.3e}")
+    log(f"timed {args.steps} solves: {secs * 1e3:.2f} ms each (median {tst['median_ms']:.2f}); iters={st['iters']} "
+        f"ru={st['reliable_updates']} resid={st['true_resid']:.3e}")
     # plain FP64 GPU CG at the same accuracy (speed-up reference), outside the timed region
     work64 = g.workspace(1, "f64")
-    t64, r64 = solve_series(g, [mass], bd, "f64", w["tol"], 2, 1, stream, work64, x)
+    t64, times64, r64 = solve_series(g, [mass], bd, "f64", w["tol"], 3, 1, stream, work64, x)
     log(f"f64 CG: iters={r64.stats[0]['iters']} resid={r64.stats[0]['true_resid']:.3e} {t64 * 1e3:.1f} ms")
 
     # dominant kernel: the sloppy single-RHS Dslash
@@ -251,6 +303,8 @@ def run_single(args, asq, torch):
                                f"reliable-update CG, FP32 and FP64 18-real links",
                    "global_batch": 1, "parallelism": "single GPU"},
         "time_to_solution_ms": ms,
+        "time_to_solution": tst,
+        "f64_time_to_solution": time_stats(times64),
         "iterations": iters,
         "reliable_updates": st["reliable_updates"],
         "true_resid": st["true_resid"],
@@ -294,7 +348,7 @@ def run_batched(args, asq, torch):
     work = g.workspace(ncol, mode)
     x = torch.empty_like(bd)
     steps = max(1, min(args.steps, 3))
-    secs, last = solve_series(g, masses, bd, mode, w["tol"], steps, 1, stream, work, x)
+    secs, _, last = solve_series(g, masses, bd, mode, w["tol"], steps, 1, stream, work, x)
     its = [s["iters"] for s in last.stats]
     res = [s["true_resid"] for s in last.stats]
     log(f"batched {ncol} columns: {secs:.3f} s; iters min/max {min(its)}/{max(its)}; resid max {max(res):.3e}")
@@ -330,13 +384,16 @@ def run_threelevel(args, asq, torch):
     log(f"gauge generated in {time.perf_counter() - t0:.0f} s")
     g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
     del fat, lng
+    if args.kernels_only:
+        kernels_only_threelevel(asq, g, dims, ncol)
+        return
     b = synth.make_sources(dims, ncol, synth.source_seed(w["index"]))
     stream = torch.cuda.Stream()
     bd = asq.vec_to_device(b, "f64")
     del b
     work = g.workspace(ncol, "mixed16")
     x = torch.empty_like(bd)
-    secs, last = solve_series(g, [mass] * ncol, bd, "mixed16", w["tol"], 1, 1, stream, work, x)
+    secs, _, last = solve_series(g, [mass] * ncol, bd, "mixed16", w["tol"], 1, 1, stream, work, x)
     its = [s["iters"] for s in last.stats]
     res = [s["true_resid"] for s in last.stats]
     log(f"three-level {ncol} columns: {secs:.3f} s; iters {max(its)}; resid max {max(res):.3e}")
@@ -356,12 +413,17 @@ def run_threelevel(args, asq, torch):
         xs = asq.vec_from_device(x, ncol, half, "f64")
         oracle_resid = [oracle.true_residual(dims, fat, lng, mass, b[c], xs[c]) for c in range(ncol)]
         log(f"oracle FP64 true residual of every column: max {max(oracle_resid):.3e}")
+    traffic = measured_traffic("f16_f16r12_12rhs", bytes_launch, lattice="48x48x48x96")
+    if traffic:
+        log(f"counter-measured traffic {traffic / 1e9:.2f} GB per launch: {traffic / dt / 1e9:.0f} GB/s")
     out = {"metric": METRIC, "workload": "threelevel_48x48x48x96", "value": secs * 1e3, "unit": "ms to 1e-10",
            "columns": ncol, "mass": mass, "iters_max": max(its), "true_resid_max": max(res),
            "oracle_true_resid_max": max(oracle_resid) if oracle_resid else None,
            "reliable_updates": max(s["reliable_updates"] for s in last.stats),
            "dslash_12rhs": {"us": dt * 1e6, "GBps": gbs, "TFLOPs": tf, "frac_hbm": gbs / PEAK_HBM_GBS,
-                            "frac_fp32_alu": tf / PEAK_FP32_TFLOPS},
+                            "frac_fp32_alu": tf / PEAK_FP32_TFLOPS, "bytes_per_launch": bytes_launch,
+                            "traffic": traffic,
+                            "traffic_GBps": traffic / dt / 1e9 if traffic else None},
            "dslash_1rhs_GBps": gbs1}
     print(json.dumps(out), flush=True)
 
@@ -369,7 +431,7 @@ def run_threelevel(args, asq, torch):
 def run_serving(args, asq, torch):
     """Poisson stream of solves on four resident lattices (continuous batching, HBM budget)."""
     lattices = synth.SERVING_LATTICES
-    n_warm = 50
+    n_warm = args.serve_warmup
     trace = synth.serving_trace(args.requests + n_warm, rate=args.rate)
     mode = "mixed16" if args.mode == "mixed32" else args.mode
     gauges, pools = [], []
@@ -379,7 +441,7 @@ def run_serving(args, asq, torch):
         pools.append(asq.vec_to_device(synth.make_sources(dims, 12, synth.BASE_SEED + 20 + k), "f64"))
         del fat, lng
     budget = 48 << 30
-    srv = asq.Server(budget, max_streams=4, max_cols=16)
+    srv = asq.Server(budget, max_streams=args.serve_streams, max_cols=args.serve_cols)
     gids = [srv.register(gg) for gg in gauges]
     torch.cuda.synchronize()
     log(f"serving {len(trace)} requests ({n_warm} warm-up), budget {budget >> 30} GiB")
@@ -420,7 +482,7 @@ def run_serving(args, asq, torch):
             per_lat["x".join(map(str, lattices[i]))] = {"n": len(li), "p50_ms": float(np.percentile(li, 50) * 1e3),
                                                         "p99_ms": float(np.percentile(li, 99) * 1e3)}
     out = {"metric": METRIC, "workload": "serving", "value": len(meas) / wall, "unit": "requests/s",
-           "rate": args.rate, "mode": mode, "stable": len(meas) / wall >= 0.95 * len(meas) / span,
+           "rate": args.rate, "mode": mode, "max_cols": args.serve_cols, "max_streams": args.serve_streams, "stable": len(meas) / wall >= 0.95 * len(meas) / span,
            "requests": len(meas), "rhs_solves": rhs, "wall_s": wall, "offered_requests_per_s": len(meas) / span,
            "achieved_rhs_per_s": rhs / wall, "p50_latency_ms": float(np.percentile(lats, 50) * 1e3),
            "p99_latency_ms": float(np.percentile(lats, 99) * 1e3), "failed": len(bad),

@@ -7,8 +7,9 @@ namespace asq {
 
 using Gauge_t = asq_gauge;
 
-// Widest batch whose D_eo launch forms alpha itself instead of a scalar launch.
-constexpr int kFoldAlphaCols = 2;
+// Widest batch whose D_eo launch forms alpha itself instead of a scalar launch
+// (its tiles are then at most kFoldAlphaMaxTile columns wide).
+constexpr int kFoldAlphaCols = kFoldAlphaMaxTile;
 
 struct Batch {
   const asq_gauge* g = nullptr;

@@ -121,6 +121,8 @@ int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, 
 // Launch variant code: columns per thread (1, 2, 4, 8) | kPipeBit for the
 // software-pipelined hop loop.
 constexpr int kPipeBit = 0x100;
+// Widest column tile whose UPDATE launch may form alpha itself (DslashArgs::apa).
+constexpr int kFoldAlphaMaxTile = 2;
 
 // Tuned launch variant for a Dslash configuration.
 int tuned_rtile(const asq_gauge* g, int link_kind, int in_kind, int out_kind, int epi, int ncol);

@@ -93,32 +93,54 @@ __device__ inline void finalize_column(ColState& S, double s, int op) {
 }
 
 // This thread's share of a fixed-order sum of partials[0..n): elements
-// threadIdx.x, threadIdx.x + kBlock, ... added in increasing order.  Four loads
-// are issued before the adds (same order, so the same bits) to hide latency.
+// threadIdx.x, threadIdx.x + kBlock, ... added in increasing order.  Every
+// group of four loads, the last partial one included, is issued before its adds
+// (the same adds in the same order, so the same bits), so a sum of n partials
+// costs about n / (4 kBlock) memory round trips instead of n / kBlock.
 __device__ inline double strided_sum(const double* partials, int n) {
   double v = 0;
-  int k = (int)threadIdx.x;
-  for (; k + 3 * kBlock < n; k += 4 * kBlock) {
-    const double a = partials[k], b = partials[k + kBlock], c = partials[k + 2 * kBlock],
-                 d = partials[k + 3 * kBlock];
+  for (int k = (int)threadIdx.x; k < n; k += 4 * kBlock) {
+    const bool h1 = k + kBlock < n, h2 = k + 2 * kBlock < n, h3 = k + 3 * kBlock < n;
+    const double a = partials[k];
+    const double b = h1 ? partials[k + kBlock] : 0.0;
+    const double c = h2 ? partials[k + 2 * kBlock] : 0.0;
+    const double d = h3 ? partials[k + 3 * kBlock] : 0.0;
     v += a;
-    v += b;
-    v += c;
-    v += d;
+    if (h1) v += b;
+    if (h2) v += c;
+    if (h3) v += d;
   }
-  for (; k < n; k += kBlock) v += partials[k];
   return v;
 }
 
-// Sum of v over the block, valid in every thread (the bits of block_sum).
-// sh: kBlock/64 + 1 doubles of LDS.
-__device__ inline double block_sum_all(double v, double* sh) {
-  const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) sh[kBlock / 64] = s;
+// Sums of u and v over the block, valid in every thread (each the bits of
+// block_sum).  sh: 2 (kBlock/64 + 1) doubles of LDS.
+__device__ inline void block_sum2_all(double& u, double& v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    u += __shfl_xor(u, o, 64);
+    v += __shfl_xor(v, o, 64);
+  }
+  constexpr int W = kBlock / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[w] = u;
+    sh[W + 1 + w] = v;
+  }
   __syncthreads();
-  const double r = sh[kBlock / 64];
+  if (threadIdx.x == 0) {
+    double su = 0, sv = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      su += sh[k];
+      sv += sh[W + 1 + k];
+    }
+    sh[W] = su;
+    sh[2 * W + 1] = sv;
+  }
   __syncthreads();
-  return r;
+  u = sh[W];
+  v = sh[2 * W + 1];
 }
 
 }  // namespace asq

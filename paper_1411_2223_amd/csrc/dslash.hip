@@ -207,21 +207,22 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     in[r] = (on[r] && A.in_sel) ? pick_new(A, A.in, A.in_alt, c) : A.in;
   }
   if (!any) return;  // uniform over the block
+  // alpha of each column for the UPDATE epilogue: formed here from the partials
+  // for the narrow tiles of small batches, read from the column state otherwise
   [[maybe_unused]] double alpha[R];
-  if constexpr (EPI == EPI_UPDATE) {
+  if constexpr (EPI == EPI_UPDATE && R <= kFoldAlphaMaxTile) {
     if (A.apa) {
       // alpha = rr / (a |p|^2 + |t|^2) from the partials of update_p and D_oe; the
       // loads are issued here so that their latency overlaps the hop loop's start
-      __shared__ double sa[kBlock / 64 + 1];
+      __shared__ double sa[2 * (kBlock / 64 + 1)];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         alpha[r] = 0;
         if (!on[r]) continue;  // uniform over the block
         const int c = c0 + r;
-        const double va = strided_sum(A.apa + (size_t)c * A.nblk, A.nblk);
-        const double vb = strided_sum(A.apb + (size_t)c * A.nblk, A.nblk);
-        const double pp = block_sum_all(va, sa);
-        const double tt = block_sum_all(vb, sa);
+        double pp = strided_sum(A.apa + (size_t)c * A.nblk, A.nblk);
+        double tt = strided_sum(A.apb + (size_t)c * A.nblk, A.nblk);
+        block_sum2_all(pp, tt, sa);
         ColState& S = A.st[c];
         const double pAp = S.a * pp + tt;
         const bool ok = isfinite(pAp) && pAp > 0;
@@ -239,9 +240,6 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
           }
         }
       }
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) alpha[r] = on[r] ? A.st[c0 + r].alpha : 0.0;
     }
   }
   const int half = A.g.half;
@@ -298,7 +296,8 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
             ap.c[k].im = (rr)fmaR(a, y.c[k].im, -acc[r].c[k].im);
           }
           Vec3<rr> rv = OutT::load(A.r, half, c, i);
-          const rr ar = (rr)alpha[r];
+          const double al64 = (R <= kFoldAlphaMaxTile && A.apa) ? alpha[r] : S.alpha;
+          const rr ar = (rr)al64;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
             rv.c[k].re = fmaR(-ar, ap.c[k].re, rv.c[k].re);
@@ -308,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
           if constexpr (InT::kind == VEC_F64) {
             // FP64 mode: x itself
             Vec3<double> x = VecF64::load(A.x, half, c, i);
-            const double al = alpha[r];
+            const double al = al64;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
               x.c[k].re = __builtin_fma(al, (double)y.c[k].re, x.c[k].re);
@@ -318,7 +317,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
           } else {
             // FP32 accumulator of the reliable-update segment
             Vec3<float> x = VecF32::load(A.x, half, c, i);
-            const float al = (float)alpha[r];
+            const float al = (float)al64;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
               x.c[k].re = fmaR(al, (float)y.c[k].re, x.c[k].re);
@@ -350,6 +349,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
 
 template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
 int go(const DslashArgs& a0, hipStream_t s) {
+  if (a0.apa && R > kFoldAlphaMaxTile) return ASQ_EINVAL;  // alpha is formed in-kernel only by narrow tiles
   DslashArgs a = a0;
   a.ntiles = (a.ncol + R - 1) / R;
   const long nb = (long)a.nblk * a.ntiles;

@@ -58,6 +58,7 @@ struct Run {
   int cap = 0;
   int poll = 8;
   bool use_graph = true;
+  bool draining = false;      // takes no new columns; destroyed once idle, freeing its stream
   size_t off = 0, bytes = 0;  // arena range
   Batch B;
   hipStream_t stream = nullptr;
@@ -188,6 +189,7 @@ Run* make_run(asq_server* S, const asq_gauge* g, const asq_cg_params& p) {
 }
 
 int free_slots(const Run* r, int n) {
+  if (r->draining) return -1;
   int runlen = 0;
   for (int c = 0; c < r->cap; ++c) {
     runlen = r->owner[c] ? 0 : runlen + 1;
@@ -302,6 +304,30 @@ bool run_idle(const Run* r) {
   return true;
 }
 
+int used_slots(const Run* r) {
+  int n = 0;
+  for (auto* o : r->owner) n += o != nullptr;
+  return n;
+}
+
+// Every stream is taken and a queued request's field has no run at all: let a
+// field that holds two or more runs give one up (the least occupied stops
+// taking columns and is destroyed once its columns are done), so that one busy
+// field cannot starve the others.  At most one run drains at a time.
+void make_room(asq_server* S, const asq_gauge* g) {
+  if ((int)S->runs.size() < S->max_streams) return;
+  std::map<const asq_gauge*, int> per_field;
+  for (auto& r : S->runs) {
+    if (r->draining) return;
+    per_field[r->g] += 1;
+  }
+  if (per_field.count(g)) return;
+  Run* victim = nullptr;
+  for (auto& r : S->runs)
+    if (per_field[r->g] >= 2 && (!victim || used_slots(r.get()) < used_slots(victim))) victim = r.get();
+  if (victim) victim->draining = true;
+}
+
 void worker_main(asq_server* S) {
   hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
@@ -316,6 +342,7 @@ void worker_main(asq_server* S) {
         if (r->g == g && r->mode == q->params.mode && r->in_flight && free_slots(r.get(), q->nrhs) >= 0)
           blocked_by_flight = true;
       if (!blocked_by_flight) placed = admit(S, q);
+      if (!placed && !blocked_by_flight) make_room(S, g);
       if (placed) it = S->queue.erase(it);
       else ++it;
     }
@@ -325,8 +352,16 @@ void worker_main(asq_server* S) {
       any_flight |= r->in_flight;
     }
     finish_copies(S);
-    // drop idle runs when others wait for arena memory or streams
-    if (!S->queue.empty()) {
+    // An idle run gives up its stream and arena range only to a queued request
+    // whose field has no run to join; otherwise it stays for its own field.
+    bool need_run = false;
+    for (Request* q : S->queue) {
+      bool has = false;
+      for (auto& r : S->runs)
+        has |= !r->draining && r->g == S->gauges[q->gauge_id] && r->mode == q->params.mode;
+      need_run |= !has;
+    }
+    if (need_run) {
       for (auto it = S->runs.begin(); it != S->runs.end();) {
         Run* r = it->get();
         if (!r->in_flight && run_idle(r)) {

@@ -4,7 +4,7 @@ measured on (a counter figure is only reported while those sources are unchanged
 
     python -m paper_1411_2223_amd.profiling stats <kernel_stats.csv> [--top N]
     python -m paper_1411_2223_amd.profiling counters <fetch counter_collection.csv> <write counter_collection.csv>
-    python -m paper_1411_2223_amd.profiling write-counters <fetch csv> <write csv> --dir <run dir>
+    python -m paper_1411_2223_amd.profiling write-counters <fetch csv> <write csv> --dir <run dir> [--lattice L]
     python -m paper_1411_2223_amd.profiling write-stats <kernel_stats.csv> <bench log> --out <md> --title T --command C
 """
 from __future__ import annotations
@@ -19,7 +19,12 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = ("csrc/dslash.hip", "csrc/asq_device.h", "csrc/asq_reduce.h", "csrc/asq_internal.h")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "dslash_counters.json")
+
+
+def counters_file(lattice: str) -> str:
+    """Counter figures of one lattice's Dslash launches (read by bench.py)."""
+    return os.path.join(ROOT, "profiles", f"dslash_counters_{lattice}.json")
+
 
 
 def kernel_source_hash() -> str:
@@ -47,41 +52,64 @@ def short_name(name: str) -> str:
     return n[:110]
 
 
-def counter_means(path: str, counter: str) -> dict:
-    """kernel name -> (dispatches, mean counter value per dispatch) from counter_collection.csv."""
+def counter_means(path: str, counter: str, by_grid: bool = False) -> dict:
+    """kernel name (or (name, grid size in threads)) -> (dispatches, mean counter value per
+    dispatch) from counter_collection.csv."""
     acc = defaultdict(list)
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name", r.get("counter_name")) != counter:
             continue
         name = r.get("Kernel_Name", r.get("kernel_name"))
-        acc[name].append(float(r.get("Counter_Value", r.get("value"))))
+        key = (name, int(r["Grid_Size"])) if by_grid else name
+        acc[key].append(float(r.get("Counter_Value", r.get("value"))))
     return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
 
 
-# Dslash launches of `bench.py --kernels-only` at 20^3 x 64 (256 000 output sites),
-# keyed like bench.py's roofline lookup: (vector tier)_(link tier)_1rhs.
+# Dslash launches of `bench.py [--workload ...] --kernels-only` per lattice, keyed
+# like bench.py's traffic lookup: (vector tier)_(link tier)_(columns)rhs ->
+# (kernel name prefix, algorithmic bytes per launch, columns).
+H20 = 20 * 20 * 20 * 64 // 2
+H48 = 48 * 48 * 48 * 96 // 2
+HALF = {"20x20x20x64": H20, "48x48x48x96": H48}
 KERNELS_ONLY = {
-    "f32_f32_1rhs": ("dslash_kernel<LinkF32R18, VecF32, VecF32, ", (16 * 72 + 2 * 24) * 256000),
-    "f64_f64_1rhs": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 2 * 48) * 256000),
-    "f16_f32_1rhs": ("dslash_kernel<LinkF32R18, VecF16, VecF16, ", (16 * 72 + 2 * 16) * 256000),
+    "20x20x20x64": {
+        "workload": "single_20x20x20x64",
+        "f32_f32_1rhs": ("dslash_kernel<LinkF32R18, VecF32, VecF32, ", (16 * 72 + 2 * 24) * H20, 1),
+        "f64_f64_1rhs": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 2 * 48) * H20, 1),
+        "f16_f32_1rhs": ("dslash_kernel<LinkF32R18, VecF16, VecF16, ", (16 * 72 + 2 * 16) * H20, 1),
+        "f16_f32_96rhs": ("dslash_kernel<LinkF32R18, VecF16, VecF16, ", (16 * 72 + 96 * 2 * 16) * H20, 96),
+    },
+    "48x48x48x96": {
+        "workload": "threelevel_48x48x48x96",
+        "f16_f16r12_12rhs": ("dslash_kernel<LinkI16R12, VecF16, VecF16, ", (16 * 24 + 12 * 2 * 16) * H48, 12),
+        "f64_f64_12rhs": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 12 * 2 * 48) * H48, 12),
+    },
 }
 COPY_KERNEL = "copy_kernel"
 COPY_BYTES = 1 << 30
 
 
-def write_counters(fetch_csv: str, write_csv: str, run_dir: str) -> None:
-    """profiles/dslash_counters.json (read by bench.py) and its Markdown summary."""
-    fetch = counter_means(fetch_csv, "FETCH_SIZE")
-    write = counter_means(write_csv, "WRITE_SIZE")
+def write_counters(fetch_csv: str, write_csv: str, run_dir: str, lattice: str = "20x20x20x64") -> None:
+    """profiles/dslash_counters_<lattice>.json (read by bench.py) and its Markdown summary."""
+    spec = KERNELS_ONLY[lattice]
+    fetch = counter_means(fetch_csv, "FETCH_SIZE", by_grid=True)
+    write = counter_means(write_csv, "WRITE_SIZE", by_grid=True)
+    nblk = (HALF[lattice] + 255) // 256
 
     def is_plain(name):
         # a plain-epilogue Dslash (template argument 5 is 0), or any other kernel
         n = short_name(name)
         return not n.startswith("dslash_kernel<") or n.split(", ")[4] == "0"
 
-    def find(prefix):
-        # the launch variant the timed loop used: the one with the most dispatches
-        hits = [k for k in fetch if short_name(k).startswith(prefix) and is_plain(k)]
+    def tile(name):
+        n = short_name(name)
+        return int(n.split(", ")[3]) if n.startswith("dslash_kernel<") else 0
+
+    def find(prefix, ncol=0):
+        # the launch variant the timed loop used: among launches over ncol columns
+        # (grid = site blocks x column tiles), the one with the most dispatches
+        hits = [(k, g) for (k, g) in fetch if short_name(k).startswith(prefix) and is_plain(k)
+                and (ncol == 0 or g == nblk * 256 * -(-ncol // tile(k)))]
         if not hits:
             raise KeyError(prefix)
         return max(hits, key=lambda k: fetch[k][0])
@@ -91,21 +119,26 @@ def write_counters(fetch_csv: str, write_csv: str, run_dir: str) -> None:
     wf = COPY_BYTES / 1024 / write[copy][1]
     h = kernel_source_hash()
     kernels = {}
-    for key, (prefix, _) in KERNELS_ONLY.items():
-        k = find(prefix)
+    keys = [k for k in spec if k != "workload"]
+    for key in keys:
+        k = find(spec[key][0], spec[key][2])
         kernels[key] = {"FETCH_SIZE_KiB": fetch[k][1], "WRITE_SIZE_KiB": write[k][1], "dispatches": fetch[k][0],
-                        "kernel": short_name(k)}
-    cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {run_dir}/fetch -o k -- python -u bench.py --kernels-only",
-            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {run_dir}/write -o k -- python -u bench.py --kernels-only",
-            f"python -m paper_1411_2223_amd.profiling write-counters {fetch_csv} {write_csv} --dir {run_dir}"]
-    out = {"kernel_source_sha": h, "lattice": "20x20x20x64", "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+                        "kernel": short_name(k[0]), "grid_threads": k[1]}
+    wl = "" if spec["workload"] == "single_20x20x20x64" else f"--workload {spec['workload']} "
+    cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {run_dir}/fetch -o k -- python -u bench.py "
+            f"{wl}--kernels-only",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {run_dir}/write -o k -- python -u bench.py "
+            f"{wl}--kernels-only",
+            f"python -m paper_1411_2223_amd.profiling write-counters {fetch_csv} {write_csv} --dir {run_dir} "
+            f"--lattice {lattice}"]
+    out = {"kernel_source_sha": h, "lattice": lattice, "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
            "calibration": {"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES,
                            "copy_FETCH_SIZE_KiB": fetch[copy][1], "copy_WRITE_SIZE_KiB": write[copy][1]},
            "commands": cmds, "kernels": kernels}
-    with open(COUNTERS_FILE, "w") as f:
+    with open(counters_file(lattice), "w") as f:
         json.dump(out, f, indent=1)
-    lines = ["# Dslash HBM traffic from hardware counters, 20^3x64, 1 column", "",
-             "Commands (repository root on the MI355X box, one counter per pass):", ""]
+    lines = [f"# Dslash HBM traffic from hardware counters, {lattice}",
+             "", "Commands (repository root on the MI355X box, one counter per pass):", ""]
     lines += ["    " + c for c in cmds]
     lines += ["", f"Kernel sources hash (`python -m paper_1411_2223_amd.profiling hash`): `{h}`", "",
               f"Calibration with the plain copy kernel (`asq_copy_probe`, {COPY_BYTES >> 30} GiB read + "
@@ -114,15 +147,18 @@ def write_counters(fetch_csv: str, write_csv: str, run_dir: str) -> None:
               f"WRITE_SIZE).", "",
               "| key | kernel (dispatches) | FETCH_SIZE KiB | WRITE_SIZE KiB | measured MB/launch | "
               "algorithmic MB/launch | measured / algorithmic |", "|---|---|---|---|---|---|---|"]
-    for key, (prefix, alg) in KERNELS_ONLY.items():
+    for key in keys:
+        alg = spec[key][1]
         v = kernels[key]
+        kernels[key]["alg_bytes"] = alg
         m = 1024 * (ff * v["FETCH_SIZE_KiB"] + wf * v["WRITE_SIZE_KiB"])
         lines.append(f"| `{key}` | `{v['kernel']}` ({v['dispatches']}) | {v['FETCH_SIZE_KiB']:.0f} | "
                      f"{v['WRITE_SIZE_KiB']:.0f} | {m / 1e6:.1f} | {alg / 1e6:.1f} | {m / alg:.3f} |")
-    lines += ["", "Algorithmic bytes per output site: 16 links (72 B FP32 / 144 B FP64 18-real) + one input and one",
-              "output colour vector (24 B FP32, 48 B FP64, 16 B FP16-with-norm); 256 000 output sites per launch.",
-              "Reads above the algorithmic count are neighbour vectors fetched into more than one XCD's L2."]
-    with open(os.path.join(ROOT, "profiles", "dslash_counters_20x20x20x64.md"), "w") as f:
+    lines += ["", "Algorithmic bytes per output site: 16 links (144 B FP64 / 72 B FP32 18-real, 24 B 16-bit",
+              "12-real) + one input and one output colour vector per column (48 B FP64, 24 B FP32, 16 B",
+              "FP16-with-norm). Reads above the algorithmic count are neighbour vectors fetched into more",
+              "than one XCD's L2."]
+    with open(os.path.join(ROOT, "profiles", f"dslash_counters_{lattice}.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
 
@@ -155,6 +191,7 @@ def main():
     s4.add_argument("fetch_csv")
     s4.add_argument("write_csv")
     s4.add_argument("--dir", required=True)
+    s4.add_argument("--lattice", default="20x20x20x64", choices=sorted(KERNELS_ONLY))
     s5 = sub.add_parser("write-stats")
     s5.add_argument("csv")
     s5.add_argument("log")
@@ -165,7 +202,7 @@ def main():
     s5.add_argument("--top", type=int, default=14)
     a = ap.parse_args()
     if a.cmd == "write-counters":
-        write_counters(a.fetch_csv, a.write_csv, a.dir)
+        write_counters(a.fetch_csv, a.write_csv, a.dir, a.lattice)
         return
     if a.cmd == "write-stats":
         write_stats(a.csv, a.log, a.out, a.title, a.command, a.top, a.note)
