@@ -130,6 +130,16 @@ int asq_gauge_destroy(asq_gauge* g);
 int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
                      void* out_dev, void* hip_stream);
 
+/* The same operator with a caller-chosen launch variant instead of the tuned
+   one (for tests that cover every variant and for tuning studies; every
+   variant computes the same result, bit for bit).  variant = cols | pipe << 8 |
+   order << 12: cols = 1, 2, 4 or 8 columns per thread; pipe = 1 for the
+   software-pipelined hop loop; order = 0 walks the column tiles of a site block
+   together, 1, 2, 3 walk tile by tile inside groups of 16, 64 or all site
+   blocks.  Returns ASQ_EINVAL for any other code. */
+int asqtad_dslash_eo_variant(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
+                             void* out_dev, int variant, void* hip_stream);
+
 /* ---- solvers --------------------------------------------------------------- */
 
 /* Device workspace bytes cg_solve / cg_solve_batch need for nrhs columns. */

@@ -64,6 +64,8 @@ _SIGS = {
                                         ctypes.POINTER(_vp)]),
     "asq_gauge_destroy": (ctypes.c_int, [_vp]),
     "asqtad_dslash_eo": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    "asqtad_dslash_eo_variant": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                                ctypes.c_int, _vp]),
     "asq_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int]),
     "cg_solve": (ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t,
                                 ctypes.POINTER(asq_cg_params), ctypes.POINTER(asq_cg_stats), _vp]),
@@ -85,6 +87,17 @@ _SIGS = {
 EXPORTS = tuple(_SIGS)
 
 _lib = None
+
+
+def variant_code(cols: int, pipe: bool = False, order: int = 0) -> int:
+    """Launch variant of asqtad_dslash_eo_variant: columns per thread, pipelined hop
+    loop, block order (0 tiles of a site block adjacent; 1, 2, 3 tile by tile in
+    groups of 16, 64 or all site blocks)."""
+    return int(cols) | (0x100 if pipe else 0) | (int(order) << 12)
+
+
+# Every launch variant the library builds: (cols, pipe, order).
+VARIANTS_ALL = [(c, p, o) for o in (0, 1, 2, 3) for p in (False, True) for c in (1, 2, 4, 8)]
 
 
 def load():
@@ -243,14 +256,20 @@ class Gauge:
         except Exception:
             pass
 
-    def dslash(self, out_parity, vin, prec="f64", nrhs=1, out=None, stream=None):
-        """out = D_{out_parity <- other} vin on device tensors in the library layout."""
+    def dslash(self, out_parity, vin, prec="f64", nrhs=1, out=None, stream=None, variant=None):
+        """out = D_{out_parity <- other} vin on device tensors in the library layout, with the
+        tuned launch variant or the given one (see variant_code)."""
         torch = _torch()
         if out is None:
             out = torch.empty_like(vin)
-        rc = asqtad_dslash_eo(self.handle, int(out_parity), PRECS[prec], int(nrhs), vin.data_ptr(), out.data_ptr(),
-                              stream_ptr(stream))
-        check(rc, "asqtad_dslash_eo")
+        if variant is None:
+            rc = asqtad_dslash_eo(self.handle, int(out_parity), PRECS[prec], int(nrhs), vin.data_ptr(),
+                                  out.data_ptr(), stream_ptr(stream))
+            check(rc, "asqtad_dslash_eo")
+        else:
+            rc = asqtad_dslash_eo_variant(self.handle, int(out_parity), PRECS[prec], int(nrhs), vin.data_ptr(),
+                                          out.data_ptr(), int(variant), stream_ptr(stream))
+            check(rc, "asqtad_dslash_eo_variant")
         return out
 
     def workspace(self, nrhs, mode="mixed32"):

@@ -109,6 +109,7 @@ struct DslashArgs {
   int nblk;
   const double* apa;    // UPDATE, when set: every block forms alpha = rr / (a sum(apa) + sum(apb))
   const double* apb;    // from the [ncol][nblk] partials of |p|^2 and |D_oe p|^2 itself
+  int sgroup;           // block order: 0 site block by site block, else tile by tile in groups of sgroup
   double coeff_fat;     // 12-real tiers: fat / long coefficients re-applied in-kernel
   double coeff_long;
   int reverse;          // walk the lattice from the last site block to the first
@@ -118,9 +119,24 @@ struct DslashArgs {
 // output tier (PLAIN, NORM, RESID) or the residual tier (UPDATE).
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
                   hipStream_t s);
-// Launch variant code: columns per thread (1, 2, 4, 8) | kPipeBit for the
-// software-pipelined hop loop.
+// The same, one function per link tier (one translation unit each).
+int launch_dslash_f64(int out_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
+int launch_dslash_f32r18(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
+int launch_dslash_f32r12(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
+int launch_dslash_i16r12(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
+// Launch variant code: columns per thread (1, 2, 4, 8) in the low byte,
+// kPipeBit for the software-pipelined hop loop, and the block order << kOrderShift:
+// 0 the tiles of a site block adjacent; 1, 2, 3 tile by tile inside groups of
+// 16, 64 or all site blocks.
 constexpr int kPipeBit = 0x100;
+constexpr int kOrderShift = 12;
+inline int rtile_order(int rtile) { return (rtile >> kOrderShift) & 3; }
+inline int order_group(int order, int nblk) { return order == 0 ? 0 : (order == 1 ? 16 : (order == 2 ? 64 : nblk)); }
+// Whether the library builds launch variant rtile (for any link and vector tier).
+bool variant_built(int link_kind, int in_kind, int rtile);
+inline int make_rtile(int cols, bool pipe, int order) {
+  return cols | (pipe ? kPipeBit : 0) | (order << kOrderShift);
+}
 // Widest column tile whose UPDATE launch may form alpha itself (DslashArgs::apa).
 constexpr int kFoldAlphaMaxTile = 2;
 

@@ -1,414 +1,31 @@
-// dslash.hip -- the single-parity asqtad hopping term on gfx950.
-//
-//   out(x) = sum_mu eta_mu(x) [ F_mu(x) in(x+mu) - F_mu(x-mu)^dag in(x-mu)
-//                             + L_mu(x) in(x+3mu) - L_mu(x-3mu)^dag in(x-3mu) ]
-// for x of the output parity (the operator whose cost dominates the paper's
-// CG inverter; the paper gives no formula, this is the standard asqtad form).
-//
-// One thread per output site and R columns: every link is loaded once and
-// applied to R colour vectors.  Links and vectors are site-fastest structures
-// of arrays, so each wavefront load is one contiguous run; neighbour vectors
-// come through L2 (blocks are remapped so each XCD walks a contiguous slab).
-//
-// Epilogues (the CG arithmetic that touches the same output sites):
-//   EPI_PLAIN   out = D in
-//   EPI_NORM    out = D in and block partials of |out|^2: with t = D_oe p this
-//               gives <p, A p> = a |p|^2 + |t|^2, since D_eo = -D_oe^dag
-//   EPI_UPDATE  Ap = a p - D_eo t kept in registers; r -= alpha Ap and
-//               x += alpha p at the site; block partials of |r|^2.  With few
-//               columns every block sums the <p, A p> partials itself (same
-//               order and tree as the scalar kernel, so the same alpha) and the
-//               scalar launch between the two Dslash launches disappears
-//   EPI_RESID   out = b - a y + D in in FP64 (the true residual), stored in the
-//               output tier as the new iterated r; block partials of |out|^2
-#include "asq_reduce.h"
+// dslash.hip -- tier checks and dispatch of the Dslash launches (the kernels
+// are in dslash_impl.h, one translation unit per link tier).
+#include "asq_internal.h"
 
 namespace asq {
-namespace {
 
-__device__ __forceinline__ bool col_on(const DslashArgs& A, int c) {
-  if (c >= A.ncol) return false;
-  if (A.mask == MASK_ALL || A.st == nullptr) return true;
-  const ColState& s = A.st[c];
-  if (A.mask == MASK_ACTIVE) return s.active != 0 && s.frozen == 0;
-  return s.active != 0 && s.want_ru != 0;
+bool variant_built(int link_kind, int in_kind, int rtile) {
+  (void)link_kind;
+  (void)in_kind;
+  const int cols = rtile & 0xff;
+  if ((rtile & ~(0xff | kPipeBit | (3 << kOrderShift))) != 0) return false;
+  return cols == 1 || cols == 2 || cols == 4 || cols == 8;
 }
-
-// Raw neighbour record of one column: FP16 keeps the 16-byte record (halves and
-// norm), the other tiers the colour vector.
-template <class InT>
-__device__ __forceinline__ typename InT::raw fetch(const void* in, int half, int c, int j) {
-  if constexpr (InT::kind == VEC_F16) return VecF16::load_rec(in, half, c, j);
-  else return InT::load(in, half, c, j);
-}
-
-// acc += sgn * (U or U^dag) v for one column.  Folded 18-real links carry their
-// sign (add or subtract); 12-real links pass their full scale.  FP16 records
-// keep the norm out of the product, acc += (sgn nu) (U h), so the binary16
-// values feed mixed-precision FMAs directly.
-template <class Link, class InT, bool ADJ>
-__device__ __forceinline__ void term(const typename InT::raw& w, const Mat3<typename InT::real>& U,
-                                     typename InT::real scale, bool neg, Vec3<typename InT::real>& acc) {
-  using real = typename InT::real;
-  if constexpr (InT::kind == VEC_F16) {
-    const float nu = __uint_as_float(w.w);
-    const Vec3<float> h = VecF16::halves(w);
-    const Vec3<float> u = ADJ ? mul_adj(U, h) : mul(U, h);
-    float sc = Link::folded ? nu : nu * scale;
-    if (neg) sc = -sc;
-    axpy3(acc, sc, u);
-  } else {
-    const Vec3<real> u = ADJ ? mul_adj(U, w) : mul(U, w);
-    if constexpr (Link::folded) {
-      if (neg) sub3(acc, u);
-      else add3(acc, u);
-    } else {
-      axpy3(acc, neg ? -scale : scale, u);
-    }
-  }
-}
-
-// One link term for R columns: all R neighbour loads are issued together
-// (columns past the batch read its last column, so no branch is needed), then
-// each active column accumulates under its own uniform branch.
-template <class Link, class InT, int R, bool ADJ>
-__device__ __forceinline__ void link_term(const DslashArgs& A, int p, int slot, int site, int j, int half,
-                                          const bool (&on)[R], const int (&col)[R], const void* const (&in)[R],
-                                          typename InT::real scale, bool neg, Vec3<typename InT::real> (&acc)[R]) {
-  using real = typename InT::real;
-  const Mat3<real> U = Link::load(A.links, half, p, slot, site);
-  typename InT::raw w[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) w[r] = fetch<InT>(in[r], half, col[r], j);
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (on[r]) term<Link, InT, ADJ>(w[r], U, scale, neg, acc[r]);
-}
-
-// The four terms of direction MU for output site i, accumulated into R columns.
-template <class Link, class InT, int R, int MU>
-__device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& s, const bool (&on)[R],
-                                        const int (&col)[R], const void* const (&in)[R],
-                                        Vec3<typename InT::real> (&acc)[R]) {
-  using real = typename InT::real;
-  static_assert(sizeof(typename Link::real) == sizeof(real), "link and vector arithmetic must match");
-  const Geom& g = A.g;
-  const int p = A.out_parity;
-  const int half = g.half;
-  const int jf1 = neighbour<MU>(g, i, s, +1);
-  const int jb1 = neighbour<MU>(g, i, s, -1);
-  const int jf3 = neighbour<MU>(g, i, s, +3);
-  const int jb3 = neighbour<MU>(g, i, s, -3);
-  // 12-real tiers: coefficient * eta * time-boundary sign, applied to U psi.
-  real sf1 = 1, sb1 = 1, sf3 = 1, sb3 = 1;
-  if constexpr (!Link::folded) {
-    const real e = (real)eta_sign<MU>(s);
-    const real cf = (real)A.coeff_fat, cl = (real)A.coeff_long;
-    sf1 = e * cf;
-    sb1 = e * cf;
-    sf3 = e * cl;
-    sb3 = e * cl;
-    if constexpr (MU == 3) {
-      if (s.t == g.T - 1) sf1 = -sf1;
-      if (s.t == 0) sb1 = -sb1;
-      if (s.t >= g.T - 3) sf3 = -sf3;
-      if (s.t < 3) sb3 = -sb3;
-    }
-  }
-  link_term<Link, InT, R, false>(A, p, MU, i, jf1, half, on, col, in, sf1, false, acc);
-  link_term<Link, InT, R, true>(A, 1 - p, MU, jb1, jb1, half, on, col, in, sb1, true, acc);
-  link_term<Link, InT, R, false>(A, p, 4 + MU, i, jf3, half, on, col, in, sf3, false, acc);
-  link_term<Link, InT, R, true>(A, 1 - p, 4 + MU, jb3, jb3, half, on, col, in, sb3, true, acc);
-}
-
-// Software-pipelined form of the 16 terms: the link and the R neighbour records
-// of term K+1 are loaded before the arithmetic of term K, so each wave keeps
-// loads in flight while it computes (two stages of registers).
-template <class Link, class InT, int R>
-struct Stage {
-  Mat3<typename InT::real> U;
-  typename InT::raw w[R];
-};
-
-template <int K>
-struct TermK {
-  static constexpr int MU = K / 4;
-  static constexpr int kind = K % 4;  // +1, -1, +3, -3 hops
-  static constexpr int hop = kind == 0 ? 1 : (kind == 1 ? -1 : (kind == 2 ? 3 : -3));
-  static constexpr int slot = (kind < 2 ? 0 : 4) + MU;
-  static constexpr bool back = (kind & 1) != 0;
-};
-
-template <class Link, class InT, int R, int K>
-__device__ __forceinline__ void stage_load(const DslashArgs& A, int i, const Site& s, const int (&col)[R],
-                                           const void* const (&in)[R], Stage<Link, InT, R>& st) {
-  using T = TermK<K>;
-  const int half = A.g.half;
-  const int p = A.out_parity;
-  const int j = neighbour<T::MU>(A.g, i, s, T::hop);
-  st.U = Link::load(A.links, half, T::back ? 1 - p : p, T::slot, T::back ? j : i);
-#pragma unroll
-  for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, col[r], j);
-}
-
-template <class Link, class InT, int R, int K>
-__device__ __forceinline__ void stage_compute(const DslashArgs& A, const Site& s, const bool (&on)[R],
-                                              const Stage<Link, InT, R>& st, Vec3<typename InT::real> (&acc)[R]) {
-  using T = TermK<K>;
-  using real = typename InT::real;
-  real sc = 1;
-  if constexpr (!Link::folded) {
-    sc = (real)eta_sign<T::MU>(s) * (real)(T::kind < 2 ? A.coeff_fat : A.coeff_long);
-    if constexpr (T::MU == 3) {
-      const int t = s.t, Tn = A.g.T;
-      const bool flip = T::kind == 0 ? (t == Tn - 1) : T::kind == 1 ? (t == 0) : T::kind == 2 ? (t >= Tn - 3) : (t < 3);
-      if (flip) sc = -sc;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (on[r]) term<Link, InT, T::back>(st.w[r], st.U, sc, T::back, acc[r]);
-}
-
-template <class Link, class InT, int R, int K>
-__device__ __forceinline__ void pipe_run(const DslashArgs& A, int i, const Site& s, const bool (&on)[R],
-                                         const int (&col)[R], const void* const (&in)[R],
-                                         Stage<Link, InT, R> (&st)[2], Vec3<typename InT::real> (&acc)[R]) {
-  if constexpr (K + 1 < 16) stage_load<Link, InT, R, K + 1>(A, i, s, col, in, st[(K + 1) & 1]);
-  stage_compute<Link, InT, R, K>(A, s, on, st[K & 1], acc);
-  if constexpr (K + 1 < 16) pipe_run<Link, InT, R, K + 1>(A, i, s, on, col, in, st, acc);
-}
-
-// The column's new direction buffer (pbuf == 0: the alternate one).
-__device__ __forceinline__ const void* pick_new(const DslashArgs& A, const void* base, const void* alt, int c) {
-  return A.st[c].pbuf ? base : alt;
-}
-
-template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
-__global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
-  using real = typename InT::real;
-  int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  // Alternate sweeps start on the links the previous sweep read last, which the
-  // memory-side cache (MALL) still holds.
-  if (A.reverse) lin = (int)gridDim.x - 1 - lin;
-  const int tile = lin % A.ntiles;  // column tiles of the same sites are neighbours in dispatch order
-  const int sblk = lin / A.ntiles;
-  const int c0 = tile * R;
-  bool on[R];
-  int col[R];
-  const void* in[R];
-  bool any = false;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int c = c0 + r;
-    on[r] = col_on(A, c);
-    any |= on[r];
-    col[r] = c < A.ncol ? c : A.ncol - 1;  // in-bounds column for the unconditional loads
-    in[r] = (on[r] && A.in_sel) ? pick_new(A, A.in, A.in_alt, c) : A.in;
-  }
-  if (!any) return;  // uniform over the block
-  // alpha of each column for the UPDATE epilogue: formed here from the partials
-  // for the narrow tiles of small batches, read from the column state otherwise
-  [[maybe_unused]] double alpha[R];
-  if constexpr (EPI == EPI_UPDATE && R <= kFoldAlphaMaxTile) {
-    if (A.apa) {
-      // alpha = rr / (a |p|^2 + |t|^2) from the partials of update_p and D_oe; the
-      // loads are issued here so that their latency overlaps the hop loop's start
-      __shared__ double sa[2 * (kBlock / 64 + 1)];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        alpha[r] = 0;
-        if (!on[r]) continue;  // uniform over the block
-        const int c = c0 + r;
-        double pp = strided_sum(A.apa + (size_t)c * A.nblk, A.nblk);
-        double tt = strided_sum(A.apb + (size_t)c * A.nblk, A.nblk);
-        block_sum2_all(pp, tt, sa);
-        ColState& S = A.st[c];
-        const double pAp = S.a * pp + tt;
-        const bool ok = isfinite(pAp) && pAp > 0;
-        if (ok) alpha[r] = S.rr / pAp;
-        on[r] = ok;  // every block takes the same decision
-        if (sblk == 0 && threadIdx.x == 0) {
-          // the record the scalar kernel would have left; no block of this
-          // launch reads these fields
-          S.pAp = pAp;
-          if (ok) {
-            S.alpha = alpha[r];
-          } else {
-            S.status = ASQ_ENAN;
-            S.active = 0;
-          }
-        }
-      }
-    }
-  }
-  const int half = A.g.half;
-  const int i = sblk * kBlock + (int)threadIdx.x;
-  const bool valid = i < half;
-
-  Vec3<real> acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) acc[r].c[a].re = acc[r].c[a].im = 0;
-
-  if (valid) {
-    const Site s = decode(A.g, i, A.out_parity);
-    if constexpr (PIPE) {
-      Stage<Link, InT, R> st[2];
-      stage_load<Link, InT, R, 0>(A, i, s, col, in, st[0]);
-      pipe_run<Link, InT, R, 0>(A, i, s, on, col, in, st, acc);
-    } else {
-      hop_dir<Link, InT, R, 0>(A, i, s, on, col, in, acc);
-      hop_dir<Link, InT, R, 1>(A, i, s, on, col, in, acc);
-      hop_dir<Link, InT, R, 2>(A, i, s, on, col, in, acc);
-      hop_dir<Link, InT, R, 3>(A, i, s, on, col, in, acc);
-    }
-  }
-
-  if constexpr (EPI == EPI_PLAIN) {
-    if (valid) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (on[r]) OutT::store(A.out, half, c0 + r, i, convert<typename OutT::real>(acc[r]));
-    }
-  } else {
-    __shared__ double sh[kBlock / 64];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (!on[r]) continue;  // uniform over the block
-      const int c = c0 + r;
-      double d = 0;
-      if (valid) {
-        if constexpr (EPI == EPI_NORM) {
-          d = norm2_d(OutT::store(A.out, half, c, i, convert<typename OutT::real>(acc[r])));
-        } else if constexpr (EPI == EPI_UPDATE) {
-          // OutT is the residual tier.  Ap = a p - D t; r -= alpha Ap; x += alpha p
-          using rr = typename OutT::real;
-          const ColState& S = A.st[c];
-          const void* pb = A.y_sel ? pick_new(A, A.y, A.y_alt, c) : A.y;
-          const Vec3<real> y = InT::load(pb, half, c, i);
-          const real a = (real)S.a;
-          Vec3<rr> ap;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            ap.c[k].re = (rr)fmaR(a, y.c[k].re, -acc[r].c[k].re);
-            ap.c[k].im = (rr)fmaR(a, y.c[k].im, -acc[r].c[k].im);
-          }
-          Vec3<rr> rv = OutT::load(A.r, half, c, i);
-          const double al64 = (R <= kFoldAlphaMaxTile && A.apa) ? alpha[r] : S.alpha;
-          const rr ar = (rr)al64;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            rv.c[k].re = fmaR(-ar, ap.c[k].re, rv.c[k].re);
-            rv.c[k].im = fmaR(-ar, ap.c[k].im, rv.c[k].im);
-          }
-          d = norm2_d(OutT::store(A.r, half, c, i, rv));
-          if constexpr (InT::kind == VEC_F64) {
-            // FP64 mode: x itself
-            Vec3<double> x = VecF64::load(A.x, half, c, i);
-            const double al = al64;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              x.c[k].re = __builtin_fma(al, (double)y.c[k].re, x.c[k].re);
-              x.c[k].im = __builtin_fma(al, (double)y.c[k].im, x.c[k].im);
-            }
-            VecF64::store(A.x, half, c, i, x);
-          } else {
-            // FP32 accumulator of the reliable-update segment
-            Vec3<float> x = VecF32::load(A.x, half, c, i);
-            const float al = (float)al64;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              x.c[k].re = fmaR(al, (float)y.c[k].re, x.c[k].re);
-              x.c[k].im = fmaR(al, (float)y.c[k].im, x.c[k].im);
-            }
-            VecF32::store(A.x, half, c, i, x);
-          }
-        } else {
-          // out = b - a y + D in  (FP64);  d = |out|^2
-          const double a = A.st[c].a;
-          const Vec3<double> y = VecF64::load(A.y, half, c, i);
-          const Vec3<double> b = VecF64::load(A.b, half, c, i);
-          Vec3<double> o;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            o.c[k].re = __builtin_fma(-a, y.c[k].re, b.c[k].re) + (double)acc[r].c[k].re;
-            o.c[k].im = __builtin_fma(-a, y.c[k].im, b.c[k].im) + (double)acc[r].c[k].im;
-          }
-          OutT::store(A.out, half, c, i, convert<typename OutT::real>(o));
-          d = norm2_d(o);
-        }
-      }
-      const double tot = block_sum(d, sh);
-      if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
-      __syncthreads();
-    }
-  }
-}
-
-template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
-int go(const DslashArgs& a0, hipStream_t s) {
-  if (a0.apa && R > kFoldAlphaMaxTile) return ASQ_EINVAL;  // alpha is formed in-kernel only by narrow tiles
-  DslashArgs a = a0;
-  a.ntiles = (a.ncol + R - 1) / R;
-  const long nb = (long)a.nblk * a.ntiles;
-  if (nb <= 0) return ASQ_OK;
-  if (nb >= (1L << 31)) return ASQ_EINVAL;
-  dslash_kernel<Link, InT, OutT, R, EPI, PIPE><<<(unsigned)nb, kBlock, 0, s>>>(a);
-  return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
-}
-
-// rtile encodes the launch variant: columns per thread in the low byte, the
-// software-pipelined form in bit 8 (see tuned_rtile).
-template <class Link, class InT, class OutT, int EPI>
-int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
-  const bool pipe = (rtile & kPipeBit) != 0;
-  switch (rtile & 0xff) {
-    case 1: return pipe ? go<Link, InT, OutT, 1, EPI, true>(a, s) : go<Link, InT, OutT, 1, EPI, false>(a, s);
-    case 2: return pipe ? go<Link, InT, OutT, 2, EPI, true>(a, s) : go<Link, InT, OutT, 2, EPI, false>(a, s);
-    case 4: return pipe ? go<Link, InT, OutT, 4, EPI, true>(a, s) : go<Link, InT, OutT, 4, EPI, false>(a, s);
-    case 8: return pipe ? go<Link, InT, OutT, 8, EPI, true>(a, s) : go<Link, InT, OutT, 8, EPI, false>(a, s);
-  }
-  return ASQ_EINVAL;
-}
-
-// Iterated tiers: PLAIN and NORM write the input tier; UPDATE takes the residual tier.
-template <class Link, class V, class RT>
-int pick_iter(int epi, int rtile, const DslashArgs& a, hipStream_t s) {
-  if (epi == EPI_PLAIN) return pick_r<Link, V, V, EPI_PLAIN>(rtile, a, s);
-  if (epi == EPI_NORM) return pick_r<Link, V, V, EPI_NORM>(rtile, a, s);
-  if (epi == EPI_UPDATE) return pick_r<Link, V, RT, EPI_UPDATE>(rtile, a, s);
-  return ASQ_EINVAL;
-}
-
-}  // namespace
 
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,
                   hipStream_t s) {
+  if (!variant_built(link_kind, in_kind, rtile)) return ASQ_EINVAL;
   if (link_kind == LINK_F64_R18) {
     if (in_kind != VEC_F64) return ASQ_EINVAL;
-    if (epi == EPI_RESID) {
-      if (out_kind == VEC_F64) return pick_r<LinkF64R18, VecF64, VecF64, EPI_RESID>(rtile, a, s);
-      if (out_kind == VEC_F32) return pick_r<LinkF64R18, VecF64, VecF32, EPI_RESID>(rtile, a, s);
-      return ASQ_EINVAL;
-    }
-    if (out_kind != VEC_F64) return ASQ_EINVAL;
-    return pick_iter<LinkF64R18, VecF64, VecF64>(epi, rtile, a, s);
+    return launch_dslash_f64(out_kind, epi, rtile, a, s);
   }
   if (epi == EPI_RESID) return ASQ_EINVAL;
   // PLAIN / NORM write the input tier; UPDATE keeps r in FP32
   const int want_out = epi == EPI_UPDATE ? VEC_F32 : in_kind;
   if (out_kind != want_out) return ASQ_EINVAL;
-  if (link_kind == LINK_F32_R18) {
-    if (in_kind == VEC_F32) return pick_iter<LinkF32R18, VecF32, VecF32>(epi, rtile, a, s);
-    if (in_kind == VEC_F16) return pick_iter<LinkF32R18, VecF16, VecF32>(epi, rtile, a, s);
-  } else if (link_kind == LINK_F32_R12) {
-    if (in_kind == VEC_F32) return pick_iter<LinkF32R12, VecF32, VecF32>(epi, rtile, a, s);
-    if (in_kind == VEC_F16) return pick_iter<LinkF32R12, VecF16, VecF32>(epi, rtile, a, s);
-  } else if (link_kind == LINK_I16_R12) {
-    if (in_kind == VEC_F16) return pick_iter<LinkI16R12, VecF16, VecF32>(epi, rtile, a, s);
-  }
+  if (link_kind == LINK_F32_R18) return launch_dslash_f32r18(in_kind, epi, rtile, a, s);
+  if (link_kind == LINK_F32_R12) return launch_dslash_f32r12(in_kind, epi, rtile, a, s);
+  if (link_kind == LINK_I16_R12) return launch_dslash_i16r12(in_kind, epi, rtile, a, s);
   return ASQ_EINVAL;
 }
 

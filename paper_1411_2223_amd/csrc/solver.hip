@@ -453,10 +453,12 @@ extern "C" int cg_solve(const asq_gauge* g, double mass, const double* b_dev, do
   return cg_solve_batch(g, 1, &mass, b_dev, x_dev, work_dev, work_bytes, params, stats, hip_stream);
 }
 
-extern "C" int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
-                                void* out_dev, void* hip_stream) {
+// Shared by asqtad_dslash_eo and asqtad_dslash_eo_variant: variant < 0 takes
+// the tuned launch variant.
+static int dslash_public(const char* who, const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
+                         void* out_dev, int variant, hipStream_t stream) {
   if (!g || !in_dev || !out_dev || nrhs <= 0 || (out_parity != 0 && out_parity != 1)) {
-    set_last_error("asqtad_dslash_eo: null pointer, nrhs <= 0 or parity not 0/1");
+    set_last_error(std::string(who) + ": null pointer, nrhs <= 0 or parity not 0/1");
     return ASQ_EINVAL;
   }
   int link;
@@ -464,15 +466,15 @@ extern "C" int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, in
   else if (prec == ASQ_F32) link = g->sloppy_link32;
   else if (prec == ASQ_F16) link = g->sloppy_link16;
   else {
-    set_last_error("asqtad_dslash_eo: prec must be ASQ_F64, ASQ_F32 or ASQ_F16");
+    set_last_error(std::string(who) + ": prec must be ASQ_F64, ASQ_F32 or ASQ_F16");
     return ASQ_EINVAL;
   }
   if (!g->links[link]) {
-    set_last_error("asqtad_dslash_eo: the gauge field keeps no links for this precision");
+    set_last_error(std::string(who) + ": the gauge field keeps no links for this precision");
     return ASQ_EINVAL;
   }
   if (((uintptr_t)in_dev & 15) || ((uintptr_t)out_dev & 15)) {
-    set_last_error("asqtad_dslash_eo: vectors must be 16-byte aligned");
+    set_last_error(std::string(who) + ": vectors must be 16-byte aligned");
     return ASQ_EINVAL;
   }
   const int vk = prec == ASQ_F64 ? VEC_F64 : (prec == ASQ_F32 ? VEC_F32 : VEC_F16);
@@ -489,12 +491,31 @@ extern "C" int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, in
   a.nblk = g->nblk;
   a.coeff_fat = g->desc.fat_scale;
   a.coeff_long = g->desc.long_scale;
-  int rc0 = tune_dslash(g, link, vk, nrhs, in_dev, out_dev, (hipStream_t)hip_stream);
-  if (rc0) return rc0;
-  const int rt = tuned_rtile(g, link, vk, vk, EPI_PLAIN, nrhs);
-  const int rc = launch_dslash(link, vk, vk, EPI_PLAIN, rt, a, (hipStream_t)hip_stream);
+  int rt = variant;
+  if (variant < 0) {
+    const int rc0 = tune_dslash(g, link, vk, nrhs, in_dev, out_dev, stream);
+    if (rc0) return rc0;
+    rt = tuned_rtile(g, link, vk, vk, EPI_PLAIN, nrhs);
+  }
+  const int rc = launch_dslash(link, vk, vk, EPI_PLAIN, rt, a, stream);
   if (rc == ASQ_EHIP) set_last_error(hipGetErrorString(hipGetLastError()));
+  if (rc == ASQ_EINVAL) set_last_error(std::string(who) + ": launch variant not available for this tier");
   return rc;
+}
+
+extern "C" int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
+                                void* out_dev, void* hip_stream) {
+  return dslash_public("asqtad_dslash_eo", g, out_parity, prec, nrhs, in_dev, out_dev, -1, (hipStream_t)hip_stream);
+}
+
+extern "C" int asqtad_dslash_eo_variant(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
+                                        void* out_dev, int variant, void* hip_stream) {
+  if (variant < 0) {
+    set_last_error("asqtad_dslash_eo_variant: variant must be >= 0");
+    return ASQ_EINVAL;
+  }
+  return dslash_public("asqtad_dslash_eo_variant", g, out_parity, prec, nrhs, in_dev, out_dev, variant,
+                       (hipStream_t)hip_stream);
 }
 
 extern "C" const char* asq_strerror(int code) {

@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "asq_internal.h"
 
@@ -69,7 +70,19 @@ bool tuning_on() {
 
 }  // namespace
 
+// ASQ_VARIANT=<code> (decimal) replaces the tuned launch variant wherever the
+// library builds that variant for the tier (tests use it to run every variant
+// through the solver epilogues).
+int forced_variant(int link, int in) {
+  const char* e = getenv("ASQ_VARIANT");
+  if (!e || !*e) return -1;
+  const int v = atoi(e);
+  return variant_built(link, in, v) ? v : -1;
+}
+
 int tuned_rtile(const asq_gauge* g, int link, int in, int out, int epi, int ncol) {
+  const int fv = forced_variant(link, in);
+  if (fv >= 0 && (fv & 0xff) <= (ncol > 1 ? ncol : 1)) return fv;
   std::lock_guard<std::mutex> lk(g_mu);
   load_cache_locked();
   auto it = g_cache.find(key_of(g, link, in, out, epi, ncol));
@@ -106,7 +119,13 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     ASQ_HIP_TRY(hipEventCreate(&e0));
     ASQ_HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    const int cands[8] = {1, 2, 4, 8, 1 | kPipeBit, 2 | kPipeBit, 4 | kPipeBit, 8 | kPipeBit};
+    // columns per thread x hop-loop form x block order (orders differ only when
+    // there are several tiles)
+    std::vector<int> cands;
+    for (int order = 0; order < 4; ++order)
+      for (int pipe = 0; pipe < 2; ++pipe)
+        for (int cols : {1, 2, 4, 8})
+          if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, pipe, order));
     for (int r : cands) {
       const int cols = r & 0xff;
       if (cols > 1 && cols > ncol) continue;  // a wider tile than the batch only wastes lanes

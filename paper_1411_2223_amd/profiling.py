@@ -18,7 +18,9 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ("csrc/dslash.hip", "csrc/asq_device.h", "csrc/asq_reduce.h", "csrc/asq_internal.h")
+KERNEL_SOURCES = ("csrc/dslash.hip", "csrc/dslash_impl.h", "csrc/dslash_f64.hip", "csrc/dslash_f32.hip",
+                  "csrc/dslash_r12.hip", "csrc/dslash_i16.hip", "csrc/asq_device.h", "csrc/asq_reduce.h",
+                  "csrc/asq_internal.h")
 
 
 def counters_file(lattice: str) -> str:
@@ -52,17 +54,25 @@ def short_name(name: str) -> str:
     return n[:110]
 
 
-def counter_means(path: str, counter: str, by_grid: bool = False) -> dict:
+def counter_means(path: str, counter: str, by_grid: bool = False, last: int = 0) -> dict:
     """kernel name (or (name, grid size in threads)) -> (dispatches, mean counter value per
-    dispatch) from counter_collection.csv."""
+    dispatch) from counter_collection.csv; with last > 0 over the last `last` dispatches
+    only (the timed launches, after the autotuner's trials of other variants of the
+    same kernel)."""
     acc = defaultdict(list)
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name", r.get("counter_name")) != counter:
             continue
         name = r.get("Kernel_Name", r.get("kernel_name"))
         key = (name, int(r["Grid_Size"])) if by_grid else name
-        acc[key].append(float(r.get("Counter_Value", r.get("value"))))
-    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
+        acc[key].append((int(r["Dispatch_Id"]), float(r.get("Counter_Value", r.get("value")))))
+    out = {}
+    for k, v in acc.items():
+        vals = [x for _, x in sorted(v)]
+        if last > 0:
+            vals = vals[-last:]
+        out[k] = (len(vals), sum(vals) / len(vals))
+    return out
 
 
 # Dslash launches of `bench.py [--workload ...] --kernels-only` per lattice, keyed
@@ -74,15 +84,15 @@ HALF = {"20x20x20x64": H20, "48x48x48x96": H48}
 KERNELS_ONLY = {
     "20x20x20x64": {
         "workload": "single_20x20x20x64",
-        "f32_f32_1rhs": ("dslash_kernel<LinkF32R18, VecF32, VecF32, ", (16 * 72 + 2 * 24) * H20, 1),
-        "f64_f64_1rhs": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 2 * 48) * H20, 1),
-        "f16_f32_1rhs": ("dslash_kernel<LinkF32R18, VecF16, VecF16, ", (16 * 72 + 2 * 16) * H20, 1),
-        "f16_f32_96rhs": ("dslash_kernel<LinkF32R18, VecF16, VecF16, ", (16 * 72 + 96 * 2 * 16) * H20, 96),
+        "f32_f32_1rhs": ("dslash_kernel<LinkF32R18, VecF32, VecF32, ", (16 * 72 + 2 * 24) * H20, 1, 20),
+        "f64_f64_1rhs": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 2 * 48) * H20, 1, 20),
+        "f16_f32_1rhs": ("dslash_kernel<LinkF32R18, VecF16, VecF16, ", (16 * 72 + 2 * 16) * H20, 1, 20),
+        "f16_f32_96rhs": ("dslash_kernel<LinkF32R18, VecF16, VecF16, ", (16 * 72 + 96 * 2 * 16) * H20, 96, 12),
     },
     "48x48x48x96": {
         "workload": "threelevel_48x48x48x96",
-        "f16_f16r12_12rhs": ("dslash_kernel<LinkI16R12, VecF16, VecF16, ", (16 * 24 + 12 * 2 * 16) * H48, 12),
-        "f64_f64_12rhs": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 12 * 2 * 48) * H48, 12),
+        "f16_f16r12_12rhs": ("dslash_kernel<LinkI16R12, VecF16, VecF16, ", (16 * 24 + 12 * 2 * 16) * H48, 12, 10),
+        "f64_f64_12rhs": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 12 * 2 * 48) * H48, 12, 5),
     },
 }
 COPY_KERNEL = "copy_kernel"
@@ -94,6 +104,11 @@ def write_counters(fetch_csv: str, write_csv: str, run_dir: str, lattice: str = 
     spec = KERNELS_ONLY[lattice]
     fetch = counter_means(fetch_csv, "FETCH_SIZE", by_grid=True)
     write = counter_means(write_csv, "WRITE_SIZE", by_grid=True)
+    # the timed launches of each key: the last dispatches of its variant
+    fetch_last = {key: counter_means(fetch_csv, "FETCH_SIZE", by_grid=True, last=spec[key][3])
+                  for key in spec if key != "workload"}
+    write_last = {key: counter_means(write_csv, "WRITE_SIZE", by_grid=True, last=spec[key][3])
+                  for key in spec if key != "workload"}
     nblk = (HALF[lattice] + 255) // 256
 
     def is_plain(name):
@@ -122,7 +137,8 @@ def write_counters(fetch_csv: str, write_csv: str, run_dir: str, lattice: str = 
     keys = [k for k in spec if k != "workload"]
     for key in keys:
         k = find(spec[key][0], spec[key][2])
-        kernels[key] = {"FETCH_SIZE_KiB": fetch[k][1], "WRITE_SIZE_KiB": write[k][1], "dispatches": fetch[k][0],
+        fl, wl_ = fetch_last[key][k], write_last[key][k]
+        kernels[key] = {"FETCH_SIZE_KiB": fl[1], "WRITE_SIZE_KiB": wl_[1], "dispatches": fl[0],
                         "kernel": short_name(k[0]), "grid_threads": k[1]}
     wl = "" if spec["workload"] == "single_20x20x20x64" else f"--workload {spec['workload']} "
     cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {run_dir}/fetch -o k -- python -u bench.py "
@@ -141,6 +157,8 @@ def write_counters(fetch_csv: str, write_csv: str, run_dir: str, lattice: str = 
              "", "Commands (repository root on the MI355X box, one counter per pass):", ""]
     lines += ["    " + c for c in cmds]
     lines += ["", f"Kernel sources hash (`python -m paper_1411_2223_amd.profiling hash`): `{h}`", "",
+              "Each row averages the timed launches of the variant the autotuner chose (the last",
+              "dispatches of that kernel and grid; the tuner's trial launches come first).", "",
               f"Calibration with the plain copy kernel (`asq_copy_probe`, {COPY_BYTES >> 30} GiB read + "
               f"{COPY_BYTES >> 30} GiB written): FETCH_SIZE = {fetch[copy][1]:.1f} KiB, WRITE_SIZE = "
               f"{write[copy][1]:.1f} KiB per dispatch, so bytes = 1024 x ({ff:.4f} x FETCH_SIZE + {wf:.4f} x "

@@ -72,6 +72,44 @@ def test_dslash_parity_full_size(asq, prec, recon, nrhs):
     _check(asq, g, fat, lng, dims, prec, nrhs, 7)
 
 
+@pytest.mark.parametrize("prec,recon", TIERS)
+def test_every_launch_variant(asq, prec, recon):
+    # Every column-tile width, hop-loop form and block order computes each column
+    # with the same arithmetic in the same order: bitwise equal outputs, and the
+    # oracle's tolerance.  13 columns leave a partial tile, 960 output sites a
+    # ragged last block and a short last group of site blocks.
+    import torch
+
+    if prec == "f64" and recon == 12:
+        pytest.skip("FP64 links are always 18-real")
+    dims, nrhs = (6, 4, 8, 10), 13
+    g, fat, lng = _gauge(asq, dims, 0.3, 5, recon)
+    half = int(np.prod(dims)) // 2
+    v = synth.make_sources(dims, nrhs, 77)
+    vin = asq.vec_to_device(v, prec)
+    ref_dev = g.dslash(1, vin, prec, nrhs)
+    torch.cuda.synchronize()
+    ref = oracle_dslash_cols(dims, fat, lng, 1, quantize_like_device(v, prec))
+    err = rel_err(asq.vec_from_device(ref_dev, nrhs, half, prec), ref)
+    assert err.max() <= TOL[prec]
+    for cols, pipe, order in asq.VARIANTS_ALL:
+        out = g.dslash(1, vin, prec, nrhs, variant=asq.variant_code(cols, pipe, order))
+        torch.cuda.synchronize()
+        print(f"prec={prec} recon={recon} variant cols={cols} pipe={pipe} order={order}", flush=True)
+        assert torch.equal(out, ref_dev), f"variant ({cols}, {pipe}, {order}) differs from the tuned one"
+
+
+def test_unbuilt_variant_rejected(asq):
+    # codes outside the documented set are refused without launching
+    dims = (4, 4, 4, 8)
+    g, fat, lng = _gauge(asq, dims, 0.3, 14112223, 18)
+    vin = asq.vec_to_device(synth.make_sources(dims, 8, 1), "f64")
+    for bad in (3, 16, asq.variant_code(4) | (1 << 14)):
+        with pytest.raises(asq.AsqError) as e:
+            g.dslash(1, vin, "f64", 8, variant=bad)
+        assert e.value.code == asq.ASQ_EINVAL
+
+
 def test_free_field_plane_wave_on_gpu(asq):
     # U = 1: D_eo D_oe on an even plane wave is -4 sum f(p)^2 (closed form, no oracle involved)
     import torch

@@ -77,6 +77,31 @@ def test_cg_batch_columns_match_solo(asq, mode):
         assert np.array_equal(xs[0], xb[c]), "column result depends on the batch"
 
 
+@pytest.mark.parametrize("mode,recon", [("mixed16", 18), ("mixed16", 12), ("mixed32", 18), ("f64", 18)])
+def test_batch_every_launch_variant(asq, mode, recon, monkeypatch):
+    # The NORM, UPDATE and RESID epilogues of every launch variant reduce their
+    # partials with the same tree: a batched solve gives bitwise the same x under
+    # each forced variant (ASQ_VARIANT) as under the tuned ones.
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    precs = ("f64", "f32", "f16") if recon == 12 else ("f64", "f32")
+    g = asq.Gauge(dims, fat, lng, precs=precs, recon=recon)
+    masses = [0.05, 0.1, 0.02, 0.2, 0.07, 0.03, 0.15, 0.05, 0.1, 0.04, 0.3, 0.06, 0.08]
+    b = synth.make_sources(dims, len(masses), 43)
+    x0, r0 = _solve(asq, g, masses, b, mode)
+    assert r0.rc == 0
+    assert np.all(oracle_resid_cols(dims, fat, lng, masses, b, x0) <= TOL)
+    for cols, pipe, order in asq.VARIANTS_ALL:
+        if cols == 1 and order > 0:
+            continue  # one-column tiles: the orders only permute blocks, covered by the Dslash test
+        monkeypatch.setenv("ASQ_VARIANT", str(asq.variant_code(cols, pipe, order)))
+        x, r = _solve(asq, g, masses, b, mode)
+        print(f"mode={mode} recon={recon} variant cols={cols} pipe={pipe} order={order}", flush=True)
+        assert r.rc == 0
+        assert [s["iters"] for s in r.stats] == [s["iters"] for s in r0.stats]
+        assert np.array_equal(x, x0), f"variant ({cols}, {pipe}, {order}) changes the solution"
+
+
 def test_graph_matches_eager(asq):
     dims = (6, 4, 8, 10)
     fat, lng = gauge_arrays(dims, 0.3, 5)
