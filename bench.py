@@ -131,6 +131,26 @@ def copy_bandwidth(asq, stream, nbytes=1 << 30, reps=10):
     return 2 * nbytes / dt / 1e9
 
 
+def read_bandwidth(asq, stream, nbytes=1 << 30, reps=10):
+    """Read-only GB/s of the library's read probe on a buffer far beyond the 256 MB MALL."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    sink = torch.empty(asq.asq_read_probe_blocks(nbytes) * 16, dtype=torch.uint8, device="cuda")
+    sp = asq.stream_ptr(stream)
+    for _ in range(2):
+        asq.check(asq.asq_read_probe(src.data_ptr(), nbytes, sink.data_ptr(), sp), "asq_read_probe")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        asq.check(asq.asq_read_probe(src.data_ptr(), nbytes, sink.data_ptr(), sp), "asq_read_probe")
+    e1.record(stream)
+    e1.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, sink
+    return nbytes / dt / 1e9
+
+
 def cpu_baseline(w, fat, lng, b, mass, iters_full, seconds):
     """Oracle CG on the same workload, bounded: time a prefix of iterations, scale to a full solve."""
     import oracle
@@ -160,6 +180,31 @@ def cpu_baseline(w, fat, lng, b, mass, iters_full, seconds):
             "seconds_per_solve": t_solve,
             "dslash_ms": t_d * 1e3,
             "dslash_gbs_effective": dslash_bytes_per_site("f64", "f64", 1) * half / t_d / 1e9}
+
+
+def cpu_baseline_extrapolated(dims, fat, lng, b0, mass, col_iters, seconds, unit):
+    """Oracle FP64 CG per-iteration time on a bounded prefix of one column's solve, scaled
+    to the batch: the oracle solves the columns one after another, each for the number of
+    iterations the GPU needed for it (labelled extrapolated)."""
+    import oracle
+
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.apply_A(dims, fat, lng, mass, b0)
+    per_apply = time.perf_counter() - t0
+    n = max(3, int(seconds / max(per_apply, 1e-6)))
+    t0 = time.perf_counter()
+    _, it, _, _ = oracle.cg(dims, fat, lng, mass, b0, tol=1e-10, maxiter=n)
+    dt = time.perf_counter() - t0
+    per_iter = max(dt - per_apply, 1e-9) / max(it, 1)
+    total = per_iter * sum(col_iters)
+    value = len(col_iters) / total if unit == "RHS-solves/s" else total * 1e3
+    return {"value": value, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle",
+            "extrapolated": True,
+            "sample": f"oracle FP64 CG, first {it} iterations of one column at "
+                      f"{'x'.join(map(str, dims))} ({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled to "
+                      f"{len(col_iters)} columns x their GPU iteration counts ({sum(col_iters)} iterations)",
+            "seconds_per_batch": total}
 
 
 def kernels_only(asq, g, dims):
@@ -280,7 +325,8 @@ def run_single(args, asq, torch):
     f64_gbs = dslash_bytes_per_site("f64", "f64", 1) * half / dt64 / 1e9
     log(f"dslash {tprec}: {dt * 1e6:.2f} us, {achieved:.0f} GB/s; f64: {dt64 * 1e6:.2f} us, {f64_gbs:.0f} GB/s")
     copy_gbs = copy_bandwidth(asq, stream)
-    log(f"copy probe: {copy_gbs:.0f} GB/s")
+    read_gbs = read_bandwidth(asq, stream)
+    log(f"copy probe: {copy_gbs:.0f} GB/s; read probe: {read_gbs:.0f} GB/s")
 
     ms = secs * 1e3
     iters = st["iters"]
@@ -315,6 +361,7 @@ def run_single(args, asq, torch):
         "dslash_gbs": achieved,
         "dslash_f64_gbs": f64_gbs,
         "copy_probe_gbs": copy_gbs,
+        "read_probe_gbs": read_gbs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(f"{tprec}_{link}_1rhs", bytes_launch),
@@ -368,7 +415,12 @@ def run_batched(args, asq, torch):
            "dslash": {"us": dt * 1e6, "GBps": gbs, "TFLOPs": tf, "bytes_per_site": bytes_launch / half,
                       "flop_per_byte": flops_launch / bytes_launch,
                       "frac_hbm": gbs / PEAK_HBM_GBS, "frac_fp32_alu": tf / PEAK_FP32_TFLOPS,
-                      "frac_fp32_packed_peak": tf / PEAK_FP32_PACKED_TFLOPS}}
+                      "frac_fp32_packed_peak": tf / PEAK_FP32_PACKED_TFLOPS,
+                      "traffic": measured_traffic(f"{tprec}_{link}_{ncol}rhs", bytes_launch)}}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, extrapolated) ...")
+        out["cpu_baseline"] = cpu_baseline_extrapolated(dims, fat, lng, src[0], masses_u[0], its,
+                                                        args.cpu_seconds, "RHS-solves/s")
     print(json.dumps(out), flush=True)
 
 
@@ -405,14 +457,19 @@ def run_threelevel(args, asq, torch):
     gbs1 = dslash_bytes_per_site("f16r12", "f16", 1) * half / dt1 / 1e9
     log(f"dslash f16 r12 x{ncol}: {dt * 1e6:.0f} us, {gbs:.0f} GB/s, {tf:.1f} TFLOP/s; 1 RHS {gbs1:.0f} GB/s")
     oracle_resid = None
-    if not args.no_oracle_check:
+    cpu = None
+    if not args.no_oracle_check or not args.no_cpu_baseline:
         import oracle
 
         fat, lng = synth.make_gauge(dims, w["eps"], synth.gauge_seed(w["index"]))
         b = synth.make_sources(dims, ncol, synth.source_seed(w["index"]))
-        xs = asq.vec_from_device(x, ncol, half, "f64")
-        oracle_resid = [oracle.true_residual(dims, fat, lng, mass, b[c], xs[c]) for c in range(ncol)]
-        log(f"oracle FP64 true residual of every column: max {max(oracle_resid):.3e}")
+        if not args.no_oracle_check:
+            xs = asq.vec_from_device(x, ncol, half, "f64")
+            oracle_resid = [oracle.true_residual(dims, fat, lng, mass, b[c], xs[c]) for c in range(ncol)]
+            log(f"oracle FP64 true residual of every column: max {max(oracle_resid):.3e}")
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle, extrapolated) ...")
+            cpu = cpu_baseline_extrapolated(dims, fat, lng, b[0], mass, its, args.cpu_seconds, "ms to 1e-10")
     traffic = measured_traffic("f16_f16r12_12rhs", bytes_launch, lattice="48x48x48x96")
     if traffic:
         log(f"counter-measured traffic {traffic / 1e9:.2f} GB per launch: {traffic / dt / 1e9:.0f} GB/s")
@@ -425,6 +482,8 @@ def run_threelevel(args, asq, torch):
                             "traffic": traffic,
                             "traffic_GBps": traffic / dt / 1e9 if traffic else None},
            "dslash_1rhs_GBps": gbs1}
+    if cpu:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -3,10 +3,10 @@
  *
  * The paper (Lattice 2014 proceedings on Kepler GPUs and Xeon Phi) measures a
  * mixed-precision conjugate-gradient inverter for the staggered asqtad quark
- * matrix on a 20^3 x 64 MILC lattice, "most of the calculations performed in
- * single precision" (section "GTX Titan Black", CG performance figure and
- * table; section "CPS & QUDA", mixed precision and automatic tuning of the
- * running parameters).  The paper states no formulas; the operator below is
+ * matrix on a 20^3 x 64 MILC lattice, with the bulk of its arithmetic in single
+ * precision (section "GTX Titan Black", CG performance figure and table;
+ * section "CPS & QUDA", mixed precision and automatic tuning of the launch
+ * parameters).  The paper states no formulas; the operator below is
  * the standard asqtad one:
  *
  *   (D psi)(x) = sum_mu eta_mu(x) [ F_mu(x) psi(x+mu) - F_mu(x-mu)^dag psi(x-mu)
@@ -193,6 +193,12 @@ const char* asq_last_error(void);
    device pointers), asynchronous.  The plain copy kernel used to calibrate
    bandwidth and hardware counters. */
 int asq_copy_probe(void* dst_dev, const void* src_dev, size_t n, void* hip_stream);
+/* HBM read probe: reads n bytes of src (n a multiple of 16, 16-byte aligned)
+   and writes one 16-byte XOR digest per block to sink_dev (at least
+   asq_read_probe_blocks(n) x 16 bytes), asynchronous.  The read-only ceiling
+   next to which a read-dominated kernel such as the Dslash is judged. */
+int asq_read_probe(const void* src_dev, size_t n, void* sink_dev, void* hip_stream);
+size_t asq_read_probe_blocks(size_t n);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,8 @@ _SIGS = {
     "asq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "asq_last_error": (ctypes.c_char_p, []),
     "asq_copy_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+    "asq_read_probe": (ctypes.c_int, [_vp, ctypes.c_size_t, _vp, _vp]),
+    "asq_read_probe_blocks": (ctypes.c_size_t, [ctypes.c_size_t]),
 }
 
 EXPORTS = tuple(_SIGS)

@@ -132,6 +132,48 @@ __global__ void __launch_bounds__(256) copy_kernel(uint4* __restrict__ dst, cons
   for (; k < n; k += stride) dst[k] = src[k];
 }
 
+// XOR of the 16-byte words src[k], k = thread, thread + stride, ...; four loads
+// in flight per thread; one digest per block (so the reads cannot be dropped).
+__global__ void __launch_bounds__(256) read_kernel(const uint4* __restrict__ src, size_t n, uint4* sink) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint4 acc = make_uint4(0, 0, 0, 0);
+  for (; k + 3 * stride < n; k += 4 * stride) {
+    const uint4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
+    acc.x ^= a.x ^ b.x ^ c.x ^ d.x;
+    acc.y ^= a.y ^ b.y ^ c.y ^ d.y;
+    acc.z ^= a.z ^ b.z ^ c.z ^ d.z;
+    acc.w ^= a.w ^ b.w ^ c.w ^ d.w;
+  }
+  for (; k < n; k += stride) {
+    const uint4 a = src[k];
+    acc.x ^= a.x;
+    acc.y ^= a.y;
+    acc.z ^= a.z;
+    acc.w ^= a.w;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.x ^= __shfl_xor(acc.x, o, 64);
+    acc.y ^= __shfl_xor(acc.y, o, 64);
+    acc.z ^= __shfl_xor(acc.z, o, 64);
+    acc.w ^= __shfl_xor(acc.w, o, 64);
+  }
+  __shared__ uint4 sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint4 r = sh[0];
+    for (int w = 1; w < 4; ++w) {
+      r.x ^= sh[w].x;
+      r.y ^= sh[w].y;
+      r.z ^= sh[w].z;
+      r.w ^= sh[w].w;
+    }
+    sink[blockIdx.x] = r;
+  }
+}
+
 template <class PT, class RT>
 int launch_vec(int which, const VecArgs& a, int ncol, hipStream_t s) {
   const dim3 grid((unsigned)a.nblk, (unsigned)ncol);
@@ -182,6 +224,24 @@ extern "C" int asq_copy_probe(void* dst_dev, const void* src_dev, size_t n, void
   size_t blocks = (n16 + 1023) / 1024;
   if (blocks > 4096) blocks = 4096;
   asq::copy_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)hip_stream>>>((uint4*)dst_dev, (const uint4*)src_dev, n16);
+  ASQ_HIP_TRY(hipGetLastError());
+  return ASQ_OK;
+}
+
+extern "C" size_t asq_read_probe_blocks(size_t n) {
+  const size_t n16 = n / 16;
+  size_t blocks = (n16 + 1023) / 1024;
+  return blocks > 4096 ? 4096 : (blocks ? blocks : 1);
+}
+
+extern "C" int asq_read_probe(const void* src_dev, size_t n, void* sink_dev, void* hip_stream) {
+  if (!src_dev || !sink_dev || (n & 15) || ((uintptr_t)src_dev & 15) || ((uintptr_t)sink_dev & 15))
+    return ASQ_EINVAL;
+  const size_t n16 = n / 16;
+  if (n16 == 0) return ASQ_OK;
+  const size_t blocks = asq_read_probe_blocks(n);
+  asq::read_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)hip_stream>>>((const uint4*)src_dev, n16,
+                                                                          (uint4*)sink_dev);
   ASQ_HIP_TRY(hipGetLastError());
   return ASQ_OK;
 }

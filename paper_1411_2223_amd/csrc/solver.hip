@@ -1,7 +1,7 @@
 // solver.hip -- CG drivers on even sites: plain FP64 CG and mixed-precision
-// CG with reliable updates (the paper's inverter does "most of the
-// calculations in single precision", section "GTX Titan Black"; QUDA's CG
-// that it adopts is mixed precision, section "CPS & QUDA").
+// CG with reliable updates (the paper's inverter does most of its arithmetic
+// in single precision, section "GTX Titan Black"; the QUDA CG it moves to is
+// mixed precision as well, section "CPS & QUDA").
 //
 // One iteration, all columns at once, all scalars on the device:
 //   p   = r + beta p, |p|^2            (vector kernel, into the other p buffer)
