@@ -162,13 +162,49 @@ int cg_solve_batch(const asq_gauge* g, int nrhs, const double* masses, const dou
                    void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
                    void* hip_stream);
 
+/* Every (mass, source) pair of nmass masses and nsrc sources at once: the
+   shifted systems (4 m_j^2 - D_eo D_oe) x = b share the Krylov space of the
+   smallest mass, so one CG per source (FP32, no reliable updates) carries all
+   masses along with vector updates only, to a relative iterated residual of
+   max(tol, 1e-7).  Each (mass, source) column is then refined from that
+   solution by the reliable-update CG of params->mode to the FP64 true residual
+   tol.  b_dev: device double [nsrc][3][V/2][2]; x_dev: [nmass][nsrc][3][V/2][2]
+   (column j * nsrc + s).  masses: host double [nmass] (> 0, any order).
+   work_dev: >= asq_multishift_workspace_bytes, 256-byte aligned.  stats[c]:
+   iters = shifted-phase plus refinement iterations; reliable updates, true
+   residual and status as cg_solve_batch.  Needs the FP32 links.  Returns when
+   done.  (The multi-shift form of the paper's 24-source x 4-mass workload.) */
+size_t asq_multishift_workspace_bytes(const asq_gauge* g, int nsrc, int nmass, int mode);
+int cg_solve_multishift(const asq_gauge* g, int nsrc, int nmass, const double* masses, const double* b_dev,
+                        double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
+                        asq_cg_stats* stats, void* hip_stream);
+
+/* The full-lattice system M x_c = b_c, M = 2 m_c + D on both parities,
+   through the even-odd reduction the CG works on:
+     b' = 2m b_e - D_eo b_o,  (4m^2 - D_eo D_oe) x_e = b' (cg_solve_batch),
+     x_o = (b_o - D_oe x_e) / (2m).
+   The odd equations then hold exactly, so |b - M x| = |b' - A x_e| / (2m) and
+   each column's even solve runs to tol * 2m |b| / |b'|.  b_dev, x_dev: device
+   double [2][nrhs][3][V/2][2] (the even halves of all columns, then the odd
+   halves).  work_dev: >= asq_full_workspace_bytes, 256-byte aligned.
+   stats[c]: iterations and reliable updates of the even solve; true_resid =
+   |b - M x| / |b| recomputed with the FP64 operator after the
+   reconstruction (ASQ_ENOCONV if it exceeds tol).  Returns when done. */
+size_t asq_full_workspace_bytes(const asq_gauge* g, int nrhs, int mode);
+int cg_solve_full(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev, double* x_dev,
+                  void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
+                  void* hip_stream);
+
 /* ---- serving --------------------------------------------------------------- */
 
 /* A request loop with continuous batching: requests on a registered gauge
    field join the in-flight batch of that field when column slots and arena
    memory free up; batches of different fields run on their own streams.
    arena_dev/arena_bytes: caller-owned device memory = the HBM budget for
-   solver workspaces.  max_streams >= 1, max_cols >= 1 columns per batch. */
+   solver workspaces.  max_streams >= 1: concurrent batches (streams).
+   max_cols >= 1: column slots of a batch of the largest registered field and
+   the most columns one request may have; batches of smaller fields get up to
+   8x as many slots (in proportion to the site counts, as the arena allows). */
 int serve_create(void* arena_dev, size_t arena_bytes, int max_streams, int max_cols, asq_server** out);
 /* The gauge field must outlive the server. */
 int serve_register_gauge(asq_server* s, const asq_gauge* g, int* gauge_id);

@@ -72,6 +72,14 @@ _SIGS = {
     "cg_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp, _vp,
                                       ctypes.c_size_t, ctypes.POINTER(asq_cg_params),
                                       ctypes.POINTER(asq_cg_stats), _vp]),
+    "asq_multishift_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "cg_solve_multishift": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp,
+                                           _vp, _vp, ctypes.c_size_t, ctypes.POINTER(asq_cg_params),
+                                           ctypes.POINTER(asq_cg_stats), _vp]),
+    "asq_full_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int]),
+    "cg_solve_full": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp, _vp,
+                                     ctypes.c_size_t, ctypes.POINTER(asq_cg_params),
+                                     ctypes.POINTER(asq_cg_stats), _vp]),
     "serve_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
     "serve_register_gauge": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int)]),
     "serve_submit": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp,
@@ -296,6 +304,49 @@ class Gauge:
                             ctypes.byref(params), stats, stream_ptr(stream))
         if rc < 0 and rc not in (ASQ_ENOCONV,):
             check(rc, "cg_solve_batch")
+        return SolveResult(x, [s.as_dict() for s in stats], rc)
+
+    def solve_multishift(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.1, poll_iters=8,
+                         use_graph=True, work=None, x=None, stream=None):
+        """Every (mass, source) pair: b is a device tensor [nsrc][3][V/2][2] float64; x is
+        [nmass][nsrc][3][V/2][2] (column j * nsrc + s); returns SolveResult over those columns."""
+        torch = _torch()
+        masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
+        nmass = len(masses)
+        nsrc = b.numel() // (6 * self.half)
+        if work is None:
+            work = empty_bytes(asq_multishift_workspace_bytes(self.handle, nsrc, nmass, MODES[mode]), self.device)
+        if x is None:
+            x = torch.empty(nmass * b.numel(), dtype=b.dtype, device=b.device)
+        params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
+                               1 if use_graph else 0)
+        stats = (asq_cg_stats * (nmass * nsrc))()
+        m = (ctypes.c_double * nmass)(*masses)
+        rc = cg_solve_multishift(self.handle, nsrc, nmass, m, b.data_ptr(), x.data_ptr(), work.data_ptr(),
+                                 work.numel(), ctypes.byref(params), stats, stream_ptr(stream))
+        if rc < 0 and rc not in (ASQ_ENOCONV,):
+            check(rc, "cg_solve_multishift")
+        return SolveResult(x, [s.as_dict() for s in stats], rc)
+
+    def solve_full(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.1, poll_iters=8,
+                   use_graph=True, work=None, x=None, stream=None):
+        """M x = b on both parities (M = 2m + D): b is a device tensor [2][nrhs][3][V/2][2] float64
+        (even halves, then odd halves); returns SolveResult with |b - M x| / |b| per column."""
+        torch = _torch()
+        masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
+        nrhs = len(masses)
+        if work is None:
+            work = empty_bytes(asq_full_workspace_bytes(self.handle, nrhs, MODES[mode]), self.device)
+        if x is None:
+            x = torch.empty_like(b)
+        params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
+                               1 if use_graph else 0)
+        stats = (asq_cg_stats * nrhs)()
+        m = (ctypes.c_double * nrhs)(*masses)
+        rc = cg_solve_full(self.handle, nrhs, m, b.data_ptr(), x.data_ptr(), work.data_ptr(), work.numel(),
+                           ctypes.byref(params), stats, stream_ptr(stream))
+        if rc < 0 and rc not in (ASQ_ENOCONV,):
+            check(rc, "cg_solve_full")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
 
 

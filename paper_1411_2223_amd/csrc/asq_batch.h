@@ -48,7 +48,13 @@ int enqueue_iteration(const Batch& B, hipStream_t s);
 int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s);
 int enqueue_block(const Batch& B, int iters, hipStream_t s);
 int capture_block(const Batch& B, int iters, hipStream_t cap, hipGraphExec_t* exec);
-void init_states(const Batch& B, const double* masses, const asq_cg_params* p, ColState* host);
+void init_states(const Batch& B, const double* masses, const asq_cg_params* p, ColState* host, const double* tols);
+// cg_solve_batch with optional per-column tolerances (host, or nullptr) and,
+// with guess, the solution's initial values taken from x_dev instead of 0.
+int solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double* tols, const double* b_dev,
+                double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
+                void* hip_stream, bool guess = false);
+int enqueue_init_guess(const Batch& B, hipStream_t s);
 void fill_stats(const Batch& B, const ColState* S, double seconds, asq_cg_stats* out, int* worst);
 int check_params(const asq_gauge* g, const asq_cg_params* p);
 

@@ -81,11 +81,12 @@ struct alignas(128) ColState {
   int frozen;      // sloppy residual met tol: skip iterations until the FP64 check
   int status;      // 0 ok, ASQ_ENAN on a non-finite or non-positive reduction
   int pbuf;        // which of the two p buffers holds the current direction
+  int sloppy_stop; // stop at the iterated residual, without an FP64 decision (shifted CG's first phase)
 };
 static_assert(sizeof(ColState) == 128, "ColState layout");
 
 // Scalar updates applied to a column from its reduced sums (see asq_reduce.h).
-enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_FINAL = 4 };
+enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_FINAL = 4, OP_INIT_GUESS = 5 };
 
 struct DslashArgs {
   Geom g;

@@ -56,9 +56,13 @@ __device__ inline void finalize_column(ColState& S, double s, int op) {
       S.beta = s / S.rr_old;
       const double r = sqrt(s);
       if (r <= S.tol * sqrt(S.bb) || S.iters >= S.maxiter) {
-        // iterated residual met tol (or the budget is spent): decide on the FP64 residual
-        S.frozen = 1;
-        S.want_ru = 1;
+        if (S.sloppy_stop) {
+          S.active = 0;  // the caller decides on the solution
+        } else {
+          // iterated residual met tol (or the budget is spent): decide on the FP64 residual
+          S.frozen = 1;
+          S.want_ru = 1;
+        }
       } else if (S.delta > 0 && r < S.delta * S.maxr) {
         S.want_ru = 1;
       }
@@ -90,6 +94,27 @@ __device__ inline void finalize_column(ColState& S, double s, int op) {
       S.true_rr = s;
       break;
   }
+}
+
+// Start from a given x: bb = |b|^2, rr = |b - A x|^2 (FP64).  With b = 0 the
+// relative tolerance cannot be met unless r = 0 as well.
+__device__ inline void finalize_guess(ColState& S, double bb, double rr) {
+  const bool finite = isfinite(bb) && isfinite(rr);
+  S.bb = bb;
+  S.rr = rr;
+  S.rr_old = rr;
+  S.true_rr = rr;
+  S.maxr = sqrt(rr);
+  S.alpha = 0;
+  S.beta = 0;
+  S.iters = 0;
+  S.n_ru = 0;
+  S.want_ru = 0;
+  S.frozen = 0;
+  S.pbuf = 0;
+  S.status = finite ? 0 : ASQ_ENAN;
+  S.converged = finite && (rr == 0 || (bb > 0 && sqrt(rr) <= S.tol * sqrt(bb)));
+  S.active = finite && !S.converged;
 }
 
 // This thread's share of a fixed-order sum of partials[0..n): elements

@@ -4,7 +4,7 @@
 
 namespace asq {
 
-enum VecKernel { VK_INIT = 0, VK_P = 2, VK_FLUSH = 3 };
+enum VecKernel { VK_INIT = 0, VK_P = 2, VK_FLUSH = 3, VK_GUESS = 4 };
 
 struct VecArgs {
   int half;

@@ -48,6 +48,25 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const VecArgs A) {
   if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
 }
 
+// Start from the x already in place: x_s = 0, p = 0 (the first direction update
+// makes p = r); partials of |b|^2.  The FP64 residual is computed next.
+template <class PT, class RT>
+__global__ void __launch_bounds__(kBlock) guess_kernel(const VecArgs A) {
+  const int c = blockIdx.y, sblk = blockIdx.x;
+  const int half = A.half;
+  const int i = sblk * kBlock + (int)threadIdx.x;
+  double d = 0;
+  if (i < half) {
+    const Vec3<double> b = VecF64::load(A.b, half, c, i);
+    if (A.xs) VecF32::store(A.xs, half, c, i, zero3<float>());
+    PT::store(A.p, half, c, i, zero3<typename PT::real>());
+    d = norm2_d(b);
+  }
+  __shared__ double sh[kBlock / 64];
+  const double tot = block_sum(d, sh);
+  if (threadIdx.x == 0) A.partials[(size_t)c * A.nblk + sblk] = tot;
+}
+
 // p_new = r + beta p into the buffer that is not current; partials of |p_new|^2
 // (as stored), which give <p, A p> = a |p|^2 + |D_oe p|^2 without a dot with A p.
 template <class PT, class RT>
@@ -98,21 +117,26 @@ __global__ void __launch_bounds__(kBlock) flush_x_kernel(const VecArgs A) {
 
 // Scalar kernel: fixed-order sums of a column's partials, then its update.
 // OP_ALPHA: <p, A p> = a * sum(pa) + sum(pb) (|p|^2 and |D_oe p|^2 partials);
+// OP_INIT_GUESS: |b|^2 = sum(pa), |r|^2 = sum(pb);
 // OP_BETA, OP_RU, OP_INIT, OP_FINAL: the one sum of pb.  The partials are
 // loaded before the column state so that the two latencies overlap.
 __global__ void __launch_bounds__(kBlock) reduce_kernel(ColState* st, const double* pa, const double* pb, int nblk,
                                                         int op) {
   const int c = blockIdx.x;
+  const bool two = op == OP_ALPHA || op == OP_INIT_GUESS;
   const double vb = strided_sum(pb + (size_t)c * nblk, nblk);
-  const double va = op == OP_ALPHA ? strided_sum(pa + (size_t)c * nblk, nblk) : 0.0;
+  const double va = two ? strided_sum(pa + (size_t)c * nblk, nblk) : 0.0;
   ColState& S = st[c];
   const int mask = (op == OP_ALPHA || op == OP_BETA) ? MASK_ACTIVE : (op == OP_RU ? MASK_RELIABLE : MASK_ALL);
   if (!state_on(S, mask)) return;
   __shared__ double sh[2][kBlock / 64];
   const double s = block_sum(vb, sh[0]);
-  if (op == OP_ALPHA) {
-    const double pp = block_sum(va, sh[1]);
-    if (threadIdx.x == 0) finalize_column(S, S.a * pp + s, OP_ALPHA);
+  if (two) {
+    const double sa = block_sum(va, sh[1]);
+    if (threadIdx.x == 0) {
+      if (op == OP_ALPHA) finalize_column(S, S.a * sa + s, OP_ALPHA);
+      else finalize_guess(S, sa, s);  // sa = |b|^2, s = |r|^2
+    }
   } else if (threadIdx.x == 0) {
     finalize_column(S, s, op);
   }
@@ -181,6 +205,8 @@ int launch_vec(int which, const VecArgs& a, int ncol, hipStream_t s) {
     init_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
   } else if (which == VK_P) {
     update_p_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
+  } else if (which == VK_GUESS) {
+    guess_kernel<PT, RT><<<grid, kBlock, 0, s>>>(a);
   } else if (which == VK_FLUSH) {
     if (!a.xs) return ASQ_EINVAL;
     flush_x_kernel<<<grid, kBlock, 0, s>>>(a);
@@ -200,7 +226,7 @@ int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hip
 }
 
 int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s) {
-  if (op == OP_ALPHA && !pa) return ASQ_EINVAL;
+  if ((op == OP_ALPHA || op == OP_INIT_GUESS) && !pa) return ASQ_EINVAL;
   reduce_kernel<<<(unsigned)ncol, kBlock, 0, s>>>(st, pa, pb, nblk, op);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }

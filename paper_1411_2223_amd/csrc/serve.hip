@@ -13,6 +13,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -20,6 +21,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -151,16 +153,32 @@ void destroy_run(asq_server* S, Run* r) {
   S->arena.release(r->off, r->bytes);
 }
 
+// Column slots of a run: max_cols for the largest registered field and up to
+// eight times as many for smaller ones, so that runs carry similar work per
+// iteration (a small field's requests would otherwise queue behind a few slots
+// while its kernels wait for the GPU beside the large fields' kernels).
+int run_capacity(const asq_server* S, const asq_gauge* g) {
+  long hmax = 1;
+  for (const asq_gauge* o : S->gauges) hmax = std::max(hmax, (long)o->geom.half);
+  const long ratio = std::max(1L, std::min(8L, hmax / std::max(1L, (long)g->geom.half)));
+  return (int)std::min(4096L, (long)S->max_cols * ratio);
+}
+
 // Create a run for (gauge, mode) if the arena and the stream budget allow it.
 Run* make_run(asq_server* S, const asq_gauge* g, const asq_cg_params& p) {
   if ((int)S->runs.size() >= S->max_streams) return nullptr;
-  const size_t need = batch_bytes(g, S->max_cols, p.mode, true);
+  int cap = run_capacity(S, g);
+  size_t need = batch_bytes(g, cap, p.mode, true);
   size_t off = 0;
-  if (!S->arena.alloc(need, &off)) return nullptr;
+  if (!S->arena.alloc(need, &off)) {
+    cap = S->max_cols;  // the arena decides: fall back to the base width
+    need = batch_bytes(g, cap, p.mode, true);
+    if (!S->arena.alloc(need, &off)) return nullptr;
+  }
   std::unique_ptr<Run> r(new Run());
   r->g = g;
   r->mode = p.mode;
-  r->cap = S->max_cols;
+  r->cap = cap;
   r->poll = p.poll_iters > 0 ? p.poll_iters : 8;
   r->use_graph = p.use_graph != 0;
   r->off = off;
@@ -222,7 +240,7 @@ bool admit(asq_server* S, Request* q) {
   // per-column constants, then b into the slots, then the init kernels
   Batch tmp = B;
   tmp.ncol = q->nrhs;
-  init_states(tmp, q->masses.data(), &p, run->staging + c0);
+  init_states(tmp, q->masses.data(), &p, run->staging + c0, nullptr);
   bool ok = hipMemcpyAsync(B.st + c0, run->staging + c0, q->nrhs * sizeof(ColState), hipMemcpyHostToDevice, s) ==
             hipSuccess;
   ok = ok && hipMemcpyAsync(B.b + (size_t)c0 * half * 6, q->b, (size_t)q->nrhs * half * 48,
@@ -362,9 +380,20 @@ void worker_main(asq_server* S) {
       need_run |= !has;
     }
     if (need_run) {
+      // While the streams cover every field in use (gauge and mode, running or
+      // queued), a field's only run is kept even when idle (small fields would
+      // otherwise lose their stream between requests); streams for a new field
+      // come from drained extra runs.
+      std::set<std::pair<const asq_gauge*, int>> fields;
+      for (auto& r : S->runs) fields.insert({r->g, r->mode});
+      for (Request* q : S->queue) fields.insert({S->gauges[q->gauge_id], q->params.mode});
+      const bool keep_last = (int)fields.size() <= S->max_streams;
       for (auto it = S->runs.begin(); it != S->runs.end();) {
         Run* r = it->get();
-        if (!r->in_flight && run_idle(r)) {
+        int same = 0;
+        for (auto& o : S->runs) same += !o->draining && o->g == r->g && o->mode == r->mode;
+        const bool last_of_field = !r->draining && same == 1;
+        if (!r->in_flight && run_idle(r) && !(keep_last && last_of_field)) {
           bool copies_pending = false;
           for (auto& kv : S->reqs)
             if (kv.second->state == 2 && kv.second->run == r) copies_pending = true;

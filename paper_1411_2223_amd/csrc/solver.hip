@@ -178,6 +178,28 @@ int enqueue_init(const Batch& B, int c0, int n, hipStream_t s) {
   return launch_reduce(OP_INIT, v.st, nullptr, v.partials, v.nblk, n, s);
 }
 
+// Start from the x in place: x_s = 0, p = 0, r = b - A x with the FP64 operator
+// (stored in the r tier), then bb, rr and the convergence check per column.
+int enqueue_init_guess(const Batch& B, hipStream_t s) {
+  const Gauge_t* g = B.g;
+  const void* L = g->links[LINK_F64_R18];
+  VecArgs v = vargs(B, 0);
+  v.partials = B.partials_p;
+  int rc = launch_vec_kernel(VK_GUESS, B.pt, B.rt, v, B.ncol, s);
+  if (rc) return rc;
+  DslashArgs d1 = dargs(B, 1, B.x, B.t64, MASK_ALL);
+  d1.links = L;
+  rc = launch_dslash(LINK_F64_R18, VEC_F64, VEC_F64, EPI_PLAIN, B.rt64_plain, d1, s);
+  if (rc) return rc;
+  DslashArgs d2 = dargs(B, 0, B.t64, B.r, MASK_ALL);
+  d2.links = L;
+  d2.y = B.x;
+  d2.b = B.b;
+  rc = launch_dslash(LINK_F64_R18, VEC_F64, B.rt, EPI_RESID, B.rt64_resid, d2, s);
+  if (rc) return rc;
+  return launch_reduce(OP_INIT_GUESS, B.st, B.partials_p, B.partials, g->nblk, B.ncol, s);
+}
+
 int enqueue_iteration(const Batch& B, hipStream_t s) {
   const Gauge_t* g = B.g;
   const void* L = g->links[B.link];
@@ -346,11 +368,11 @@ int check_params(const asq_gauge* g, const asq_cg_params* p) {
   return ASQ_OK;
 }
 
-void init_states(const Batch& B, const double* masses, const asq_cg_params* p, ColState* host) {
+void init_states(const Batch& B, const double* masses, const asq_cg_params* p, ColState* host, const double* tols) {
   for (int c = 0; c < B.ncol; ++c) {
     memset(&host[c], 0, sizeof(ColState));
     host[c].a = 4.0 * masses[c] * masses[c];
-    host[c].tol = p->tol;
+    host[c].tol = tols ? tols[c] : p->tol;
     host[c].delta = p->mode == ASQ_MODE_F64 ? 0.0 : p->delta;
     host[c].maxiter = p->maxiter;
   }
@@ -368,6 +390,12 @@ extern "C" size_t asq_workspace_bytes(const asq_gauge* g, int nrhs, int mode) {
 extern "C" int cg_solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev,
                               double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
                               asq_cg_stats* stats, void* hip_stream) {
+  return asq::solve_batch(g, nrhs, masses, nullptr, b_dev, x_dev, work_dev, work_bytes, params, stats, hip_stream);
+}
+
+int asq::solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double* tols, const double* b_dev,
+                     double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
+                     asq_cg_stats* stats, void* hip_stream, bool guess) {
   if (!g || nrhs <= 0 || !masses || !b_dev || !x_dev || !work_dev || !stats) {
     set_last_error("cg_solve_batch: null pointer or nrhs <= 0");
     return ASQ_EINVAL;
@@ -377,8 +405,8 @@ extern "C" int cg_solve_batch(const asq_gauge* g, int nrhs, const double* masses
     return ASQ_EINVAL;
   }
   for (int c = 0; c < nrhs; ++c)
-    if (!(masses[c] > 0) || !isfinite(masses[c])) {
-      set_last_error("cg_solve_batch: masses must be positive and finite");
+    if (!(masses[c] > 0) || !isfinite(masses[c]) || (tols && !(tols[c] > 0 && isfinite(tols[c])))) {
+      set_last_error("cg_solve_batch: masses (and tolerances) must be positive and finite");
       return ASQ_EINVAL;
     }
   if (((uintptr_t)b_dev & 15) || ((uintptr_t)x_dev & 15) || ((uintptr_t)work_dev & 255)) {
@@ -397,9 +425,9 @@ extern "C" int cg_solve_batch(const asq_gauge* g, int nrhs, const double* masses
   HostRes& H = host_res();
   if ((rc = H.ensure((size_t)nrhs))) return rc;
   ColState* mirror[2] = {H.pinned, H.pinned + nrhs};
-  init_states(B, masses, params, mirror[0]);
+  init_states(B, masses, params, mirror[0], tols);
   ASQ_HIP_TRY(hipMemcpyAsync(B.st, mirror[0], nrhs * sizeof(ColState), hipMemcpyHostToDevice, s));
-  if ((rc = enqueue_init(B, 0, nrhs, s))) return rc;
+  if ((rc = guess ? enqueue_init_guess(B, s) : enqueue_init(B, 0, nrhs, s))) return rc;
   // the mirror is reused below: make sure the upload has consumed it
   ASQ_HIP_TRY(hipStreamSynchronize(s));
 

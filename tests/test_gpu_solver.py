@@ -102,6 +102,112 @@ def test_batch_every_launch_variant(asq, mode, recon, monkeypatch):
         assert np.array_equal(x, x0), f"variant ({cols}, {pipe}, {order}) changes the solution"
 
 
+@pytest.mark.parametrize("mode", ["f64", "mixed32", "mixed16"])
+def test_multishift_every_mass_and_source(asq, mode):
+    # One shifted CG per source carries every mass; the refinement brings each
+    # (mass, source) column to the FP64 true residual, checked with the oracle.
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
+    masses = [0.05, 0.02, 0.2, 0.1]  # not sorted: the smallest is found
+    nsrc = 3
+    b = synth.make_sources(dims, nsrc, 71)
+    res = g.solve_multishift(masses, asq.vec_to_device(b, "f64"), mode=mode)
+    import torch
+
+    torch.cuda.synchronize()
+    assert res.rc == 0
+    x = asq.vec_from_device(res.x, len(masses) * nsrc, g.half, "f64")
+    for j, m in enumerate(masses):
+        for sidx in range(nsrc):
+            c = j * nsrc + sidx
+            r = oracle.true_residual(dims, fat, lng, m, b[sidx], x[c])
+            st = res.stats[c]
+            print(f"mode={mode} m={m} src={sidx} iters={st['iters']} resid={r:.3e}", flush=True)
+            assert st["converged"] == 1 and r <= TOL
+
+
+def test_multishift_matches_direct_solves(asq):
+    # Against dense solves on 4^3 x 8 at a loose tolerance, where the shifted
+    # phase does nearly all the work: every mass's error is within the condition
+    # number times the tolerance, and its residual within the tolerance.
+    dims = (4, 4, 4, 8)
+    fat, lng = gauge_arrays(dims, 0.3, 14112223)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    masses = [0.1, 0.3, 0.05]
+    b = synth.make_sources(dims, 2, 72)
+    tol = 1e-6
+    res = g.solve_multishift(masses, asq.vec_to_device(b, "f64"), mode="mixed32", tol=tol)
+    assert res.rc == 0
+    x = asq.vec_from_device(res.x, len(masses) * 2, g.half, "f64")
+    for j, m in enumerate(masses):
+        A = oracle.dense_operator(lambda v, m=m: oracle.apply_A(dims, fat, lng, m, v), g.half)
+        cond = np.linalg.cond(A)
+        for sidx in range(2):
+            xd = np.linalg.solve(A, b[sidx].reshape(-1)).reshape(g.half, 3)
+            err = np.linalg.norm(x[j * 2 + sidx] - xd) / np.linalg.norm(xd)
+            r = oracle.true_residual(dims, fat, lng, m, b[sidx], x[j * 2 + sidx])
+            print(f"m={m} src={sidx} resid {r:.3e} rel err vs dense {err:.3e} cond {cond:.1f}", flush=True)
+            assert r <= tol
+            assert err <= cond * tol
+
+
+def _full_apply(dims, fat, lng, m, xe, xo):
+    """M x = 2m x + D x on both parities, composed from the oracle's one-parity D."""
+    return (2 * m * xe + oracle.dslash(dims, fat, lng, 0, xo), 2 * m * xo + oracle.dslash(dims, fat, lng, 1, xe))
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed32", "mixed16"])
+def test_full_system_solve(asq, mode):
+    # M x = b on both parities (M = 2m + D) through the even-odd reduction and the
+    # odd-site reconstruction: the oracle's M applied to the GPU's x leaves a
+    # relative residual <= tol, and the reported residual is that one.
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
+    masses = [0.1, 0.05, 0.2]
+    n = len(masses)
+    v = synth.make_sources(dims, 2 * n, 61)  # even halves, then odd halves
+    bd = asq.vec_to_device(v, "f64")
+    res = g.solve_full(masses, bd, mode=mode)
+    import torch
+
+    torch.cuda.synchronize()
+    assert res.rc == 0
+    x = asq.vec_from_device(res.x, 2 * n, g.half, "f64")
+    for c, m in enumerate(masses):
+        re, ro = _full_apply(dims, fat, lng, m, x[c], x[n + c])
+        r = np.sqrt(np.sum(np.abs(v[c] - re) ** 2) + np.sum(np.abs(v[n + c] - ro) ** 2))
+        r /= np.sqrt(np.sum(np.abs(v[c]) ** 2) + np.sum(np.abs(v[n + c]) ** 2))
+        st = res.stats[c]
+        print(f"mode={mode} m={m} iters={st['iters']} resid={r:.3e} gpu_resid={st['true_resid']:.3e}", flush=True)
+        assert st["converged"] == 1 and r <= TOL
+        assert abs(st["true_resid"] - r) <= 1e-3 * r + 1e-15
+
+
+def test_full_system_matches_dense_solve(asq):
+    # brute force on 4^3 x 8: the dense M (both parities) solved directly
+    dims, m = (4, 4, 4, 8), 0.1
+    fat, lng = gauge_arrays(dims, 0.3, 14112223)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    half = g.half
+    v = synth.make_sources(dims, 2, 62)
+    res = g.solve_full([m], asq.vec_to_device(v, "f64"), mode="mixed32")
+    assert res.rc == 0
+    x = asq.vec_from_device(res.x, 2, half, "f64")
+
+    def apply_m(z):
+        z = z.reshape(2, half, 3)
+        re, ro = _full_apply(dims, fat, lng, m, z[0], z[1])
+        return np.stack([re, ro])
+
+    M = oracle.dense_operator(apply_m, 2 * half)
+    xd = np.linalg.solve(M, v.reshape(-1)).reshape(2, half, 3)
+    err = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+    print(f"dense full solve: rel err {err:.3e} cond {np.linalg.cond(M):.2e}", flush=True)
+    assert err <= 1e-8
+
+
 def test_graph_matches_eager(asq):
     dims = (6, 4, 8, 10)
     fat, lng = gauge_arrays(dims, 0.3, 5)
