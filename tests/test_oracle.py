@@ -175,6 +175,29 @@ def test_anti_hermiticity(dims):
     assert abs(lhs - rhs) < 1e-14 * abs(lhs) * 10
 
 
+def test_full_operator_composition():
+    # M = 2m + D on both parities, composed from the one-parity D as the
+    # full-system GPU tests compose it: since D is anti-Hermitian every
+    # eigenvalue of M has real part 2m, and M^dag M restricted to even sites is
+    # exactly A = 4m^2 - D_eo D_oe.  A transposed parity or a sign slip in the
+    # composition breaks one of the two.
+    dims, m = (4, 4, 4, 8), 0.07
+    fat, lng = synth.make_gauge(dims, 0.3, 8)
+    half = int(np.prod(dims)) // 2
+
+    def apply_m(z):
+        z = z.reshape(2, half, 3)
+        return np.stack([2 * m * z[0] + oracle.dslash(dims, fat, lng, 0, z[1]),
+                         2 * m * z[1] + oracle.dslash(dims, fat, lng, 1, z[0])])
+
+    M = oracle.dense_operator(apply_m, 2 * half)
+    ev = np.linalg.eigvals(M)
+    assert np.max(np.abs(ev.real - 2 * m)) < 1e-12
+    A = oracle.dense_operator(lambda v: oracle.apply_A(dims, fat, lng, m, v), half)
+    n = half * 3
+    assert np.max(np.abs((M.conj().T @ M)[:n, :n] - A)) < 1e-12
+
+
 def _split(dims, g_lex, vec_full):
     """Apply per-site SU(3) g to a vector given on all sites in lexicographic order."""
     return np.einsum("sij,sj->si", g_lex, vec_full)
