@@ -272,7 +272,7 @@ extern "C" int cg_solve_multishift(const asq_gauge* g, int nsrc, int nmass, cons
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int c = 0; c < ncol; ++c) stats[c].seconds = secs;
   if (log_enabled())
-    fprintf(stderr, "[asq] multishift nsrc=%d nmass=%d phase-1 iters %d, total %.3f s\\n", nsrc, nmass,
+    fprintf(stderr, "[asq] multishift nsrc=%d nmass=%d phase-1 iters %d, total %.3f s\n", nsrc, nmass,
             it1[j0 * nsrc], secs);
   return rc;
 }

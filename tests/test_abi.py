@@ -81,6 +81,14 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert asq.serve_submit(None, 0, 1, m, 16, 16, ctypes.byref(params), None) == asq.ASQ_EINVAL
     assert asq.serve_poll(None, 1, None, None) == asq.ASQ_EINVAL
     assert asq.asq_copy_probe(16, 16, 15, None) == asq.ASQ_EINVAL
+    assert asq.asq_read_probe(16, 15, 16, None) == asq.ASQ_EINVAL
+    assert asq.asq_read_probe(None, 16, 16, None) == asq.ASQ_EINVAL
+    assert asq.asqtad_dslash_eo_variant(None, 0, 0, 1, 16, 16, 1, None) == asq.ASQ_EINVAL
+    assert asq.cg_solve_full(None, 1, m, 16, 16, 256, 1, ctypes.byref(params), stats, None) == asq.ASQ_EINVAL
+    assert asq.asq_full_workspace_bytes(None, 1, 0) == 0
+    assert asq.cg_solve_multishift(None, 1, 1, m, 16, 16, 256, 1, ctypes.byref(params), stats,
+                                   None) == asq.ASQ_EINVAL
+    assert asq.asq_multishift_workspace_bytes(None, 1, 1, 0) == 0
 
 
 def test_magic_division_formula():
