@@ -182,6 +182,28 @@ __device__ __forceinline__ void pipe_run(const DslashArgs& A, int i, const Site&
   if constexpr (K + 1 < 16) pipe_run<Link, InT, R, K + 1>(A, i, s, on, col, in, st, acc);
 }
 
+// alpha of column c from its reduced |p|^2 and |t|^2 partial sums: false (and
+// the column stopped, by one block) when <p, A p> is not positive and finite.
+// Block 0 also leaves the record the scalar kernel would have left; no block of
+// the launch reads those fields.
+__device__ __forceinline__ bool fold_alpha(const DslashArgs& A, int c, int sblk, double pp, double tt,
+                                           double& alpha) {
+  ColState& S = A.st[c];
+  const double pAp = S.a * pp + tt;
+  const bool ok = isfinite(pAp) && pAp > 0;
+  alpha = ok ? S.rr / pAp : 0.0;
+  if (sblk == 0 && threadIdx.x == 0) {
+    S.pAp = pAp;
+    if (ok) {
+      S.alpha = alpha;
+    } else {
+      S.status = ASQ_ENAN;
+      S.active = 0;
+    }
+  }
+  return ok;
+}
+
 // The column's new direction buffer (pbuf == 0: the alternate one).
 __device__ __forceinline__ const void* pick_new(const DslashArgs& A, const void* base, const void* alt, int c) {
   return A.st[c].pbuf ? base : alt;
@@ -226,37 +248,41 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     in[r] = (on[r] && A.in_sel) ? pick_new(A, A.in, A.in_alt, c) : A.in;
   }
   if (!any) return;  // uniform over the block
-  // alpha of each column for the UPDATE epilogue: formed here from the partials
-  // for the narrow tiles of small batches, read from the column state otherwise
+  // alpha of each column for the UPDATE epilogue: formed in this launch from the
+  // partials for the narrow tiles of small batches (same order and tree as the
+  // scalar kernel), read from the column state otherwise.  Up to 4 kBlock
+  // partials per column, the loads are issued here and summed after the hop
+  // loop, which hides their latency; longer sums are done here.
   [[maybe_unused]] double alpha[R];
+  [[maybe_unused]] double qa[R][4], qb[R][4];
+  [[maybe_unused]] bool deferred = false;
   if constexpr (EPI == EPI_UPDATE && R <= kFoldAlphaMaxTile) {
     if (A.apa) {
-      // alpha = rr / (a |p|^2 + |t|^2) from the partials of update_p and D_oe; the
-      // loads are issued here so that their latency overlaps the hop loop's start
-      __shared__ double sa[2 * (kBlock / 64 + 1)];
+      deferred = A.nblk <= 4 * kBlock;
+      if (deferred) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        alpha[r] = 0;
-        if (!on[r]) continue;  // uniform over the block
-        const int c = c0 + r;
-        double pp = strided_sum(A.apa + (size_t)c * A.nblk, A.nblk);
-        double tt = strided_sum(A.apb + (size_t)c * A.nblk, A.nblk);
-        block_sum2_all(pp, tt, sa);
-        ColState& S = A.st[c];
-        const double pAp = S.a * pp + tt;
-        const bool ok = isfinite(pAp) && pAp > 0;
-        if (ok) alpha[r] = S.rr / pAp;
-        on[r] = ok;  // every block takes the same decision
-        if (sblk == 0 && threadIdx.x == 0) {
-          // the record the scalar kernel would have left; no block of this
-          // launch reads these fields
-          S.pAp = pAp;
-          if (ok) {
-            S.alpha = alpha[r];
-          } else {
-            S.status = ASQ_ENAN;
-            S.active = 0;
+        for (int r = 0; r < R; ++r) {
+          const double* pa = A.apa + (size_t)(c0 + r) * A.nblk;
+          const double* pb = A.apb + (size_t)(c0 + r) * A.nblk;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = tid + q * kBlock;
+            const bool in = on[r] && k < A.nblk;
+            qa[r][q] = in ? pa[k] : 0.0;
+            qb[r][q] = in ? pb[k] : 0.0;
           }
+        }
+      } else {
+        __shared__ double sa[2 * (kBlock / 64 + 1)];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          alpha[r] = 0;
+          if (!on[r]) continue;  // uniform over the block
+          const int c = c0 + r;
+          double pp = strided_sum(A.apa + (size_t)c * A.nblk, A.nblk);
+          double tt = strided_sum(A.apb + (size_t)c * A.nblk, A.nblk);
+          block_sum2_all(pp, tt, sa);
+          on[r] = fold_alpha(A, c, sblk, pp, tt, alpha[r]);  // every block takes the same decision
         }
       }
     }
@@ -292,6 +318,26 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
         if (on[r]) OutT::store(A.out, half, c0 + r, i, convert<typename OutT::real>(acc[r]));
     }
   } else {
+    if constexpr (EPI == EPI_UPDATE && R <= kFoldAlphaMaxTile) {
+      if (deferred) {
+        // the sums of the partials loaded before the hop loop (strided_sum's order)
+        __shared__ double sa[2 * (kBlock / 64 + 1)];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          alpha[r] = 0;
+          if (!on[r]) continue;  // uniform over the block
+          double pp = 0, tt = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (tid + q * kBlock < A.nblk) {
+              pp += qa[r][q];
+              tt += qb[r][q];
+            }
+          block_sum2_all(pp, tt, sa);
+          on[r] = fold_alpha(A, c0 + r, sblk, pp, tt, alpha[r]);
+        }
+      }
+    }
     // Block partials of |out|^2 per column over the kBlock sites: a wave tree,
     // then the four wave sums in order (the tree and order of block_sum).
     __shared__ double sh[R][kBlock / 64];
