@@ -286,7 +286,7 @@ class Gauge:
         n = asq_workspace_bytes(self.handle, int(nrhs), MODES[mode])
         return empty_bytes(n, self.device)
 
-    def solve(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.1, poll_iters=8, use_graph=True,
+    def solve(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.01, poll_iters=16, use_graph=True,
               work=None, x=None, stream=None):
         """Batched CG: b is a device tensor [nrhs][3][V/2][2] float64; returns SolveResult."""
         torch = _torch()
@@ -306,7 +306,7 @@ class Gauge:
             check(rc, "cg_solve_batch")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
 
-    def solve_multishift(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.1, poll_iters=8,
+    def solve_multishift(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.01, poll_iters=16,
                          use_graph=True, work=None, x=None, stream=None):
         """Every (mass, source) pair: b is a device tensor [nsrc][3][V/2][2] float64; x is
         [nmass][nsrc][3][V/2][2] (column j * nsrc + s); returns SolveResult over those columns."""
@@ -328,7 +328,7 @@ class Gauge:
             check(rc, "cg_solve_multishift")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
 
-    def solve_full(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.1, poll_iters=8,
+    def solve_full(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.01, poll_iters=16,
                    use_graph=True, work=None, x=None, stream=None):
         """M x = b on both parities (M = 2m + D): b is a device tensor [2][nrhs][3][V/2][2] float64
         (even halves, then odd halves); returns SolveResult with |b - M x| / |b| per column."""
@@ -368,7 +368,7 @@ class Server:
         self.gauges.append(gauge)
         return gid.value
 
-    def submit(self, gauge_id, masses, b, x, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.1, poll_iters=8,
+    def submit(self, gauge_id, masses, b, x, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.01, poll_iters=8,
                use_graph=True):
         masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
         n = len(masses)

@@ -65,7 +65,7 @@ def test_same_alone_and_in_the_mix(asq, max_cols, max_streams):
     for k, (li, masses, b) in enumerate(reqs):
         bd = asq.vec_to_device(b, "f64")
         x = torch.empty_like(bd)
-        t = srv.submit(gids[li], masses, bd, x, mode="mixed32")
+        t = srv.submit(gids[li], masses, bd, x, mode="mixed32", delta=0.01, poll_iters=8)
         tickets[t] = len(masses)
         xs[t] = (k, bd, x)
     res = _wait(srv, tickets)
@@ -80,7 +80,7 @@ def test_same_alone_and_in_the_mix(asq, max_cols, max_streams):
         xm = asq.vec_from_device(x, len(masses), gauges[li].half, "f64")
         r = oracle_resid_cols(dims, fat, lng, masses, b, xm)
         assert np.all(r <= 1e-10)
-        alone = gauges[li].solve(masses, bd, mode="mixed32")
+        alone = gauges[li].solve(masses, bd, mode="mixed32", delta=0.01, poll_iters=8)  # the server's parameters
         torch.cuda.synchronize()
         xa = asq.vec_from_device(alone.x, len(masses), gauges[li].half, "f64")
         assert [s["iters"] for s in alone.stats] == [s["iters"] for s in stats]
