@@ -231,6 +231,7 @@ class Gauge:
         load()
         self.dims = tuple(int(d) for d in dims)
         self.half = int(np.prod(self.dims)) // 2
+        self.precs = tuple(precs)
         mask = 0
         for p in precs:
             mask |= 1 << PRECS[p]
@@ -282,11 +283,17 @@ class Gauge:
             check(rc, "asqtad_dslash_eo_variant")
         return out
 
+    def default_delta(self, mode):
+        """Reliable-update trigger: 0.01, or 0.1 when the FP16 tier iterates with 16-bit
+        links (their rounding makes the iterated residual drift faster: at 48^3 x 96 the
+        three-level solve needs 454 iterations with 0.1 and 1047 with 0.01)."""
+        return 0.1 if mode == "mixed16" and "f16" in self.precs else 0.01
+
     def workspace(self, nrhs, mode="mixed32"):
         n = asq_workspace_bytes(self.handle, int(nrhs), MODES[mode])
         return empty_bytes(n, self.device)
 
-    def solve(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.01, poll_iters=16, use_graph=True,
+    def solve(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=None, poll_iters=16, use_graph=True,
               work=None, x=None, stream=None):
         """Batched CG: b is a device tensor [nrhs][3][V/2][2] float64; returns SolveResult."""
         torch = _torch()
@@ -296,6 +303,8 @@ class Gauge:
             work = self.workspace(nrhs, mode)
         if x is None:
             x = torch.empty_like(b)
+        if delta is None:
+            delta = self.default_delta(mode)
         params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
                                1 if use_graph else 0)
         stats = (asq_cg_stats * nrhs)()
@@ -306,7 +315,7 @@ class Gauge:
             check(rc, "cg_solve_batch")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
 
-    def solve_multishift(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.01, poll_iters=16,
+    def solve_multishift(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=None, poll_iters=16,
                          use_graph=True, work=None, x=None, stream=None):
         """Every (mass, source) pair: b is a device tensor [nsrc][3][V/2][2] float64; x is
         [nmass][nsrc][3][V/2][2] (column j * nsrc + s); returns SolveResult over those columns."""
@@ -318,6 +327,8 @@ class Gauge:
             work = empty_bytes(asq_multishift_workspace_bytes(self.handle, nsrc, nmass, MODES[mode]), self.device)
         if x is None:
             x = torch.empty(nmass * b.numel(), dtype=b.dtype, device=b.device)
+        if delta is None:
+            delta = self.default_delta(mode)
         params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
                                1 if use_graph else 0)
         stats = (asq_cg_stats * (nmass * nsrc))()
@@ -328,7 +339,7 @@ class Gauge:
             check(rc, "cg_solve_multishift")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
 
-    def solve_full(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.01, poll_iters=16,
+    def solve_full(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=None, poll_iters=16,
                    use_graph=True, work=None, x=None, stream=None):
         """M x = b on both parities (M = 2m + D): b is a device tensor [2][nrhs][3][V/2][2] float64
         (even halves, then odd halves); returns SolveResult with |b - M x| / |b| per column."""
@@ -339,6 +350,8 @@ class Gauge:
             work = empty_bytes(asq_full_workspace_bytes(self.handle, nrhs, MODES[mode]), self.device)
         if x is None:
             x = torch.empty_like(b)
+        if delta is None:
+            delta = self.default_delta(mode)
         params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
                                1 if use_graph else 0)
         stats = (asq_cg_stats * nrhs)()
@@ -368,10 +381,12 @@ class Server:
         self.gauges.append(gauge)
         return gid.value
 
-    def submit(self, gauge_id, masses, b, x, mode="mixed32", tol=1e-10, maxiter=20000, delta=0.01, poll_iters=8,
+    def submit(self, gauge_id, masses, b, x, mode="mixed32", tol=1e-10, maxiter=20000, delta=None, poll_iters=8,
                use_graph=True):
         masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
         n = len(masses)
+        if delta is None:
+            delta = self.gauges[gauge_id].default_delta(mode)
         params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
                                1 if use_graph else 0)
         t = ctypes.c_uint64()
