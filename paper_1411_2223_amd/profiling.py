@@ -180,34 +180,51 @@ def write_counters(fetch_csv: str, write_csv: str, run_dir: str, lattice: str = 
         f.write("\n".join(lines) + "\n")
 
 
-def write_valu(counter_csv: str, stats_csv: str, out: str, command: str, lattice: str = "20x20x20x64",
+def trace_durations(trace_csv: str) -> dict:
+    """(kernel name, grid size in threads) -> durations in ns, in dispatch order, from a
+    rocprofv3 kernel_trace.csv."""
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        key = (r["Kernel_Name"], int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+        acc[key].append((int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    return {k: [d for _, d in sorted(v)] for k, v in acc.items()}
+
+
+def write_valu(counter_csv: str, trace_csv: str, out: str, command: str, lattice: str = "20x20x20x64",
                clock_ghz: float = 2.4, cus: int = 256) -> None:
     """VALU issue utilization of the timed Dslash launches: SQ_INSTS_VALU per launch (wave
     instructions; a wave64 VALU instruction occupies its 16-lane SIMD for 4 cycles, so a
-    CU issues at most one per cycle) over cus x clock x the launch's duration from a
-    kernel-trace run (counter runs serialize and slow the kernels)."""
+    CU issues at most one per cycle) over cus x clock x the launch's duration, taken from a
+    kernel-trace run of the same command (counter runs serialize and slow the kernels)."""
     spec = KERNELS_ONLY[lattice]
     nblk = (HALF[lattice] + 255) // 256
-    dur = {short_name(r["Name"]): float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    durs = trace_durations(trace_csv)
+    full = counter_means(counter_csv, "SQ_INSTS_VALU", by_grid=True)
     lines = [f"# Dslash VALU issue utilization, {lattice}", "", "Commands (repository root on the MI355X box):", "",
              "    " + command,
-             f"    python -m paper_1411_2223_amd.profiling write-valu {counter_csv} {stats_csv} --out {out}", "",
+             f"    python -m paper_1411_2223_amd.profiling write-valu {counter_csv} {trace_csv} --out {out} "
+             f"--command '...'", "",
              "Utilization = SQ_INSTS_VALU / (CUs x clock x duration): a CU issues at most one wave64 VALU",
-             f"instruction per cycle (4 SIMDs, 4 cycles each); {cus} CUs at {clock_ghz} GHz.  Durations are the",
-             "average of the same kernel in the kernel-trace run (the timed public launches dominate it).", "",
+             f"instruction per cycle (4 SIMDs, 4 cycles each); {cus} CUs at {clock_ghz} GHz.  Both figures are",
+             "averages over the timed launches of the variant the autotuner chose (the last dispatches of",
+             "that kernel and grid); durations come from the kernel-trace run.", "",
              "| key | kernel | VALU wave-instructions per launch | flops per VALU lane-op | duration us | VALU issue |",
              "|---|---|---|---|---|---|"]
     for key in [k for k in spec if k != "workload"]:
         prefix, alg, ncol, last = spec[key]
-        valu = counter_means(counter_csv, "SQ_INSTS_VALU", by_grid=True, last=last)
-        hits = [(k, g) for (k, g) in valu if short_name(k).startswith(prefix) and short_name(k).split(", ")[4] == "0"
-                and g == nblk * 256 * -(-ncol // int(short_name(k).split(", ")[3]))]
+
+        def tile(name):
+            return int(short_name(name).split(", ")[3])
+
+        hits = [(k, g) for (k, g) in full if short_name(k).startswith(prefix) and short_name(k).split(", ")[4] == "0"
+                and g == nblk * 256 * -(-ncol // tile(k))]
         if not hits:
             continue
-        k = max(hits, key=lambda h: valu[h][0])
-        n_valu = valu[k][1]
-        d_us = dur.get(short_name(k[0]), float("nan")) / 1e3
-        util = n_valu / (cus * clock_ghz * 1e3 * d_us) if d_us == d_us else float("nan")
+        k = max(hits, key=lambda h: full[h][0])
+        n_valu = counter_means(counter_csv, "SQ_INSTS_VALU", by_grid=True, last=last)[k][1]
+        d = durs.get(k, [])[-last:]
+        d_us = sum(d) / len(d) / 1e3 if d else float("nan")
+        util = n_valu / (cus * clock_ghz * 1e3 * d_us) if d else float("nan")
         flops = 1146.0 * HALF[lattice] * ncol
         lines.append(f"| `{key}` | `{short_name(k[0])}` | {n_valu:.3e} | {flops / (64 * n_valu):.2f} | {d_us:.1f} | "
                      f"{util:.2f} |")
@@ -256,13 +273,13 @@ def main():
     s5.add_argument("--top", type=int, default=14)
     s6 = sub.add_parser("write-valu")
     s6.add_argument("counter_csv")
-    s6.add_argument("stats_csv")
+    s6.add_argument("trace_csv")
     s6.add_argument("--out", required=True)
     s6.add_argument("--command", required=True)
     s6.add_argument("--lattice", default="20x20x20x64", choices=sorted(KERNELS_ONLY))
     a = ap.parse_args()
     if a.cmd == "write-valu":
-        write_valu(a.counter_csv, a.stats_csv, a.out, a.command, a.lattice)
+        write_valu(a.counter_csv, a.trace_csv, a.out, a.command, a.lattice)
         return
     if a.cmd == "write-counters":
         write_counters(a.fetch_csv, a.write_csv, a.dir, a.lattice)
