@@ -7,7 +7,7 @@ shares no code with the HIP path.
 Every function takes the canonical host arrays produced by ``synth``:
 links complex128 (V, 4, 3, 3), even/odd colour vectors complex128 (V/2, 3).
 
-Pins (tests/test_oracle_*.py) tie it to facts that do not come from itself:
+Pins (tests/test_oracle.py) tie it to facts that do not come from itself:
 free-field plane-wave spectrum (closed form), anti-Hermiticity of D, gauge
 covariance, hand-derived point-source values, brute-force dense solves and the
 finite termination of CG on an operator with few distinct eigenvalues.

@@ -86,7 +86,7 @@ struct alignas(128) ColState {
 static_assert(sizeof(ColState) == 128, "ColState layout");
 
 // Scalar updates applied to a column from its reduced sums (see asq_reduce.h).
-enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_FINAL = 4, OP_INIT_GUESS = 5 };
+enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_INIT_GUESS = 5 };
 
 struct DslashArgs {
   Geom g;

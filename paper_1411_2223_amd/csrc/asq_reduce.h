@@ -90,9 +90,6 @@ __device__ inline void finalize_column(ColState& S, double s, int op) {
         S.frozen = 0;
       }
       break;
-    case OP_FINAL:
-      S.true_rr = s;
-      break;
   }
 }
 

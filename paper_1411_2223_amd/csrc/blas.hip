@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(kBlock) flush_x_kernel(const VecArgs A) {
 // Scalar kernel: fixed-order sums of a column's partials, then its update.
 // OP_ALPHA: <p, A p> = a * sum(pa) + sum(pb) (|p|^2 and |D_oe p|^2 partials);
 // OP_INIT_GUESS: |b|^2 = sum(pa), |r|^2 = sum(pb);
-// OP_BETA, OP_RU, OP_INIT, OP_FINAL: the one sum of pb.  The partials are
+// OP_BETA, OP_RU, OP_INIT: the one sum of pb.  The partials are
 // loaded before the column state so that the two latencies overlap.
 __global__ void __launch_bounds__(kBlock) reduce_kernel(ColState* st, const double* pa, const double* pb, int nblk,
                                                         int op) {
