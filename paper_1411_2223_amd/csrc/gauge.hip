@@ -234,7 +234,11 @@ extern "C" int asq_gauge_create(const asq_gauge_desc* desc, const double* fat_de
   g->base = storage_dev;
   g->bytes = storage_bytes;
   g->nblk = (g->geom.half + kBlock - 1) / kBlock;
-  hipGetDevice(&g->device);
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    delete g;
+    set_last_error("asq_gauge_create: no current HIP device");
+    return ASQ_EHIP;
+  }
   char* b = (char*)storage_dev;
   for (int k = 0; k < LINK_KINDS; ++k) g->links[k] = off[k] == (size_t)-1 ? nullptr : b + off[k];
   g->sloppy_link32 = desc->recon == 12 ? LINK_F32_R12 : LINK_F32_R18;
