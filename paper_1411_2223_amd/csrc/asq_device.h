@@ -235,6 +235,22 @@ struct LinkF64R18 {
     }
     return U;
   }
+  // The same with non-temporal loads: the FP64 links of a lattice like 20^3 x 64
+  // (590 MB) cannot stay in the memory-side cache between launches, so streaming
+  // them past the caches leaves more room for the neighbour vectors.
+  __device__ __forceinline__ static Mat3<double> load_streaming(const void* base, int half, int p, int slot,
+                                                               int i) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* q = reinterpret_cast<const d2*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    Mat3<double> U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const d2 v = __builtin_nontemporal_load(q + (size_t)k * half);
+      U.e[k / 3][k % 3].re = v.x;
+      U.e[k / 3][k % 3].im = v.y;
+    }
+    return U;
+  }
 };
 
 struct LinkF32R18 {

@@ -23,6 +23,7 @@
 //   EPI_RESID   out = b - a y + D in in FP64 (the true residual), stored in the
 //               output tier as the new iterated r; block partials of |out|^2
 #pragma once
+#include <type_traits>
 
 #include "asq_reduce.h"
 
@@ -71,6 +72,16 @@ __device__ __forceinline__ void term(const typename InT::raw& w, const Mat3<type
   }
 }
 
+// The link of a term.  One-column FP64 launches stream their links (measured:
+// FP64 CG at 20^3 x 64 104 instead of 110 ms); with several columns the tiles of
+// a site block share each link through L2, and the FP32 tiers reuse theirs
+// through the memory-side cache across launches, so they load normally.
+template <class Link, int R>
+__device__ __forceinline__ Mat3<typename Link::real> load_link(const void* base, int half, int p, int slot, int i) {
+  if constexpr (R == 1 && std::is_same<Link, LinkF64R18>::value) return Link::load_streaming(base, half, p, slot, i);
+  else return Link::load(base, half, p, slot, i);
+}
+
 // One link term for R columns: all R neighbour loads are issued together
 // (columns past the batch read its last column, so no branch is needed), then
 // each active column accumulates under its own uniform branch.
@@ -79,7 +90,7 @@ __device__ __forceinline__ void link_term(const DslashArgs& A, int p, int slot, 
                                           const bool (&on)[R], const int (&col)[R], const void* const (&in)[R],
                                           typename InT::real scale, bool neg, Vec3<typename InT::real> (&acc)[R]) {
   using real = typename InT::real;
-  const Mat3<real> U = Link::load(A.links, half, p, slot, site);
+  const Mat3<real> U = load_link<Link, R>(A.links, half, p, slot, site);
   typename InT::raw w[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) w[r] = fetch<InT>(in[r], half, col[r], j);
@@ -149,7 +160,7 @@ __device__ __forceinline__ void stage_load(const DslashArgs& A, int i, const Sit
   const int half = A.g.half;
   const int p = A.out_parity;
   const int j = neighbour<T::MU>(A.g, i, s, T::hop);
-  st.U = Link::load(A.links, half, T::back ? 1 - p : p, T::slot, T::back ? j : i);
+  st.U = load_link<Link, R>(A.links, half, T::back ? 1 - p : p, T::slot, T::back ? j : i);
 #pragma unroll
   for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, col[r], j);
 }

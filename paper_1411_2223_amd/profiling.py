@@ -4,7 +4,7 @@ measured on (a counter figure is only reported while those sources are unchanged
 
     python -m paper_1411_2223_amd.profiling stats <kernel_stats.csv> [--top N]
     python -m paper_1411_2223_amd.profiling counters <fetch counter_collection.csv> <write counter_collection.csv>
-    python -m paper_1411_2223_amd.profiling write-counters <fetch csv> <write csv> --dir <run dir> [--lattice L]
+    python -m paper_1411_2223_amd.profiling write-counters <fetch csv> <write csv> [--lattice L]
     python -m paper_1411_2223_amd.profiling write-stats <kernel_stats.csv> <bench log> --out <md> --title T --command C
 """
 from __future__ import annotations
@@ -99,7 +99,7 @@ COPY_KERNEL = "copy_kernel"
 COPY_BYTES = 1 << 30
 
 
-def write_counters(fetch_csv: str, write_csv: str, run_dir: str, lattice: str = "20x20x20x64") -> None:
+def write_counters(fetch_csv: str, write_csv: str, lattice: str = "20x20x20x64") -> None:
     """profiles/dslash_counters_<lattice>.json (read by bench.py) and its Markdown summary."""
     spec = KERNELS_ONLY[lattice]
     fetch = counter_means(fetch_csv, "FETCH_SIZE", by_grid=True)
@@ -141,12 +141,12 @@ def write_counters(fetch_csv: str, write_csv: str, run_dir: str, lattice: str = 
         kernels[key] = {"FETCH_SIZE_KiB": fl[1], "WRITE_SIZE_KiB": wl_[1], "dispatches": fl[0],
                         "kernel": short_name(k[0]), "grid_threads": k[1]}
     wl = "" if spec["workload"] == "single_20x20x20x64" else f"--workload {spec['workload']} "
-    cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {run_dir}/fetch -o k -- python -u bench.py "
-            f"{wl}--kernels-only",
-            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {run_dir}/write -o k -- python -u bench.py "
-            f"{wl}--kernels-only",
-            f"python -m paper_1411_2223_amd.profiling write-counters {fetch_csv} {write_csv} --dir {run_dir} "
-            f"--lattice {lattice}"]
+    # each pass wrote its CSV into the directory given to -d
+    cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {os.path.dirname(fetch_csv)} -o k -- "
+            f"python -u bench.py {wl}--kernels-only",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {os.path.dirname(write_csv)} -o k -- "
+            f"python -u bench.py {wl}--kernels-only",
+            f"python -m paper_1411_2223_amd.profiling write-counters {fetch_csv} {write_csv} --lattice {lattice}"]
     out = {"kernel_source_sha": h, "lattice": lattice, "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
            "calibration": {"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES,
                            "copy_FETCH_SIZE_KiB": fetch[copy][1], "copy_WRITE_SIZE_KiB": write[copy][1]},
@@ -261,7 +261,6 @@ def main():
     s4 = sub.add_parser("write-counters")
     s4.add_argument("fetch_csv")
     s4.add_argument("write_csv")
-    s4.add_argument("--dir", required=True)
     s4.add_argument("--lattice", default="20x20x20x64", choices=sorted(KERNELS_ONLY))
     s5 = sub.add_parser("write-stats")
     s5.add_argument("csv")
@@ -282,7 +281,7 @@ def main():
         write_valu(a.counter_csv, a.trace_csv, a.out, a.command, a.lattice)
         return
     if a.cmd == "write-counters":
-        write_counters(a.fetch_csv, a.write_csv, a.dir, a.lattice)
+        write_counters(a.fetch_csv, a.write_csv, a.lattice)
         return
     if a.cmd == "write-stats":
         write_stats(a.csv, a.log, a.out, a.title, a.command, a.top, a.note)
