@@ -143,13 +143,15 @@ namespace {
 
 constexpr size_t kMaxQueue = 1 << 16;
 
+// Teardown: errors are ignored, each handle is released whatever happened to
+// the stream.
 void destroy_run(asq_server* S, Run* r) {
-  if (r->stream) hipStreamSynchronize(r->stream);
-  if (r->exec) hipGraphExecDestroy(r->exec);
-  if (r->ev) hipEventDestroy(r->ev);
-  if (r->stream) hipStreamDestroy(r->stream);
-  if (r->pinned) hipHostFree(r->pinned);
-  if (r->staging) hipHostFree(r->staging);
+  if (r->stream) (void)hipStreamSynchronize(r->stream);
+  if (r->exec) (void)hipGraphExecDestroy(r->exec);
+  if (r->ev) (void)hipEventDestroy(r->ev);
+  if (r->stream) (void)hipStreamDestroy(r->stream);
+  if (r->pinned) (void)hipHostFree(r->pinned);
+  if (r->staging) (void)hipHostFree(r->staging);
   S->arena.release(r->off, r->bytes);
 }
 
@@ -262,11 +264,33 @@ bool admit(asq_server* S, Request* q) {
   return true;
 }
 
+// A HIP call on a run's stream failed: every request running in it ends with
+// ASQ_EHIP, and the run takes no new columns and is destroyed once idle.
+void fail_run(Run* r) {
+  for (int c = 0; c < r->cap; ++c) {
+    Request* q = r->owner[c];
+    if (!q) continue;
+    if (q->state == 1) {
+      q->rc = ASQ_EHIP;
+      q->state = 3;
+      q->t_done = clk::now();
+    }
+    r->owner[c] = nullptr;
+  }
+  r->in_flight = false;
+  r->draining = true;
+}
+
 void launch_block(Run* r) {
-  if (r->exec) hipGraphLaunch(r->exec, r->stream);
-  else enqueue_block(r->B, r->poll, r->stream);
-  hipMemcpyAsync(r->pinned, r->B.st, r->cap * sizeof(ColState), hipMemcpyDeviceToHost, r->stream);
-  hipEventRecord(r->ev, r->stream);
+  bool ok = r->exec ? hipGraphLaunch(r->exec, r->stream) == hipSuccess
+                    : enqueue_block(r->B, r->poll, r->stream) == ASQ_OK;
+  ok = ok && hipMemcpyAsync(r->pinned, r->B.st, r->cap * sizeof(ColState), hipMemcpyDeviceToHost, r->stream) ==
+                 hipSuccess;
+  ok = ok && hipEventRecord(r->ev, r->stream) == hipSuccess;
+  if (!ok) {
+    fail_run(r);
+    return;
+  }
   r->in_flight = true;
   r->t_block = clk::now();
 }
@@ -291,12 +315,21 @@ void harvest(asq_server* S, Run* r) {
     if (worst != ASQ_OK && (q->rc == ASQ_OK || worst == ASQ_ENAN)) q->rc = worst;
     q->col_done[k] = 1;
     if (--q->cols_left == 0) {
-      hipMemcpyAsync(q->x, r->B.x + (size_t)q->slot0 * half * 6, (size_t)q->nrhs * half * 48,
-                     hipMemcpyDeviceToDevice, r->stream);
-      hipEventCreateWithFlags(&q->done_ev, hipEventDisableTiming);
-      hipEventRecord(q->done_ev, r->stream);
-      q->state = 2;
+      bool ok = hipMemcpyAsync(q->x, r->B.x + (size_t)q->slot0 * half * 6, (size_t)q->nrhs * half * 48,
+                               hipMemcpyDeviceToDevice, r->stream) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&q->done_ev, hipEventDisableTiming) == hipSuccess;
+      ok = ok && hipEventRecord(q->done_ev, r->stream) == hipSuccess;
       for (int j = 0; j < q->nrhs; ++j) r->owner[q->slot0 + j] = nullptr;
+      if (ok) {
+        q->state = 2;
+      } else {
+        // without a recorded event the copy cannot be waited for: end the request here
+        if (q->done_ev) (void)hipEventDestroy(q->done_ev);
+        q->done_ev = nullptr;
+        q->rc = ASQ_EHIP;
+        q->state = 3;
+        q->t_done = clk::now();
+      }
     }
   }
   (void)S;
@@ -305,8 +338,11 @@ void harvest(asq_server* S, Run* r) {
 void finish_copies(asq_server* S) {
   for (auto& kv : S->reqs) {
     Request* q = kv.second.get();
-    if (q->state == 2 && hipEventQuery(q->done_ev) == hipSuccess) {
-      hipEventDestroy(q->done_ev);
+    if (q->state != 2) continue;
+    const hipError_t e = hipEventQuery(q->done_ev);
+    if (e != hipErrorNotReady) {
+      if (e != hipSuccess) q->rc = ASQ_EHIP;
+      (void)hipEventDestroy(q->done_ev);
       q->done_ev = nullptr;
       q->t_done = clk::now();
       const double secs = std::chrono::duration<double>(q->t_done - q->t_submit).count();
@@ -347,7 +383,8 @@ void make_room(asq_server* S, const asq_gauge* g) {
 }
 
 void worker_main(asq_server* S) {
-  hipSetDevice(S->device);
+  // the device was current in serve_create, so this cannot fail on it
+  (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
     // admission at block boundaries: only runs that are not in flight take new columns
@@ -417,11 +454,16 @@ void worker_main(asq_server* S) {
     lk.unlock();
     std::this_thread::sleep_for(std::chrono::microseconds(20));
     lk.lock();
-    for (auto& r : S->runs)
-      if (r->in_flight && hipEventQuery(r->ev) == hipSuccess) {
+    for (auto& r : S->runs) {
+      if (!r->in_flight) continue;
+      const hipError_t e = hipEventQuery(r->ev);
+      if (e == hipSuccess) {
         r->in_flight = false;
         harvest(S, r.get());
+      } else if (e != hipErrorNotReady) {
+        fail_run(r.get());
       }
+    }
   }
   for (auto& r : S->runs) destroy_run(S, r.get());
   S->runs.clear();
@@ -436,11 +478,13 @@ extern "C" int serve_create(void* arena_dev, size_t arena_bytes, int max_streams
     set_last_error("serve_create: invalid arguments (arena 256-byte aligned, 1 <= max_streams <= 64)");
     return ASQ_EINVAL;
   }
+  int device = 0;
+  ASQ_HIP_TRY(hipGetDevice(&device));
   asq_server* S = new asq_server();
   S->arena.init(arena_dev, arena_bytes);
   S->max_streams = max_streams;
   S->max_cols = max_cols;
-  hipGetDevice(&S->device);
+  S->device = device;
   S->worker = std::thread(worker_main, S);
   *out = S;
   return ASQ_OK;

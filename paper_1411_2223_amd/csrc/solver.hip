@@ -282,19 +282,19 @@ struct HostRes {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipStream_t cap = nullptr;
   ~HostRes() {
-    if (pinned) hipHostFree(pinned);
+    if (pinned) (void)hipHostFree(pinned);
     for (auto& e : ev)
-      if (e) hipEventDestroy(e);
-    if (cap) hipStreamDestroy(cap);
+      if (e) (void)hipEventDestroy(e);
+    if (cap) (void)hipStreamDestroy(cap);
   }
   int ensure(size_t cols) {
     int dev = 0;
     ASQ_HIP_TRY(hipGetDevice(&dev));
     if (dev != device) {
-      if (pinned) hipHostFree(pinned);
+      if (pinned) (void)hipHostFree(pinned);
       for (auto& e : ev)
-        if (e) hipEventDestroy(e);
-      if (cap) hipStreamDestroy(cap);
+        if (e) (void)hipEventDestroy(e);
+      if (cap) (void)hipStreamDestroy(cap);
       pinned = nullptr;
       pinned_cols = 0;
       ev[0] = ev[1] = nullptr;
@@ -305,7 +305,7 @@ struct HostRes {
       ASQ_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     }
     if (pinned_cols < 2 * cols) {
-      if (pinned) hipHostFree(pinned);
+      if (pinned) (void)hipHostFree(pinned);
       pinned = nullptr;
       ASQ_HIP_TRY(hipHostMalloc((void**)&pinned, 2 * cols * sizeof(ColState), hipHostMallocDefault));
       pinned_cols = 2 * cols;
@@ -325,12 +325,12 @@ int capture_block(const Batch& B, int iters, hipStream_t cap, hipGraphExec_t* ex
   int rc = enqueue_block(B, iters, cap);
   hipError_t e = hipStreamEndCapture(cap, &graph);
   if (rc) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return rc;
   }
   ASQ_HIP_TRY(e);
   e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   ASQ_HIP_TRY(e);
   return ASQ_OK;
 }
@@ -444,7 +444,7 @@ int asq::solve_batch(const asq_gauge* g, int nrhs, const double* masses, const d
     if (exec) {
       hipError_t e = hipGraphLaunch(exec, s);
       if (e != hipSuccess) {
-        hipGraphExecDestroy(exec);
+        (void)hipGraphExecDestroy(exec);
         set_last_error(hipGetErrorString(e));
         return ASQ_EHIP;
       }
@@ -466,7 +466,7 @@ int asq::solve_batch(const asq_gauge* g, int nrhs, const double* masses, const d
     slot ^= 1;
   }
   ASQ_HIP_TRY(hipStreamSynchronize(s));
-  if (exec) hipGraphExecDestroy(exec);
+  if (exec) (void)hipGraphExecDestroy(exec);
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int worst = ASQ_OK;
   fill_stats(B, mirror[last], secs, stats, &worst);

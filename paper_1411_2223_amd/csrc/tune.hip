@@ -130,20 +130,21 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
       const int cols = r & 0xff;
       if (cols > 1 && cols > ncol) continue;  // a wider tile than the batch only wastes lanes
       if (launch_dslash(link, in, in, EPI_PLAIN, r, a, s)) continue;  // warm-up
-      hipEventRecord(e0, s);
-      for (int k = 0; k < 3; ++k) launch_dslash(link, in, in, EPI_PLAIN, r, a, s);
-      hipEventRecord(e1, s);
-      hipEventSynchronize(e1);
+      // a candidate whose timing fails is skipped
+      bool ok = hipEventRecord(e0, s) == hipSuccess;
+      for (int k = 0; k < 3; ++k) ok = ok && launch_dslash(link, in, in, EPI_PLAIN, r, a, s) == ASQ_OK;
+      ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
       float ms = 0;
-      hipEventElapsedTime(&ms, e0, e1);
+      ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      if (!ok) continue;
       if (log_enabled()) fprintf(stderr, "[asq] tune %s R=%d %.3f ms\n", kp.c_str(), r, ms / 3);
       if (ms < best_ms) {
         best_ms = ms;
         best = r;
       }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
   std::lock_guard<std::mutex> lk(g_mu);
   for (int epi = EPI_PLAIN; epi <= EPI_RESID; ++epi)
