@@ -10,7 +10,10 @@ links complex128 (V, 4, 3, 3), even/odd colour vectors complex128 (V/2, 3).
 Pins (tests/test_oracle.py) tie it to facts that do not come from itself:
 free-field plane-wave spectrum (closed form), anti-Hermiticity of D, gauge
 covariance, hand-derived point-source values, brute-force dense solves and the
-finite termination of CG on an operator with few distinct eigenvalues.
+finite termination of CG on an operator with few distinct eigenvalues.  The
+asqtad link construction is pinned by the free-field normalisation, the closed
+form for a uniform abelian flux, gauge covariance and an independent nested
+staple evaluation.
 """
 from __future__ import annotations
 
@@ -54,6 +57,9 @@ def lib():
         L.oracle_cg.argtypes = [_iptr, _dptr, _dptr, ctypes.c_double, _dptr, _dptr, ctypes.c_double,
                                 ctypes.c_int, _iptr, _dptr, _dptr]
         L.oracle_cg.restype = ctypes.c_int
+        L.oracle_asqtad_links.argtypes = [_iptr, _dptr, ctypes.c_double, ctypes.POINTER(ctypes.c_long),
+                                          ctypes.c_long, _dptr, _dptr]
+        L.oracle_asqtad_links.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -128,6 +134,26 @@ def cg(dims, fat, lng, mass: float, b, tol: float = 1e-10, maxiter: int = 100000
     if history:
         return x, it.value, tr.value, rc == 0, hist[: it.value + 1]
     return x, it.value, tr.value, rc == 0
+
+
+def asqtad_links(dims, thin, u0: float = 1.0, sites=None):
+    """Asqtad fat and long links from thin links, as sums over paths.
+
+    ``thin`` is complex128 with V*4*9 entries in the canonical order.  Returns
+    (fat, long) complex128 (n, 4, 3, 3): every site in lexicographic order, or
+    the listed ``sites`` in the given order.
+    """
+    V = int(np.prod(dims))
+    U = _c128(thin, (V, 4, 3, 3))
+    idx = None if sites is None else np.ascontiguousarray(sites, dtype=np.int64)
+    n = V if idx is None else len(idx)
+    fat = np.empty((n, 4, 3, 3), dtype=np.complex128)
+    lng = np.empty((n, 4, 3, 3), dtype=np.complex128)
+    sp = None if idx is None else idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
+    rc = lib().oracle_asqtad_links(_dims(dims), _p(U), float(u0), sp, int(n), _p(fat), _p(lng))
+    if rc != 0:
+        raise ValueError(f"oracle_asqtad_links failed ({rc})")
+    return fat, lng
 
 
 def num_threads() -> int:

@@ -232,3 +232,120 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/*
+ * Asqtad link construction from thin links.  The paper's lattices are MILC
+ * asqtad ensembles (CG benchmark, "GTX Titan Black" section) but it prints no
+ * smearing formula, so the standard asqtad action is written out here as a
+ * plain sum over paths:
+ *
+ *   F_mu(x) = sum over the paths P listed below of c(P) * (ordered product of
+ *             thin links along P), every P running from x to x + mu
+ *   L_mu(x) = c_N U_mu(x) U_mu(x+mu) U_mu(x+2mu)
+ *
+ * nu, rho, sigma are signed directions on pairwise different axes, none on
+ * mu's axis:
+ *
+ *   one link             [mu]                                  c1 = 5/8
+ *   3-staple   (6 paths) [nu, mu, -nu]                         c3 = 1/16  / u0^2
+ *   5-staple  (24 paths) [nu, rho, mu, -rho, -nu]              c5 = 1/64  / u0^4
+ *   7-staple  (48 paths) [nu, rho, sigma, mu, -sigma, -rho, -nu]  c7 = 1/384 / u0^6
+ *   Lepage     (6 paths) [nu, nu, mu, -nu, -nu]                cL = -1/16 / u0^4
+ *   Naik                 [mu, mu, mu]                          cN = -1/24 / u0^2
+ *
+ * A step +nu from site y multiplies U_nu(y); a step -nu multiplies
+ * U_nu(y - nu)^dag.  Thin links are periodic in every direction (the time
+ * boundary sign belongs to the operator).  u0 is the tadpole factor.
+ */
+static void mat_mul_into(cplx C[9], const cplx A[9], const cplx B[9]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      cplx v = 0;
+      for (int k = 0; k < 3; ++k) v += A[a * 3 + k] * B[k * 3 + b];
+      C[a * 3 + b] = v;
+    }
+}
+
+static void mat_mul_adj_into(cplx C[9], const cplx A[9], const cplx B[9]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      cplx v = 0;
+      for (int k = 0; k < 3; ++k) v += A[a * 3 + k] * conj(B[b * 3 + k]);
+      C[a * 3 + b] = v;
+    }
+}
+
+/* acc += coeff * (product of the thin links along the signed steps, from site c);
+   a step is +(axis + 1) or -(axis + 1). */
+static void add_path(const int d[4], const double* thin, const int c[4], const int* steps, int n,
+                     double coeff, cplx acc[9]) {
+  int y[4] = {c[0], c[1], c[2], c[3]};
+  cplx P[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, Q[9];
+  for (int k = 0; k < n; ++k) {
+    const int mu = abs(steps[k]) - 1;
+    if (steps[k] > 0) {
+      mat_mul_into(Q, P, link_at(thin, lex_of(d, y), mu));
+      y[mu] = (y[mu] + 1) % d[mu];
+    } else {
+      y[mu] = (y[mu] - 1 + d[mu]) % d[mu];
+      mat_mul_adj_into(Q, P, link_at(thin, lex_of(d, y), mu));
+    }
+    memcpy(P, Q, sizeof(P));
+  }
+  for (int k = 0; k < 9; ++k) acc[k] += coeff * P[k];
+}
+
+static void asqtad_site(const int d[4], const double* thin, double u0, long lex, cplx* fat, cplx* lng) {
+  const double u2 = u0 * u0, u4 = u2 * u2, u6 = u4 * u2;
+  const double c1 = 5.0 / 8.0, c3 = 1.0 / 16.0 / u2, c5 = 1.0 / 64.0 / u4, c7 = 1.0 / 384.0 / u6;
+  const double cL = -1.0 / 16.0 / u4, cN = -1.0 / 24.0 / u2;
+  int c[4];
+  coords_of(d, lex, c);
+  for (int mu = 0; mu < 4; ++mu) {
+    const int m = mu + 1;
+    cplx* F = fat + mu * 9;
+    cplx* L = lng + mu * 9;
+    for (int k = 0; k < 9; ++k) F[k] = L[k] = 0;
+    const int one[1] = {m};
+    add_path(d, thin, c, one, 1, c1, F);
+    for (int nu = -4; nu <= 4; ++nu) {
+      if (nu == 0 || abs(nu) == m) continue;
+      const int staple[3] = {nu, m, -nu};
+      add_path(d, thin, c, staple, 3, c3, F);
+      const int lepage[5] = {nu, nu, m, -nu, -nu};
+      add_path(d, thin, c, lepage, 5, cL, F);
+      for (int rho = -4; rho <= 4; ++rho) {
+        if (rho == 0 || abs(rho) == m || abs(rho) == abs(nu)) continue;
+        const int five[5] = {nu, rho, m, -rho, -nu};
+        add_path(d, thin, c, five, 5, c5, F);
+        for (int sg = -4; sg <= 4; ++sg) {
+          if (sg == 0 || abs(sg) == m || abs(sg) == abs(nu) || abs(sg) == abs(rho)) continue;
+          const int seven[7] = {nu, rho, sg, m, -sg, -rho, -nu};
+          add_path(d, thin, c, seven, 7, c7, F);
+        }
+      }
+    }
+    const int naik[3] = {m, m, m};
+    add_path(d, thin, c, naik, 3, cN, L);
+  }
+}
+
+/*
+ * Fat and long links from thin links [V][4][3][3][2].  With sites == NULL the
+ * outputs cover every site in lexicographic order, [V][4][3][3][2]; otherwise
+ * they hold the nsites listed sites in the given order, [nsites][4][3][3][2].
+ */
+int oracle_asqtad_links(const int dims[4], const double* thin, double u0, const long* sites, long nsites,
+                        double* fat, double* lng) {
+  if (check_dims(dims) || !(u0 > 0)) return -1;
+  const long V = vol(dims);
+  const long n = sites ? nsites : V;
+  for (long k = 0; sites && k < n; ++k)
+    if (sites[k] < 0 || sites[k] >= V) return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (long k = 0; k < n; ++k) {
+    const long lex = sites ? sites[k] : k;
+    asqtad_site(dims, thin, u0, lex, (cplx*)fat + k * 36, (cplx*)lng + k * 36);
+  }
+  return 0;
+}
