@@ -4,6 +4,7 @@
     python bench.py --workload batched_20x20x20x64                  # 24 RHS x 4 masses, FP16 vectors
     python bench.py --workload threelevel_48x48x48x96               # 12 RHS, 12-real 16-bit links
     python bench.py --workload serving [--requests N]               # Poisson request stream
+    python bench.py --workload asqtad_20x20x20x64                   # fat/long links built from thin links
     python bench.py --kernels-only                                  # fixed launches for counter runs
 
 Headline step: one complete solve of A x = b (A = 4m^2 - D_eo D_oe, even
@@ -36,6 +37,11 @@ PEAK_HBM_GBS = 8000.0
 # FP32 flop/clk = 78.6 TFLOP/s is the arithmetic ceiling of its kernels.
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_FP32_TFLOPS = 78.6
+# FP64 vector peak: 256 CU x 2.4 GHz x 128 FP64 flop/clk
+PEAK_FP64_TFLOPS = 78.6
+# SU(3) products per (site, direction) of the nested-staple link construction:
+# 6 x (4 x (2 x 2 + 2) + 2 + 2) for the fat link, 2 for the long link; 198 flops each
+LINK_BUILD_PRODUCTS = 170
 METRIC = "asqtad Dslash HBM GB/s; CG time-to-1e-10 at 20^3x64; solves/s + p99 latency"
 
 LINK_BYTES = {"f64": 144, "f32": 72, "f32r12": 48, "f16r12": 24}
@@ -71,7 +77,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="single_20x20x20x64",
-                    choices=["single_20x20x20x64", "batched_20x20x20x64", "threelevel_48x48x48x96", "serving"])
+                    choices=["single_20x20x20x64", "batched_20x20x20x64", "threelevel_48x48x48x96", "serving",
+                             "asqtad_20x20x20x64"])
     ap.add_argument("--mode", default="mixed32", choices=["f64", "mixed32", "mixed16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multishift", action="store_true", help="batched: skip the shifted-CG line")
@@ -84,6 +91,7 @@ def parse():
     ap.add_argument("--rate", type=float, default=50.0, help="serving: Poisson arrival rate (requests/s)")
     ap.add_argument("--no-oracle-check", action="store_true",
                     help="three-level: skip the host FP64 oracle residual of every column")
+    ap.add_argument("--u0", type=float, default=1.0, help="asqtad: tadpole factor of the link construction")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch the Dslash tiers and a 1 GiB copy probe (for hardware-counter runs)")
     return ap.parse_args()
@@ -570,6 +578,78 @@ def run_serving(args, asq, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_asqtad(args, asq, torch):
+    """Asqtad fat and long links built on the device from 20^3 x 64 thin links (the single-solve
+    workload's field), then the mixed-precision solve on them."""
+    w = synth.WORKLOADS["single_20x20x20x64"]
+    dims, mass, u0 = w["dims"], w["masses"][0], args.u0
+    V = int(np.prod(dims))
+    log(f"workload asqtad dims={dims} u0={u0} m={mass}")
+    U = synth.thin_links(dims, w["eps"], synth.gauge_seed(w["index"])).reshape(V, 4, 3, 3)
+    stream = torch.cuda.Stream()
+    thin = asq.links_to_device(U)
+    fat = torch.empty_like(thin)
+    lng = torch.empty_like(thin)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            asq.build_links(dims, thin, u0, fat, lng, stream=stream)
+        reps = max(3, args.steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            asq.build_links(dims, thin, u0, fat, lng, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / reps
+    flops = 198.0 * LINK_BUILD_PRODUCTS * 4 * V
+    tf = flops / dt / 1e12
+    log(f"link construction: {dt * 1e3:.3f} ms, {tf:.1f} TFLOP/s FP64 ({tf / PEAK_FP64_TFLOPS:.0%} of peak)")
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18, stream=stream)
+    del fat, lng
+    b = synth.make_sources(dims, 1, synth.source_seed(w["index"]))
+    bd = asq.vec_to_device(b, "f64")
+    secs, times, last = solve_series(g, [mass], bd, "mixed32", w["tol"], max(1, args.steps // 2), 1, stream)
+    st = last.stats[0]
+    log(f"mixed32 solve on the built links: {secs * 1e3:.1f} ms, iters={st['iters']} "
+        f"resid={st['true_resid']:.3e}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.lib()
+        rng = np.random.Generator(np.random.PCG64(3))
+        n = 4096
+        t0 = time.perf_counter()
+        oracle.asqtad_links(dims, U, u0, sites=rng.integers(0, V, size=n))
+        per_site = (time.perf_counter() - t0) / n
+        n = int(min(V, max(4096, args.cpu_seconds / max(per_site, 1e-9))))
+        sites = rng.integers(0, V, size=n)
+        t0 = time.perf_counter()
+        oracle.asqtad_links(dims, U, u0, sites=sites)
+        dtc = time.perf_counter() - t0
+        full = dtc / n * V
+        cpu = {"value": full * 1e3, "unit": "ms per link construction", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": (f"oracle path sums at {n} random sites of {V} ({dtc:.1f} s), scaled to every site"
+                          if n < V else f"oracle path sums at all {V} sites ({dtc:.1f} s)")}
+        log(f"cpu baseline: {full:.1f} s per construction on {cpu['cores']} threads")
+    out = {"metric": METRIC, "workload": "asqtad_20x20x20x64", "value": dt * 1e3,
+           "unit": "ms per link construction", "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "u0": u0, "config": {"workload": "asqtad_20x20x20x64", "dims": list(dims), "eps": w["eps"]},
+           "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / PEAK_FP64_TFLOPS, "traffic": None,
+                        "kernel": "fatten_kernel (FP64, one launch per construction)",
+                        "flops_per_launch": flops, "ms_per_launch": dt * 1e3},
+           "solve_mixed32": {"ms": secs * 1e3, "time_to_solution": time_stats(times), "iters": st["iters"],
+                             "reliable_updates": st["reliable_updates"], "true_resid": st["true_resid"],
+                             "mass": mass}}
+    if cpu:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -587,6 +667,8 @@ def main():
         run_batched(args, asq, torch)
     elif args.workload == "threelevel_48x48x48x96":
         run_threelevel(args, asq, torch)
+    elif args.workload == "asqtad_20x20x20x64":
+        run_asqtad(args, asq, torch)
     else:
         run_serving(args, asq, torch)
 

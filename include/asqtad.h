@@ -120,6 +120,26 @@ int asq_gauge_create(const asq_gauge_desc* desc, const double* fat_dev, const do
                      void* storage_dev, size_t storage_bytes, void* hip_stream, asq_gauge** out);
 int asq_gauge_destroy(asq_gauge* g);
 
+/* Asqtad fat and long links from thin links, in FP64.  The paper's lattices
+   are MILC asqtad ensembles (CG benchmark, "GTX Titan Black" section) and it
+   prints no smearing formula; this is the standard asqtad action:
+     F_mu(x) = sum over paths P from x to x+mu of c(P) * (thin links along P):
+       the link itself 5/8, 3-staples 1/(16 u0^2), 5-staples 1/(64 u0^4),
+       7-staples 1/(384 u0^6), Lepage [nu nu mu -nu -nu] -1/(16 u0^4)
+     L_mu(x) = -1/(24 u0^2) U_mu(x) U_mu(x+mu) U_mu(x+2mu)
+   (staples over every signed direction off mu's axis, deeper staples over
+   pairwise different axes).  With unit links F = 9/8 and L = -1/24 at u0 = 1.
+   dims: lattice extents, even, >= 4.  thin_dev: device, double [V][4][3][3][2]
+   canonical, any 3x3 complex matrices (periodic in every direction), read only.
+   u0: tadpole factor, > 0.  fat_dev, long_dev: device outputs in the same
+   layout, fully overwritten; the three arrays must not overlap and must be
+   16-byte aligned.  The fat links are not SU(3) in general, so pass them to
+   asq_gauge_create with recon 18 and no 16-bit copy.  Enqueued on hip_stream;
+   returns without waiting.  ASQ_EINVAL on a bad argument (checked on the host
+   before any launch), ASQ_EHIP if the launch fails. */
+int asqtad_build_links(const int dims[4], const double* thin_dev, double u0, double* fat_dev, double* long_dev,
+                       void* hip_stream);
+
 /* ---- operator ------------------------------------------------------------ */
 
 /* out = D restricted to sites of out_parity, acting on in (sites of the other

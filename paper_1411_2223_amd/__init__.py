@@ -87,6 +87,7 @@ _SIGS = {
     "serve_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(asq_cg_stats),
                                   ctypes.POINTER(ctypes.c_double)]),
     "serve_destroy": (ctypes.c_int, [_vp]),
+    "asqtad_build_links": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _vp, ctypes.c_double, _vp, _vp, _vp]),
     "asq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "asq_last_error": (ctypes.c_char_p, []),
     "asq_copy_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
@@ -215,6 +216,37 @@ def decode_f16n(rec, nrhs, half):
     return comp[..., 0] + 1j * comp[..., 1]
 
 
+def links_to_device(a, device="cuda"):
+    """Canonical complex128 links (V, 4, 3, 3) -> a float64 device tensor of V * 4 * 18 reals."""
+    torch = _torch()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    return torch.from_numpy(a.reshape(-1).view(np.float64)).to(device)
+
+
+def build_links(dims, thin_dev, u0=1.0, fat=None, lng=None, stream=None):
+    """Asqtad fat and long links from thin links on the device (asqtad_build_links).
+
+    thin_dev, fat, lng: float64 device tensors of V * 4 * 18 reals in the canonical
+    layout (see links_to_device); fat and lng are allocated when not given.
+    Returns (fat, lng); the work is enqueued on the stream.
+    """
+    torch = _torch()
+    load()
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims)) * 4 * 18
+    if thin_dev.dtype != torch.float64 or thin_dev.numel() != n or not thin_dev.is_contiguous():
+        raise AsqError(ASQ_EINVAL, "build_links: thin links must be a contiguous float64 tensor of V*4*18 reals")
+    fat = torch.empty(n, dtype=torch.float64, device=thin_dev.device) if fat is None else fat
+    lng = torch.empty(n, dtype=torch.float64, device=thin_dev.device) if lng is None else lng
+    for t in (fat, lng):
+        if t.dtype != torch.float64 or t.numel() != n or not t.is_contiguous():
+            raise AsqError(ASQ_EINVAL, "build_links: outputs must be contiguous float64 tensors of V*4*18 reals")
+    rc = asqtad_build_links((ctypes.c_int * 4)(*dims), thin_dev.data_ptr(), float(u0), fat.data_ptr(),
+                            lng.data_ptr(), stream_ptr(stream))
+    check(rc, "asqtad_build_links")
+    return fat, lng
+
+
 @dataclass
 class SolveResult:
     x: object
@@ -244,6 +276,8 @@ class Gauge:
         V = int(np.prod(self.dims))
 
         def up(a):
+            if isinstance(a, torch.Tensor):  # already on the device (e.g. from build_links)
+                return a
             a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(V, 4, 3, 3))
             return torch.from_numpy(a.view(np.float64)).to(device)
 
@@ -255,6 +289,16 @@ class Gauge:
         check(rc, "asq_gauge_create")
         self.handle = h
         self.device = device
+
+    @classmethod
+    def from_thin(cls, dims, thin, u0=1.0, precs=("f64", "f32"), device="cuda", stream=None):
+        """A resident gauge field whose fat and long links are built on the device from
+        canonical thin links (host array or device tensor) by asqtad_build_links.
+        The fat links are not SU(3), so the links are kept as 18 reals."""
+        torch = _torch()
+        thin_d = thin if isinstance(thin, torch.Tensor) else links_to_device(thin, device)
+        fat, lng = build_links(dims, thin_d, u0, stream=stream)
+        return cls(dims, fat, lng, precs=precs, recon=18, device=device, stream=stream)
 
     def close(self):
         if getattr(self, "handle", None):

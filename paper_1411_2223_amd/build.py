@@ -18,7 +18,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libasqtad.so")
 
 SOURCES = ["gauge.hip", "dslash.hip", "dslash_f64.hip", "dslash_f32.hip", "dslash_r12.hip", "dslash_i16.hip",
-           "blas.hip", "solver.hip", "tune.hip", "serve.hip", "full.hip", "multishift.hip"]
+           "blas.hip", "solver.hip", "tune.hip", "serve.hip", "full.hip", "multishift.hip", "fatten.hip"]
 ARCH = os.environ.get("ASQ_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,322 @@
+// fatten.hip -- asqtad fat and long links from thin links, in FP64.
+//
+// The paper's lattices are MILC asqtad ensembles (CG benchmark, "GTX Titan
+// Black" section); it gives no smearing formula, so the standard asqtad action
+// is used.  For a direction mu, with nu, rho, sigma signed directions on
+// pairwise different axes, none on mu's, and the staple map
+//
+//   T_d(X)(y) = W_d(y) X(y + d) W_d(y + mu)^dag,   W_d(y) = the thin link from y to y + d
+//             (U_a(y) for d = +a, U_a(y - a)^dag for d = -a),
+//
+// the fat link is evaluated as nested staples
+//
+//   F_mu(x) = c1 U_mu(x) + sum_nu T_nu( c3 U_mu + cL T_nu(U_mu)
+//                                       + sum_rho T_rho( c5 U_mu + c7 sum_sigma T_sigma(U_mu) ) )(x)
+//
+// which expands to the one-link, 6 three-staple, 24 five-staple, 48
+// seven-staple and 6 Lepage paths, and the long link is
+// L_mu(x) = cN U_mu(x) U_mu(x+mu) U_mu(x+2mu).  Coefficients: c1 = 5/8,
+// c3 = 1/(16 u0^2), c5 = 1/(64 u0^4), c7 = 1/(384 u0^6), cL = -1/(16 u0^4),
+// cN = -1/(24 u0^2); u0 is the tadpole factor.  Links are periodic in every
+// direction (the time-boundary sign is applied when the links are imported).
+//
+// A block covers 64 sites (lane = site) for one mu, so mu is uniform and the
+// direction loops do not diverge; its four waves split the staple sums and
+// meet in LDS.  Nothing is staged in global memory: every staple is rebuilt
+// from thin links, which come from L2.  Per (site, mu) the evaluation takes
+// 6 x (4 x 8 + 2) = 204 SU(3) products (each (nu, rho) pair rebuilds its outer
+// staple) and the long link 2.
+#include <math.h>
+
+#include "asq_internal.h"
+
+namespace asq {
+namespace {
+
+using M3 = Mat3<double>;
+
+struct FattenArgs {
+  int d[4];
+  long V;
+  const double2* thin;  // [V][4][9] complex
+  double2* fat;
+  double2* lng;
+  double c1, c3, c5, c7, cL, cN;
+};
+
+__device__ __forceinline__ long lex_of(const int d[4], const int c[4]) {
+  return c[0] + (long)d[0] * (c[1] + (long)d[1] * (c[2] + (long)d[2] * c[3]));
+}
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ M3 load(const FattenArgs& A, const int c[4], int mu) {
+  const double2* q = A.thin + (lex_of(A.d, c) * 4 + mu) * 9;
+  M3 U;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double2 v = q[k];
+    U.e[k / 3][k % 3].re = v.x;
+    U.e[k / 3][k % 3].im = v.y;
+  }
+  return U;
+}
+
+// C = A B, C = A^dag B, C += s A B^dag and C += s A B (s real), C = s X
+__device__ __forceinline__ M3 mul_nn(const M3& A, const M3& B) {
+  M3 C;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      cx<double> v{0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cmac(v, A.e[a][k], B.e[k][b]);
+      C.e[a][b] = v;
+    }
+  return C;
+}
+
+__device__ __forceinline__ M3 mul_dn(const M3& A, const M3& B) {
+  M3 C;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      cx<double> v{0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cmac_conj(v, A.e[k][a], B.e[k][b]);
+      C.e[a][b] = v;
+    }
+  return C;
+}
+
+__device__ __forceinline__ void acc_nd(M3& C, double s, const M3& A, const M3& B) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      cx<double> v{0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cmac_conj(v, B.e[b][k], A.e[a][k]);  // A[a][k] conj(B[b][k])
+      C.e[a][b].re = fmaR(s, v.re, C.e[a][b].re);
+      C.e[a][b].im = fmaR(s, v.im, C.e[a][b].im);
+    }
+}
+
+__device__ __forceinline__ void acc_nn(M3& C, double s, const M3& A, const M3& B) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      cx<double> v{0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cmac(v, A.e[a][k], B.e[k][b]);
+      C.e[a][b].re = fmaR(s, v.re, C.e[a][b].re);
+      C.e[a][b].im = fmaR(s, v.im, C.e[a][b].im);
+    }
+}
+
+__device__ __forceinline__ M3 scaled(double s, const M3& X) {
+  M3 C;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      C.e[a][b].re = s * X.e[a][b].re;
+      C.e[a][b].im = s * X.e[a][b].im;
+    }
+  return C;
+}
+
+// C += s T_d(X)(y), with d = +(ax) or -(ax) given by (ax, neg) and X the matrix at y + d.
+__device__ __forceinline__ void acc_staple(const FattenArgs& A, M3& C, double s, const int y[4], int mu, int ax,
+                                           bool neg, const M3& X) {
+  int w[4] = {y[0], y[1], y[2], y[3]};   // the site holding the first link
+  if (neg) w[ax] = wrap(w[ax] - 1, A.d[ax]);
+  const M3 P = neg ? mul_dn(load(A, w, ax), X) : mul_nn(load(A, w, ax), X);
+  w[mu] = wrap(w[mu] + 1, A.d[mu]);       // the closing link starts at y + mu (or y + mu - d)
+  if (neg) acc_nn(C, s, P, load(A, w, ax));
+  else acc_nd(C, s, P, load(A, w, ax));
+}
+
+__device__ __forceinline__ void step(int c[4], int ax, bool neg, const int d[4]) {
+  c[ax] = wrap(c[ax] + (neg ? -1 : 1), d[ax]);
+}
+
+// A block covers 64 consecutive sites (one per lane) for one mu; its 4 waves
+// split the 24 signed (nu, rho) pairs 6 each, each pair giving
+//   T_nu( T_rho( c5 U_mu + c7 sum_sigma T_sigma(U_mu) ) )(x)
+// plus, once per nu, T_nu(c3 U_mu + cL T_nu(U_mu))(x).  Each wave sums its
+// pairs into its own LDS slice; the slices and c1 U_mu(x) are then added in a
+// fixed order, so the result does not depend on scheduling.
+constexpr int kFatSites = 64;
+
+__global__ void __launch_bounds__(256) fatten_kernel(const FattenArgs A) {
+  __shared__ double2 part[4][9][kFatSites];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long site = (long)xcd_remap((int)blockIdx.x, (int)gridDim.x) * kFatSites + lane;
+  const int mu = (int)blockIdx.y;
+  const bool valid = site < A.V;
+  const long lex = valid ? site : A.V - 1;  // lanes past the end compute a copy of the last site
+  int x[4];
+  {
+    long r = lex;
+    x[0] = (int)(r % A.d[0]);
+    r /= A.d[0];
+    x[1] = (int)(r % A.d[1]);
+    r /= A.d[1];
+    x[2] = (int)(r % A.d[2]);
+    x[3] = (int)(r / A.d[2]);
+  }
+  int others[3];
+  for (int a = 0, n = 0; a < 4; ++a)
+    if (a != mu) others[n++] = a;
+
+  // pair p = 4 * ni + ri (ni: signed nu among 6, ri: signed rho among 4) goes to
+  // wave (ni + ri) % 4, so the six once-per-nu terms (ri == 0) spread over the waves
+  bool first = true;
+#pragma unroll 1
+  for (int ni = 0; ni < 6; ++ni) {
+    const int ri = (wave - ni % 4 + 4) % 4;
+    const int nax = others[ni >> 1];
+    const bool nneg = ni & 1;
+    int rax = -1;
+    for (int k = 0, n = 0; k < 3; ++k)
+      if (others[k] != nax && n++ == (ri >> 1)) rax = others[k];
+    const bool rneg = ri & 1;
+    const int sax = 6 - mu - nax - rax;
+
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    step(y, nax, nneg, A.d);
+    int z[4] = {y[0], y[1], y[2], y[3]};
+    step(z, rax, rneg, A.d);
+    M3 core = scaled(A.c5, load(A, z, mu));
+#pragma unroll 1
+    for (int sn = 0; sn < 2; ++sn) {
+      int z2[4] = {z[0], z[1], z[2], z[3]};
+      step(z2, sax, sn, A.d);
+      acc_staple(A, core, A.c7, z, mu, sax, sn, load(A, z2, mu));
+    }
+    M3 v = scaled(0.0, core);
+    acc_staple(A, v, 1.0, y, mu, rax, rneg, core);
+    if (ri == 0) {
+      int y2[4] = {y[0], y[1], y[2], y[3]};
+      step(y2, nax, nneg, A.d);
+      acc_staple(A, v, A.cL, y, mu, nax, nneg, load(A, y2, mu));  // Lepage
+      const M3 Uy = load(A, y, mu);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          v.e[a][b].re = fmaR(A.c3, Uy.e[a][b].re, v.e[a][b].re);
+          v.e[a][b].im = fmaR(A.c3, Uy.e[a][b].im, v.e[a][b].im);
+        }
+    }
+    M3 out = scaled(0.0, v);
+    acc_staple(A, out, 1.0, x, mu, nax, nneg, v);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      double2 o = make_double2(out.e[k / 3][k % 3].re, out.e[k / 3][k % 3].im);
+      if (!first) {
+        const double2 q = part[wave][k][lane];
+        o.x += q.x;
+        o.y += q.y;
+      }
+      part[wave][k][lane] = o;
+    }
+    first = false;
+  }
+  __syncthreads();
+
+  if (wave == 3) {
+    // the long link, on the wave with the fewest once-per-nu terms
+    int x1[4] = {x[0], x[1], x[2], x[3]};
+    step(x1, mu, false, A.d);
+    int x2[4] = {x1[0], x1[1], x1[2], x1[3]};
+    step(x2, mu, false, A.d);
+    const M3 Ux = load(A, x, mu);
+    M3 L = scaled(0.0, Ux);
+    acc_nn(L, A.cN, mul_nn(Ux, load(A, x1, mu)), load(A, x2, mu));
+    if (valid) {
+      double2* ql = A.lng + (lex * 4 + mu) * 9;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) ql[k] = make_double2(L.e[k / 3][k % 3].re, L.e[k / 3][k % 3].im);
+    }
+  } else if (valid) {
+    // waves 0-2 finish three of the nine entries each
+    const double2* q = A.thin + (lex * 4 + mu) * 9;
+    double2* qf = A.fat + (lex * 4 + mu) * 9;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int k = wave * 3 + j;
+      const double2 u = q[k];
+      double re = A.c1 * u.x, im = A.c1 * u.y;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        re += part[w][k][lane].x;
+        im += part[w][k][lane].y;
+      }
+      qf[k] = make_double2(re, im);
+    }
+  }
+}
+
+bool overlaps(const void* a, const void* b, size_t n) {
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + n && pb < pa + n;
+}
+
+}  // namespace
+}  // namespace asq
+
+using namespace asq;
+
+extern "C" int asqtad_build_links(const int dims[4], const double* thin_dev, double u0, double* fat_dev,
+                                  double* long_dev, void* hip_stream) {
+  if (!dims || !thin_dev || !fat_dev || !long_dev) {
+    set_last_error("asqtad_build_links: null pointer");
+    return ASQ_EINVAL;
+  }
+  for (int mu = 0; mu < 4; ++mu)
+    if (dims[mu] < 4 || (dims[mu] & 1) || dims[mu] > (1 << 14)) {
+      set_last_error("asqtad_build_links: extents must be even, >= 4 and <= 16384");
+      return ASQ_EINVAL;
+    }
+  const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
+  if (V / 64 + 1 >= (1L << 31)) {
+    set_last_error("asqtad_build_links: lattice too large");
+    return ASQ_EINVAL;
+  }
+  if (!(u0 > 0) || !isfinite(u0)) {
+    set_last_error("asqtad_build_links: u0 must be positive and finite");
+    return ASQ_EINVAL;
+  }
+  if (((uintptr_t)thin_dev & 15) || ((uintptr_t)fat_dev & 15) || ((uintptr_t)long_dev & 15)) {
+    set_last_error("asqtad_build_links: link arrays must be 16-byte aligned");
+    return ASQ_EINVAL;
+  }
+  const size_t bytes = (size_t)V * 4 * 18 * sizeof(double);
+  if (overlaps(thin_dev, fat_dev, bytes) || overlaps(thin_dev, long_dev, bytes) ||
+      overlaps(fat_dev, long_dev, bytes)) {
+    set_last_error("asqtad_build_links: thin, fat and long arrays must not overlap");
+    return ASQ_EINVAL;
+  }
+  FattenArgs a;
+  for (int mu = 0; mu < 4; ++mu) a.d[mu] = dims[mu];
+  a.V = V;
+  a.thin = (const double2*)thin_dev;
+  a.fat = (double2*)fat_dev;
+  a.lng = (double2*)long_dev;
+  const double u2 = u0 * u0, u4 = u2 * u2, u6 = u4 * u2;
+  a.c1 = 5.0 / 8.0;
+  a.c3 = 1.0 / (16.0 * u2);
+  a.c5 = 1.0 / (64.0 * u4);
+  a.c7 = 1.0 / (384.0 * u6);
+  a.cL = -1.0 / (16.0 * u4);
+  a.cN = -1.0 / (24.0 * u2);
+  const dim3 grid((unsigned)((V + kFatSites - 1) / kFatSites), 4);
+  fatten_kernel<<<grid, 256, 0, (hipStream_t)hip_stream>>>(a);
+  ASQ_HIP_TRY(hipGetLastError());
+  return ASQ_OK;
+}

@@ -89,6 +89,18 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert asq.cg_solve_multishift(None, 1, 1, m, 16, 16, 256, 1, ctypes.byref(params), stats,
                                    None) == asq.ASQ_EINVAL
     assert asq.asq_multishift_workspace_bytes(None, 1, 1, 0) == 0
+    # link construction: every case fails a host check, none reaches a launch
+    good = (ctypes.c_int * 4)(4, 4, 4, 4)
+    bad = (ctypes.c_int * 4)(5, 4, 4, 4)
+    base, step = 1 << 24, 1 << 22  # far apart: a 4^4 link array is 73728 bytes
+    assert asq.asqtad_build_links(bad, base, 1.0, base + step, base + 2 * step, None) == asq.ASQ_EINVAL
+    assert asq.asqtad_build_links(good, None, 1.0, base + step, base + 2 * step, None) == asq.ASQ_EINVAL
+    assert asq.asqtad_build_links(None, base, 1.0, base + step, base + 2 * step, None) == asq.ASQ_EINVAL
+    for u0 in (0.0, -1.0, float("nan"), float("inf")):
+        assert asq.asqtad_build_links(good, base, u0, base + step, base + 2 * step, None) == asq.ASQ_EINVAL
+    assert asq.asqtad_build_links(good, base + 8, 1.0, base + step, base + 2 * step, None) == asq.ASQ_EINVAL
+    assert asq.asqtad_build_links(good, base, 1.0, base + 4096, base + 2 * step, None) == asq.ASQ_EINVAL
+    assert asq.asqtad_build_links(good, base, 1.0, base + step, base + step + 16, None) == asq.ASQ_EINVAL
 
 
 def test_magic_division_formula():
@@ -107,3 +119,18 @@ def test_f16n_host_codec_roundtrip():
     w = asq.decode_f16n(asq.encode_f16n(v), 2, 50)
     err = np.abs(w - v).max(axis=-1) / np.abs(np.stack([v.real, v.imag], -1)).max(axis=(-1, -2))
     assert err.max() < 2 ** -11 * 1.01
+
+
+def test_build_links_binding_checks_shapes(lib):
+    """The binding refuses tensors of the wrong size or type before calling the library."""
+    import torch
+
+    dims = (4, 4, 4, 4)
+    n = 256 * 4 * 18
+    with pytest.raises(asq.AsqError):
+        asq.build_links(dims, torch.zeros(n - 1, dtype=torch.float64))
+    with pytest.raises(asq.AsqError):
+        asq.build_links(dims, torch.zeros(n, dtype=torch.float32))
+    with pytest.raises(asq.AsqError):
+        asq.build_links(dims, torch.zeros(n, dtype=torch.float64), fat=torch.zeros(n + 1, dtype=torch.float64),
+                        lng=torch.zeros(n, dtype=torch.float64))
