@@ -132,8 +132,9 @@ int asq_gauge_destroy(asq_gauge* g);
    dims: lattice extents, even, >= 4.  thin_dev: device, double [V][4][3][3][2]
    canonical, any 3x3 complex matrices (periodic in every direction), read only.
    u0: tadpole factor, > 0.  fat_dev, long_dev: device outputs in the same
-   layout, fully overwritten; the three arrays must not overlap and must be
-   16-byte aligned.  The fat links are not SU(3) in general, so pass them to
+   layout, fully overwritten (long_dev also holds a transposed copy of the thin
+   links while the fat links are built); the three arrays must not overlap and
+   must be 16-byte aligned.  The fat links are not SU(3) in general, so pass them to
    asq_gauge_create with recon 18 and no 16-bit copy.  Enqueued on hip_stream;
    returns without waiting.  ASQ_EINVAL on a bad argument (checked on the host
    before any launch), ASQ_EHIP if the launch fails. */

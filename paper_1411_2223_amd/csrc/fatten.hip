@@ -20,12 +20,18 @@
 // cN = -1/(24 u0^2); u0 is the tadpole factor.  Links are periodic in every
 // direction (the time-boundary sign is applied when the links are imported).
 //
-// A block covers 64 sites (lane = site) for one mu, so mu is uniform and the
-// direction loops do not diverge; its four waves split the staple sums and
-// meet in LDS.  Nothing is staged in global memory: every staple is rebuilt
-// from thin links, which come from L2.  Per (site, mu) the evaluation takes
-// 6 x (4 x 8 + 2) = 204 SU(3) products (each (nu, rho) pair rebuilds its outer
-// staple) and the long link 2.
+// Three launches on the caller's stream:
+//   1. a site-fastest copy of the thin links, written into the long-link output
+//      (used as scratch, so the call needs no workspace);
+//   2. the fat links: a block covers 64 sites (lane = site) for one mu, so mu is
+//      uniform and the direction loops do not diverge, and every link load is a
+//      coalesced 1 KB row; the four waves split the staple sums and meet in LDS;
+//      nothing else is staged in global memory (staples are rebuilt from thin
+//      links, which come from L2);
+//   3. the long links from the canonical thin links, overwriting the copy.
+// Per (site, mu) the fat link takes 12 x (4 + 2 x 4) + 6 x 2 = 156 SU(3)
+// products (the two orders of a {nu, rho} group share their core) and the
+// long link 2.
 #include <math.h>
 
 #include "asq_internal.h"
@@ -38,7 +44,8 @@ using M3 = Mat3<double>;
 struct FattenArgs {
   int d[4];
   long V;
-  const double2* thin;  // [V][4][9] complex
+  const double2* thin;  // canonical [V][4][9] complex
+  const double2* soa;   // the same links site-fastest, [4][9][V] complex
   double2* fat;
   double2* lng;
   double c1, c3, c5, c7, cL, cN;
@@ -50,8 +57,23 @@ __device__ __forceinline__ long lex_of(const int d[4], const int c[4]) {
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// U_mu at site c from the site-fastest copy: lanes on consecutive sites read
+// consecutive 16-byte words.
 __device__ __forceinline__ M3 load(const FattenArgs& A, const int c[4], int mu) {
-  const double2* q = A.thin + (lex_of(A.d, c) * 4 + mu) * 9;
+  const double2* q = A.soa + (size_t)mu * 9 * A.V + lex_of(A.d, c);
+  M3 U;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double2 v = q[(size_t)k * A.V];
+    U.e[k / 3][k % 3].re = v.x;
+    U.e[k / 3][k % 3].im = v.y;
+  }
+  return U;
+}
+
+// U_mu at site c from the canonical array.
+__device__ __forceinline__ M3 load_canonical(const FattenArgs& A, long lex, int mu) {
+  const double2* q = A.thin + (lex * 4 + mu) * 9;
   M3 U;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
@@ -144,19 +166,27 @@ __device__ __forceinline__ void step(int c[4], int ax, bool neg, const int d[4])
   c[ax] = wrap(c[ax] + (neg ? -1 : 1), d[ax]);
 }
 
-// A block covers 64 consecutive sites (one per lane) for one mu; its 4 waves
-// split the 24 signed (nu, rho) pairs 6 each, each pair giving
-//   T_nu( T_rho( c5 U_mu + c7 sum_sigma T_sigma(U_mu) ) )(x)
-// plus, once per nu, T_nu(c3 U_mu + cL T_nu(U_mu))(x).  Each wave sums its
-// pairs into its own LDS slice; the slices and c1 U_mu(x) are then added in a
-// fixed order, so the result does not depend on scheduling.
+// A block covers 64 consecutive sites (one per lane) for one mu.  The 24
+// signed (nu, rho) pairs form 12 unordered groups {nu, rho}; both orders share
+// the core c5 U_mu + c7 sum_sigma T_sigma(U_mu) at z = x + nu + rho (sigma runs
+// over the one axis left), so a group costs one core and two chains
+// T_nu(T_rho(core))(x) and T_rho(T_nu(core))(x).  Wave w takes the three groups
+// whose signs are (w & 1, w >> 1), one per axis pair.  The once-per-direction
+// term T_d(c3 U_mu + cL T_d(U_mu))(x) rides on a chain whose outer direction is
+// d, in a wave fixed per d.  Each wave sums into its own LDS slice; the slices
+// and c1 U_mu(x) are then added in a fixed order, so the result does not
+// depend on scheduling.
 constexpr int kFatSites = 64;
 
 __global__ void __launch_bounds__(256) fatten_kernel(const FattenArgs A) {
   __shared__ double2 part[4][9][kFatSites];
+  __shared__ double2 cores[4][9][kFatSites];  // each wave's current core, kept out of registers
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long site = (long)xcd_remap((int)blockIdx.x, (int)gridDim.x) * kFatSites + lane;
-  const int mu = (int)blockIdx.y;
+  // the four directions of a site range are neighbouring blocks (same XCD, same
+  // L2): they read the same neighbour links and write the same output lines
+  const int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int mu = lin & 3;
+  const long site = (long)(lin >> 2) * kFatSites + lane;
   const bool valid = site < A.V;
   const long lex = valid ? site : A.V - 1;  // lanes past the end compute a copy of the last site
   int x[4];
@@ -172,25 +202,22 @@ __global__ void __launch_bounds__(256) fatten_kernel(const FattenArgs A) {
   int others[3];
   for (int a = 0, n = 0; a < 4; ++a)
     if (a != mu) others[n++] = a;
+  // the wave carrying the once-per-direction term of others[i] with sign bit g
+  // (+a -> 2, -a -> 1, +b -> 0, -b -> 3, +c -> 1, -c -> 2): each has a chain
+  // with that outer direction
+  const int extra_wave[3][2] = {{2, 1}, {0, 3}, {1, 2}};
+  const bool sgn1 = wave & 1, sgn2 = wave >> 1;
 
-  // pair p = 4 * ni + ri (ni: signed nu among 6, ri: signed rho among 4) goes to
-  // wave (ni + ri) % 4, so the six once-per-nu terms (ri == 0) spread over the waves
   bool first = true;
 #pragma unroll 1
-  for (int ni = 0; ni < 6; ++ni) {
-    const int ri = (wave - ni % 4 + 4) % 4;
-    const int nax = others[ni >> 1];
-    const bool nneg = ni & 1;
-    int rax = -1;
-    for (int k = 0, n = 0; k < 3; ++k)
-      if (others[k] != nax && n++ == (ri >> 1)) rax = others[k];
-    const bool rneg = ri & 1;
-    const int sax = 6 - mu - nax - rax;
-
-    int y[4] = {x[0], x[1], x[2], x[3]};
-    step(y, nax, nneg, A.d);
-    int z[4] = {y[0], y[1], y[2], y[3]};
-    step(z, rax, rneg, A.d);
+  for (int p = 0; p < 3; ++p) {
+    // axis pair p: (a, b), (a, c), (b, c) with a, b, c = others[0..2]
+    const int i1 = p == 2 ? 1 : 0, i2 = p == 0 ? 1 : 2;
+    const int ax1 = others[i1], ax2 = others[i2];
+    const int sax = 6 - mu - ax1 - ax2;
+    int z[4] = {x[0], x[1], x[2], x[3]};
+    step(z, ax1, sgn1, A.d);
+    step(z, ax2, sgn2, A.d);
     M3 core = scaled(A.c5, load(A, z, mu));
 #pragma unroll 1
     for (int sn = 0; sn < 2; ++sn) {
@@ -198,59 +225,68 @@ __global__ void __launch_bounds__(256) fatten_kernel(const FattenArgs A) {
       step(z2, sax, sn, A.d);
       acc_staple(A, core, A.c7, z, mu, sax, sn, load(A, z2, mu));
     }
-    M3 v = scaled(0.0, core);
-    acc_staple(A, v, 1.0, y, mu, rax, rneg, core);
-    if (ri == 0) {
-      int y2[4] = {y[0], y[1], y[2], y[3]};
-      step(y2, nax, nneg, A.d);
-      acc_staple(A, v, A.cL, y, mu, nax, nneg, load(A, y2, mu));  // Lepage
-      const M3 Uy = load(A, y, mu);
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 9; ++k)
+      cores[wave][k][lane] = make_double2(core.e[k / 3][k % 3].re, core.e[k / 3][k % 3].im);
+#pragma unroll 1
+    for (int ch = 0; ch < 2; ++ch) {
+      // reread through a volatile pointer, so the core does not stay live in registers
+      const volatile double2* cq = &cores[wave][0][lane];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          v.e[a][b].re = fmaR(A.c3, Uy.e[a][b].re, v.e[a][b].re);
-          v.e[a][b].im = fmaR(A.c3, Uy.e[a][b].im, v.e[a][b].im);
-        }
-    }
-    M3 out = scaled(0.0, v);
-    acc_staple(A, out, 1.0, x, mu, nax, nneg, v);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      double2 o = make_double2(out.e[k / 3][k % 3].re, out.e[k / 3][k % 3].im);
-      if (!first) {
-        const double2 q = part[wave][k][lane];
-        o.x += q.x;
-        o.y += q.y;
+      for (int k = 0; k < 9; ++k) {
+        core.e[k / 3][k % 3].re = cq[k * kFatSites].x;
+        core.e[k / 3][k % 3].im = cq[k * kFatSites].y;
       }
-      part[wave][k][lane] = o;
+      // chain ch: outer direction (oax, oneg), inner direction (iax, ineg)
+      const int oax = ch ? ax2 : ax1, iax = ch ? ax1 : ax2;
+      const bool oneg = ch ? sgn2 : sgn1, ineg = ch ? sgn1 : sgn2;
+      const int oi = ch ? i2 : i1;
+      int y[4] = {x[0], x[1], x[2], x[3]};
+      step(y, oax, oneg, A.d);
+      M3 v = scaled(0.0, core);
+      acc_staple(A, v, 1.0, y, mu, iax, ineg, core);
+      // the once-per-direction term goes with the first chain of its wave
+      // whose outer direction it is (axis pair 0 or 1 for a, 0 or 2 for b, 1
+      // or 2 for c: the first such pair in the loop)
+      const bool first_pair = oi == 0 ? p == 0 : (oi == 1 ? p == 0 : p == 1);
+      if (wave == extra_wave[oi][oneg] && first_pair) {
+        int y2[4] = {y[0], y[1], y[2], y[3]};
+        step(y2, oax, oneg, A.d);
+        acc_staple(A, v, A.cL, y, mu, oax, oneg, load(A, y2, mu));  // Lepage
+        const M3 Uy = load(A, y, mu);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            v.e[a][b].re = fmaR(A.c3, Uy.e[a][b].re, v.e[a][b].re);
+            v.e[a][b].im = fmaR(A.c3, Uy.e[a][b].im, v.e[a][b].im);
+          }
+      }
+      M3 out = scaled(0.0, v);
+      acc_staple(A, out, 1.0, x, mu, oax, oneg, v);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        double2 o = make_double2(out.e[k / 3][k % 3].re, out.e[k / 3][k % 3].im);
+        if (!first) {
+          const double2 q = part[wave][k][lane];
+          o.x += q.x;
+          o.y += q.y;
+        }
+        part[wave][k][lane] = o;
+      }
+      first = false;
     }
-    first = false;
   }
   __syncthreads();
 
-  if (wave == 3) {
-    // the long link, on the wave with the fewest once-per-nu terms
-    int x1[4] = {x[0], x[1], x[2], x[3]};
-    step(x1, mu, false, A.d);
-    int x2[4] = {x1[0], x1[1], x1[2], x1[3]};
-    step(x2, mu, false, A.d);
-    const M3 Ux = load(A, x, mu);
-    M3 L = scaled(0.0, Ux);
-    acc_nn(L, A.cN, mul_nn(Ux, load(A, x1, mu)), load(A, x2, mu));
-    if (valid) {
-      double2* ql = A.lng + (lex * 4 + mu) * 9;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) ql[k] = make_double2(L.e[k / 3][k % 3].re, L.e[k / 3][k % 3].im);
-    }
-  } else if (valid) {
+  if (wave < 3 && valid) {
     // waves 0-2 finish three of the nine entries each
-    const double2* q = A.thin + (lex * 4 + mu) * 9;
+    const double2* q = A.soa + (size_t)mu * 9 * A.V + lex;
     double2* qf = A.fat + (lex * 4 + mu) * 9;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const int k = wave * 3 + j;
-      const double2 u = q[k];
+      const double2 u = q[(size_t)k * A.V];
       double re = A.c1 * u.x, im = A.c1 * u.y;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
@@ -260,6 +296,51 @@ __global__ void __launch_bounds__(256) fatten_kernel(const FattenArgs A) {
       qf[k] = make_double2(re, im);
     }
   }
+}
+
+// Canonical thin links -> the site-fastest copy.  A block moves 64 sites: it
+// reads their 36 complex entries each as one contiguous 36 KB run and writes 36
+// rows of 64 entries, both coalesced, through LDS.
+__global__ void __launch_bounds__(256) thin_soa_kernel(const double2* __restrict__ thin, double2* __restrict__ soa,
+                                                       long V) {
+  __shared__ double2 tile[36][kFatSites + 1];
+  const long s0 = (long)blockIdx.x * kFatSites;
+  const int n = (int)(V - s0 < kFatSites ? V - s0 : kFatSites);
+  for (int e = threadIdx.x; e < n * 36; e += blockDim.x) tile[e % 36][e / 36] = thin[s0 * 36 + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 36 * kFatSites; e += blockDim.x) {
+    const int j = e / kFatSites, i = e % kFatSites;
+    if (i < n) soa[(size_t)j * V + s0 + i] = tile[j][i];
+  }
+}
+
+// L_mu(x) = cN U_mu(x) U_mu(x+mu) U_mu(x+2mu) from the canonical thin links
+// (the site-fastest copy occupies the output until this kernel runs).
+__global__ void __launch_bounds__(256) long_link_kernel(const FattenArgs A) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= A.V * 4) return;
+  const long lex = gid >> 2;
+  const int mu = (int)(gid & 3);
+  int x[4];
+  {
+    long r = lex;
+    x[0] = (int)(r % A.d[0]);
+    r /= A.d[0];
+    x[1] = (int)(r % A.d[1]);
+    r /= A.d[1];
+    x[2] = (int)(r % A.d[2]);
+    x[3] = (int)(r / A.d[2]);
+  }
+  int x1[4] = {x[0], x[1], x[2], x[3]};
+  step(x1, mu, false, A.d);
+  int x2[4] = {x1[0], x1[1], x1[2], x1[3]};
+  step(x2, mu, false, A.d);
+  const M3 Ux = load_canonical(A, lex, mu);
+  M3 L = scaled(0.0, Ux);
+  acc_nn(L, A.cN, mul_nn(Ux, load_canonical(A, lex_of(A.d, x1), mu)), load_canonical(A, lex_of(A.d, x2), mu));
+  double2* ql = A.lng + (lex * 4 + mu) * 9;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) ql[k] = make_double2(L.e[k / 3][k % 3].re, L.e[k / 3][k % 3].im);
 }
 
 bool overlaps(const void* a, const void* b, size_t n) {
@@ -284,7 +365,7 @@ extern "C" int asqtad_build_links(const int dims[4], const double* thin_dev, dou
       return ASQ_EINVAL;
     }
   const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
-  if (V / 64 + 1 >= (1L << 31)) {
+  if (V * 36 / 256 + 1 >= (1L << 31)) {
     set_last_error("asqtad_build_links: lattice too large");
     return ASQ_EINVAL;
   }
@@ -315,8 +396,15 @@ extern "C" int asqtad_build_links(const int dims[4], const double* thin_dev, dou
   a.c7 = 1.0 / (384.0 * u6);
   a.cL = -1.0 / (16.0 * u4);
   a.cN = -1.0 / (24.0 * u2);
-  const dim3 grid((unsigned)((V + kFatSites - 1) / kFatSites), 4);
-  fatten_kernel<<<grid, 256, 0, (hipStream_t)hip_stream>>>(a);
+  // The long-link output holds the site-fastest copy of the thin links while the
+  // fat links are built; the long links overwrite it last.
+  a.soa = (const double2*)long_dev;
+  hipStream_t s = (hipStream_t)hip_stream;
+  thin_soa_kernel<<<(unsigned)((V + kFatSites - 1) / kFatSites), 256, 0, s>>>(a.thin, (double2*)long_dev, V);
+  ASQ_HIP_TRY(hipGetLastError());
+  fatten_kernel<<<(unsigned)(4 * ((V + kFatSites - 1) / kFatSites)), 256, 0, s>>>(a);
+  ASQ_HIP_TRY(hipGetLastError());
+  long_link_kernel<<<(unsigned)((V * 4 + 255) / 256), 256, 0, s>>>(a);
   ASQ_HIP_TRY(hipGetLastError());
   return ASQ_OK;
 }
