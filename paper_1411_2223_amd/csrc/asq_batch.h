@@ -20,7 +20,9 @@ struct Batch {
   int rt_sloppy_norm = 1, rt_sloppy_update = 1, rt64_plain = 1, rt64_resid = 1;
   bool sweep = true;   // D_eo walks the lattice backwards (MALL reuse of the links)
   bool fold_alpha = false;  // D_eo forms alpha itself (few columns): no scalar launch between the Dslashes
-  ColState* st = nullptr;
+  bool fold_beta = false;   // the direction update forms beta itself: no scalar launch after D_eo
+  ColState* st = nullptr;   // the column states between blocks of iterations
+  ColState* st2 = nullptr;  // second copy: with fold_beta, iterations alternate between st and st2
   double* partials = nullptr;    // [ncol][nblk] partials of |r|^2 (D_eo update, residual, init)
   double* partials_p = nullptr;  // [ncol][nblk] partials of |p|^2 (direction update)
   double* partials_t = nullptr;  // [ncol][nblk] partials of |D_oe p|^2
@@ -45,6 +47,7 @@ void batch_pick_tiles(Batch& B);
 int batch_tune(Batch& B, hipStream_t s);
 int enqueue_init(const Batch& B, int c0, int n, hipStream_t s);
 int enqueue_iteration(const Batch& B, hipStream_t s);
+int enqueue_iteration(const Batch& B, hipStream_t s, ColState* in, ColState* out, bool defer_beta);
 int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s);
 int enqueue_block(const Batch& B, int iters, hipStream_t s);
 int capture_block(const Batch& B, int iters, hipStream_t cap, hipGraphExec_t* exec);

@@ -17,9 +17,15 @@ struct VecArgs {
   void* p_alt;
   ColState* st;
   double* partials;  // this kernel's partials ([ncol][nblk])
+  // direction update only: with st_out set, beta of the previous iteration is
+  // formed from beta_partials (its |r|^2 partials) and the finalised state is
+  // written to st_out (st itself is only read)
+  ColState* st_out = nullptr;
+  const double* beta_partials = nullptr;
 };
 
 int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hipStream_t s);
-int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s);
+int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s,
+                  ColState* dst = nullptr);
 
 }  // namespace asq

@@ -69,21 +69,51 @@ __global__ void __launch_bounds__(kBlock) guess_kernel(const VecArgs A) {
 
 // p_new = r + beta p into the buffer that is not current; partials of |p_new|^2
 // (as stored), which give <p, A p> = a |p|^2 + |D_oe p|^2 without a dot with A p.
+// With A.st_out set, the kernel first does the scalar kernel's OP_BETA step
+// for the previous iteration: every block sums the |r|^2 partials in the same
+// order and tree and finalises a private copy of the state, so all blocks take
+// the same decisions; block 0 writes that copy to st_out.  The state is read
+// from st only, so no block can see another block's write.
 template <class PT, class RT>
 __global__ void __launch_bounds__(kBlock) update_p_kernel(const VecArgs A) {
   const int c = blockIdx.y, sblk = blockIdx.x;
-  const ColState& S = A.st[c];
-  if (!state_on(S, MASK_ACTIVE)) return;
   using pr = typename PT::real;
   const int half = A.half;
   const int i = sblk * kBlock + (int)threadIdx.x;
+  // r and the current direction are loaded before the scalar work so the
+  // latencies overlap.  The finalised state swaps the direction buffers exactly
+  // when the column iterated, so the buffer is known from the old state; it is
+  // checked against the finalised state below.
+  const ColState& G = A.st[c];
+  const bool was_on = state_on(G, MASK_ACTIVE);  // a column that is off stays off
+  const int pbuf_guess = (A.st_out && was_on) ? G.pbuf ^ 1 : G.pbuf;
+  Vec3<pr> r, p;
+  if (was_on && i < half) {
+    r = convert<pr>(RT::load(A.r, half, c, i));
+    p = PT::load(pbuf_guess ? A.p_alt : A.p, half, c, i);
+  }
+  // the block's copy of the state lives in LDS (a per-thread copy would be
+  // placed in LDS by the compiler too, once per thread)
+  __shared__ ColState S;
+  if (A.st_out) {
+    const double s = strided_sum(A.beta_partials + (size_t)c * A.nblk, A.nblk);
+    __shared__ double shb[kBlock / 64];
+    const double tot = block_sum(s, shb);  // valid in thread 0
+    if (threadIdx.x == 0) {
+      S = G;
+      if (state_on(S, MASK_ACTIVE)) finalize_column(S, tot, OP_BETA);
+      if (sblk == 0) A.st_out[c] = S;
+    }
+  } else if (threadIdx.x == 0) {
+    S = G;
+  }
+  __syncthreads();
+  if (!state_on(S, MASK_ACTIVE)) return;
   double d = 0;
   if (i < half) {
-    const void* pcur = S.pbuf ? A.p_alt : A.p;
+    if (S.pbuf != pbuf_guess) p = PT::load(S.pbuf ? A.p_alt : A.p, half, c, i);  // uniform; not expected
     void* pnew = S.pbuf ? A.p : A.p_alt;
     const pr beta = (pr)S.beta;
-    const Vec3<pr> r = convert<pr>(RT::load(A.r, half, c, i));
-    const Vec3<pr> p = PT::load(pcur, half, c, i);
     Vec3<pr> v;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -120,14 +150,27 @@ __global__ void __launch_bounds__(kBlock) flush_x_kernel(const VecArgs A) {
 // OP_INIT_GUESS: |b|^2 = sum(pa), |r|^2 = sum(pb);
 // OP_BETA, OP_RU, OP_INIT: the one sum of pb.  The partials are
 // loaded before the column state so that the two latencies overlap.
+// With dst set (OP_BETA only), the state is read from st and the finalised
+// copy written to dst, whether or not the column takes part.
 __global__ void __launch_bounds__(kBlock) reduce_kernel(ColState* st, const double* pa, const double* pb, int nblk,
-                                                        int op) {
+                                                        int op, ColState* dst) {
   const int c = blockIdx.x;
   const bool two = op == OP_ALPHA || op == OP_INIT_GUESS;
   const double vb = strided_sum(pb + (size_t)c * nblk, nblk);
   const double va = two ? strided_sum(pa + (size_t)c * nblk, nblk) : 0.0;
-  ColState& S = st[c];
   const int mask = (op == OP_ALPHA || op == OP_BETA) ? MASK_ACTIVE : (op == OP_RU ? MASK_RELIABLE : MASK_ALL);
+  if (dst) {
+    ColState S = st[c];
+    const bool on = state_on(S, mask);
+    __shared__ double shd[kBlock / 64];
+    const double s = on ? block_sum(vb, shd) : 0.0;  // uniform branch
+    if (threadIdx.x == 0) {
+      if (on) finalize_column(S, s, op);
+      dst[c] = S;
+    }
+    return;
+  }
+  ColState& S = st[c];
   if (!state_on(S, mask)) return;
   __shared__ double sh[2][kBlock / 64];
   const double s = block_sum(vb, sh[0]);
@@ -225,9 +268,11 @@ int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hip
   return ASQ_EINVAL;
 }
 
-int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s) {
+int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s,
+                  ColState* dst) {
   if ((op == OP_ALPHA || op == OP_INIT_GUESS) && !pa) return ASQ_EINVAL;
-  reduce_kernel<<<(unsigned)ncol, kBlock, 0, s>>>(st, pa, pb, nblk, op);
+  if (dst && (op != OP_BETA || dst == st)) return ASQ_EINVAL;
+  reduce_kernel<<<(unsigned)ncol, kBlock, 0, s>>>(st, pa, pb, nblk, op, dst);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }
 

@@ -65,7 +65,7 @@ size_t batch_bytes(const asq_gauge* g, int ncol, int mode, bool with_bx) {
   const size_t half = (size_t)g->geom.half;
   const int pt = mode_pt(mode), rt = mode_rt(mode);
   size_t n = 0;
-  n += align_up((size_t)ncol * sizeof(ColState), 256);
+  n += 2 * align_up((size_t)ncol * sizeof(ColState), 256);  // states (two copies)
   n += 3 * align_up((size_t)ncol * g->nblk * sizeof(double), 256);  // partials (three sets)
   n += align_up((size_t)ncol * half * vec_site_bytes(rt), 256);      // r
   n += 3 * align_up((size_t)ncol * half * vec_site_bytes(pt), 256);  // p, p_alt, t
@@ -109,11 +109,14 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
     B.b = const_cast<double*>(b);
     B.x = x;
   }
+  B.st2 = (ColState*)take((size_t)ncol * sizeof(ColState));
   B.link = sloppy_link(g, mode);
   B.sweep = env_flag("ASQ_SWEEP", true);
   // Each D_eo block re-sums 2 x nblk partials per column of its tile, which is
   // cheap next to the Dslash only for narrow batches.
   B.fold_alpha = ncol <= kFoldAlphaCols && env_flag("ASQ_FOLD_ALPHA", true);
+  // Likewise each direction-update block re-sums nblk partials of its column.
+  B.fold_beta = ncol <= kFoldAlphaCols && env_flag("ASQ_FOLD_BETA", true);
   batch_pick_tiles(B);
   return ASQ_OK;
 }
@@ -200,16 +203,29 @@ int enqueue_init_guess(const Batch& B, hipStream_t s) {
   return launch_reduce(OP_INIT_GUESS, B.st, B.partials_p, B.partials, g->nblk, B.ncol, s);
 }
 
-int enqueue_iteration(const Batch& B, hipStream_t s) {
+// One CG iteration.  The direction update reads the column states from `in`;
+// the rest of the iteration uses `out`.  in == out: beta was formed by the
+// scalar launch at the end of the previous iteration.  in != out: the direction
+// update forms it from the |r|^2 partials and writes the finalised states to
+// out (the two copies alternate, so no kernel writes the copy it reads).  With
+// defer_beta this iteration's own beta is left to the next direction update,
+// or to the scalar launch at the end of the block.
+int enqueue_iteration(const Batch& B, hipStream_t s, ColState* in, ColState* out, bool defer_beta) {
   const Gauge_t* g = B.g;
   const void* L = g->links[B.link];
   // p_new = r + beta p, partials of |p_new|^2
   VecArgs v = vargs(B, 0);
+  v.st = in;
   v.partials = B.partials_p;
+  if (in != out) {
+    v.st_out = out;
+    v.beta_partials = B.partials;
+  }
   int rc = launch_vec_kernel(VK_P, B.pt, B.rt, v, B.ncol, s);
   if (rc) return rc;
   // t = D_oe p_new, partials of |t|^2
   DslashArgs d1 = dargs(B, 1, B.p, B.t, MASK_ACTIVE);
+  d1.st = out;
   d1.links = L;
   d1.in_alt = B.p_alt;
   d1.in_sel = 1;
@@ -218,11 +234,12 @@ int enqueue_iteration(const Batch& B, hipStream_t s) {
   if (rc) return rc;
   // alpha = rr / (a |p|^2 + |t|^2): a scalar launch, or inside D_eo
   if (!B.fold_alpha) {
-    rc = launch_reduce(OP_ALPHA, B.st, B.partials_p, B.partials_t, g->nblk, B.ncol, s);
+    rc = launch_reduce(OP_ALPHA, out, B.partials_p, B.partials_t, g->nblk, B.ncol, s);
     if (rc) return rc;
   }
   // Ap = a p - D_eo t; r -= alpha Ap; x += alpha p; partials of |r|^2 (backward sweep)
   DslashArgs d2 = dargs(B, 0, B.t, nullptr, MASK_ACTIVE);
+  d2.st = out;
   if (B.fold_alpha) {
     d2.apa = B.partials_p;
     d2.apb = B.partials_t;
@@ -236,9 +253,12 @@ int enqueue_iteration(const Batch& B, hipStream_t s) {
   d2.reverse = B.sweep ? 1 : 0;
   rc = launch_dslash(B.link, B.pt, B.rt, EPI_UPDATE, B.rt_sloppy_update, d2, s);
   if (rc) return rc;
+  if (defer_beta) return ASQ_OK;
   // beta, triggers, p buffer swap
-  return launch_reduce(OP_BETA, B.st, nullptr, B.partials, g->nblk, B.ncol, s);
+  return launch_reduce(OP_BETA, out, nullptr, B.partials, g->nblk, B.ncol, s);
 }
+
+int enqueue_iteration(const Batch& B, hipStream_t s) { return enqueue_iteration(B, s, B.st, B.st, false); }
 
 // r = b - A x with FP64 links and vectors for the columns that asked for it,
 // then the decision on the true residual.
@@ -266,9 +286,22 @@ int enqueue_reliable(const Batch& B, int mask, int op, hipStream_t s) {
   return launch_reduce(op, B.st, nullptr, B.partials, g->nblk, B.ncol, s);
 }
 
+// `iters` iterations, then the reliable update of the columns that asked for
+// one.  With fold_beta, every iteration after the first takes the previous
+// beta inside its direction update, the states alternating between st and st2,
+// and one scalar launch finalises the last beta back into st, so the block
+// starts and ends with the states in st.
 int enqueue_block(const Batch& B, int iters, hipStream_t s) {
+  ColState* cur = B.st;
   for (int k = 0; k < iters; ++k) {
-    const int rc = enqueue_iteration(B, s);
+    ColState* next = (B.fold_beta && k > 0) ? (cur == B.st ? B.st2 : B.st) : cur;
+    const int rc = enqueue_iteration(B, s, cur, next, B.fold_beta);
+    if (rc) return rc;
+    cur = next;
+  }
+  if (B.fold_beta && iters > 0) {
+    const int rc = cur == B.st ? launch_reduce(OP_BETA, B.st, nullptr, B.partials, B.g->nblk, B.ncol, s)
+                               : launch_reduce(OP_BETA, cur, nullptr, B.partials, B.g->nblk, B.ncol, s, B.st);
     if (rc) return rc;
   }
   return enqueue_reliable(B, MASK_RELIABLE, OP_RU, s);

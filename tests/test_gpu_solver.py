@@ -286,3 +286,27 @@ def test_recon12_mixed32_matches_tolerance(asq):
     x, res = _solve(asq, g, masses, b, "mixed32")
     r = oracle_resid_cols(dims, fat, lng, masses, b, x)
     assert res.rc == 0 and np.all(r <= TOL)
+
+
+@pytest.mark.parametrize("mode,poll", [("f64", 16), ("mixed32", 16), ("mixed32", 5), ("mixed16", 7), ("mixed32", 1)])
+def test_folded_scalars_match_scalar_launches(asq, mode, poll, monkeypatch):
+    """Narrow batches form alpha inside D_eo and beta inside the direction update
+    (alternating two state copies); with both folds switched off every scalar
+    comes from the one-block reduction launch.  The sums use the same order and
+    tree, so x and the iteration counts must be bitwise equal.  poll = 16 ends a
+    block on the second state copy, 5 on the first, 1 folds nothing."""
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    b = synth.make_sources(dims, 2, 47)
+    masses = [0.05, 0.1]
+    x1, r1 = _solve(asq, g, masses, b, mode, poll_iters=poll)
+    monkeypatch.setenv("ASQ_FOLD_ALPHA", "0")
+    monkeypatch.setenv("ASQ_FOLD_BETA", "0")
+    x2, r2 = _solve(asq, g, masses, b, mode, poll_iters=poll)
+    assert r1.rc == 0 and r2.rc == 0
+    assert np.array_equal(x1, x2)
+    assert [s["iters"] for s in r1.stats] == [s["iters"] for s in r2.stats]
+    assert [s["reliable_updates"] for s in r1.stats] == [s["reliable_updates"] for s in r2.stats]
+    for c, m in enumerate(masses):
+        assert oracle.true_residual(dims, fat, lng, m, b[c], x1[c]) <= TOL
