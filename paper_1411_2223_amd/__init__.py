@@ -272,16 +272,20 @@ class Gauge:
         nbytes = asq_gauge_bytes(ctypes.byref(self.desc))
         if nbytes == 0:
             raise AsqError(ASQ_EINVAL, "asq_gauge_bytes")
-        self.storage = empty_bytes(nbytes, device)
         V = int(np.prod(self.dims))
 
         def up(a):
             if isinstance(a, torch.Tensor):  # already on the device (e.g. from build_links)
+                if (a.dtype != torch.float64 or a.numel() != V * 4 * 18 or not a.is_contiguous()
+                        or a.device.type != "cuda"):
+                    raise AsqError(ASQ_EINVAL, "Gauge: device links must be contiguous float64 CUDA tensors "
+                                               "of V*4*18 reals")
                 return a
             a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(V, 4, 3, 3))
             return torch.from_numpy(a.view(np.float64)).to(device)
 
         fat_d, lng_d = up(fat), up(lng)
+        self.storage = empty_bytes(nbytes, device)
         h = ctypes.c_void_p()
         rc = asq_gauge_create(ctypes.byref(self.desc), fat_d.data_ptr(), lng_d.data_ptr(), self.storage.data_ptr(),
                               nbytes, stream_ptr(stream), ctypes.byref(h))

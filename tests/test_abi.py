@@ -134,3 +134,13 @@ def test_build_links_binding_checks_shapes(lib):
     with pytest.raises(asq.AsqError):
         asq.build_links(dims, torch.zeros(n, dtype=torch.float64), fat=torch.zeros(n + 1, dtype=torch.float64),
                         lng=torch.zeros(n, dtype=torch.float64))
+
+
+def test_gauge_rejects_malformed_device_links(lib):
+    """A tensor passed as links must hold V*4*18 float64 values on the GPU; checked before any call."""
+    import torch
+
+    dims = (4, 4, 4, 4)
+    bad = torch.zeros(256 * 4 * 18 - 2, dtype=torch.float64)
+    with pytest.raises(asq.AsqError):
+        asq.Gauge(dims, bad, bad, device="cpu")
