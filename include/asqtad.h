@@ -157,7 +157,11 @@ int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, con
    order << 12: cols = 1, 2, 4 or 8 columns per thread; pipe = 1 for the
    software-pipelined hop loop; order = 0 walks the column tiles of a site block
    together, 1, 2, 3 walk tile by tile inside groups of 16, 64 or all site
-   blocks.  Returns ASQ_EINVAL for any other code. */
+   blocks.  variant = 0x10000 | 32 | order << 12 selects the matrix-core form
+   (prec F16 with FP32 18-real links only): 32 columns per block, FP32 products
+   on the matrix cores.  It rounds differently from the other variants (within
+   the FP16 tolerance) and is bitwise reproducible against itself.  Returns
+   ASQ_EINVAL for any other code. */
 int asqtad_dslash_eo_variant(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
                              void* out_dev, int variant, void* hip_stream);
 

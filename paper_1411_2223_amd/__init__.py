@@ -107,6 +107,12 @@ def variant_code(cols: int, pipe: bool = False, order: int = 0) -> int:
     return int(cols) | (0x100 if pipe else 0) | (int(order) << 12)
 
 
+def variant_code_mfma(order: int = 0) -> int:
+    """The matrix-core launch variant (FP32 18-real links with FP16 vectors only):
+    32 columns per block, with one of the four block orders."""
+    return 0x10000 | 32 | (int(order) << 12)
+
+
 # Every launch variant the library builds: (cols, pipe, order).
 VARIANTS_ALL = [(c, p, o) for o in (0, 1, 2, 3) for p in (False, True) for c in (1, 2, 4, 8)]
 

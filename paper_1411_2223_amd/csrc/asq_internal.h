@@ -131,6 +131,10 @@ int launch_dslash_i16r12(int in_kind, int epi, int rtile, const DslashArgs& a, h
 // 16, 64 or all site blocks.
 constexpr int kPipeBit = 0x100;
 constexpr int kOrderShift = 12;
+// The matrix-core form (FP32 18-real links with FP16-with-norm vectors only):
+// kMfmaBit | kMfmaTile | order << kOrderShift, 32 columns per block of sites.
+constexpr int kMfmaBit = 0x10000;
+constexpr int kMfmaTile = 32;
 inline int rtile_order(int rtile) { return (rtile >> kOrderShift) & 3; }
 inline int order_group(int order, int nblk) { return order == 0 ? 0 : (order == 1 ? 16 : (order == 2 ? 64 : nblk)); }
 // Whether the library builds launch variant rtile (for any link and vector tier).

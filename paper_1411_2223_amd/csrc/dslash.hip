@@ -5,9 +5,12 @@
 namespace asq {
 
 bool variant_built(int link_kind, int in_kind, int rtile) {
-  (void)link_kind;
-  (void)in_kind;
   const int cols = rtile & 0xff;
+  if (rtile & kMfmaBit) {
+    // matrix-core form: one tile width, no pipelined form
+    if ((rtile & ~(kMfmaBit | 0xff | (3 << kOrderShift))) != 0) return false;
+    return link_kind == LINK_F32_R18 && in_kind == VEC_F16 && cols == kMfmaTile;
+  }
   if ((rtile & ~(0xff | kPipeBit | (3 << kOrderShift))) != 0) return false;
   return cols == 1 || cols == 2 || cols == 4 || cols == 8;
 }

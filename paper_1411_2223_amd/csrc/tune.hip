@@ -82,7 +82,11 @@ int forced_variant(int link, int in) {
 
 int tuned_rtile(const asq_gauge* g, int link, int in, int out, int epi, int ncol) {
   const int fv = forced_variant(link, in);
-  if (fv >= 0 && (fv & 0xff) <= (ncol > 1 ? ncol : 1)) return fv;
+  // a forced tile wider than the batch is ignored, except the matrix-core form,
+  // which masks its idle columns; that form takes alpha from the column state,
+  // so it is not forced where the update launch forms alpha itself
+  if (fv >= 0 && !(fv & kMfmaBit) && (fv & 0xff) <= (ncol > 1 ? ncol : 1)) return fv;
+  if (fv >= 0 && (fv & kMfmaBit) && ncol > kFoldAlphaMaxTile) return fv;
   std::lock_guard<std::mutex> lk(g_mu);
   load_cache_locked();
   auto it = g_cache.find(key_of(g, link, in, out, epi, ncol));

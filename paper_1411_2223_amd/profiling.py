@@ -18,7 +18,7 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ("csrc/dslash.hip", "csrc/dslash_impl.h", "csrc/dslash_f64.hip", "csrc/dslash_f32.hip",
+KERNEL_SOURCES = ("csrc/dslash.hip", "csrc/dslash_impl.h", "csrc/dslash_mfma.h", "csrc/dslash_f64.hip", "csrc/dslash_f32.hip",
                   "csrc/dslash_r12.hip", "csrc/dslash_i16.hip", "csrc/asq_device.h", "csrc/asq_reduce.h",
                   "csrc/asq_internal.h")
 

@@ -142,3 +142,39 @@ def test_non_su3_links_rejected_for_compression(asq):
     assert e.value.code == asq.ASQ_ENOTSU3
     # 18-real tiers take any links
     asq.Gauge(dims, fat, fat, precs=("f64", "f32"), recon=18)
+
+
+@pytest.mark.parametrize("dims,nrhs", [((6, 4, 8, 10), 13), ((4, 4, 4, 8), 40), ((8, 6, 4, 12), 70)])
+def test_mfma_variant(asq, dims, nrhs):
+    # The matrix-core form (FP32 18-real links, FP16 vectors): the oracle's FP16
+    # tolerance for both parities, bitwise reproducible, every block order equal.
+    # 13 and 40 columns leave idle lanes in a 32-column tile; 960 and 1152 output
+    # sites a ragged last block.
+    import torch
+
+    g, fat, lng = _gauge(asq, dims, 0.3, 5, 18)
+    half = int(np.prod(dims)) // 2
+    for out_parity in (0, 1):
+        v = synth.make_sources(dims, nrhs, 81 + out_parity)
+        vin = asq.vec_to_device(v, "f16")
+        ref = oracle_dslash_cols(dims, fat, lng, out_parity, quantize_like_device(v, "f16"))
+        outs = []
+        for order in (0, 1, 2, 3, 0):
+            out = g.dslash(out_parity, vin, "f16", nrhs, variant=asq.variant_code_mfma(order))
+            torch.cuda.synchronize()
+            outs.append(out)
+        err = rel_err(asq.vec_from_device(outs[0], nrhs, half, "f16"), ref)
+        print(f"mfma dims={dims} nrhs={nrhs} parity={out_parity} max rel err {err.max():.3e}", flush=True)
+        assert err.max() <= TOL["f16"]
+        assert all(torch.equal(outs[0], o) for o in outs[1:])
+
+
+def test_mfma_variant_only_for_its_tier(asq):
+    # FP32 vectors, 12-real links and FP64 refuse the matrix-core code without launching
+    dims = (4, 4, 4, 8)
+    for prec, recon in (("f32", 18), ("f64", 18), ("f16", 12)):
+        g, fat, lng = _gauge(asq, dims, 0.3, 14112223, recon)
+        vin = asq.vec_to_device(synth.make_sources(dims, 8, 2), prec)
+        with pytest.raises(asq.AsqError) as e:
+            g.dslash(1, vin, prec, 8, variant=asq.variant_code_mfma(0))
+        assert e.value.code == asq.ASQ_EINVAL

@@ -310,3 +310,22 @@ def test_folded_scalars_match_scalar_launches(asq, mode, poll, monkeypatch):
     assert [s["reliable_updates"] for s in r1.stats] == [s["reliable_updates"] for s in r2.stats]
     for c, m in enumerate(masses):
         assert oracle.true_residual(dims, fat, lng, m, b[c], x1[c]) <= TOL
+
+
+def test_mfma_variant_in_the_solver(asq, monkeypatch):
+    # The matrix-core Dslash with its NORM and UPDATE epilogues, forced for a
+    # mixed16 batch (FP32 18-real links): every column reaches the FP64 true
+    # residual (checked by the oracle) while columns stop at different iterations.
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    masses = [0.05, 0.1, 0.02, 0.2, 0.07, 0.03, 0.15, 0.05, 0.1, 0.04, 0.3, 0.06, 0.08, 0.5, 0.01]
+    b = synth.make_sources(dims, len(masses), 44)
+    monkeypatch.setenv("ASQ_VARIANT", str(asq.variant_code_mfma(0)))
+    x, r = _solve(asq, g, masses, b, "mixed16")
+    assert r.rc == 0
+    resid = oracle_resid_cols(dims, fat, lng, masses, b, x)
+    print(f"mfma solver iters={[s['iters'] for s in r.stats]} resid max={resid.max():.3e}", flush=True)
+    assert np.all(resid <= TOL)
+    x2, r2 = _solve(asq, g, masses, b, "mixed16")
+    assert np.array_equal(x, x2)
