@@ -654,7 +654,7 @@ def run_asqtad(args, asq, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the library has no multi-GPU path); use --gpus 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

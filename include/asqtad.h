@@ -257,7 +257,7 @@ int asq_copy_probe(void* dst_dev, const void* src_dev, size_t n, void* hip_strea
 /* HBM read probe: reads n bytes of src (n a multiple of 16, 16-byte aligned)
    and writes one 16-byte XOR digest per block to sink_dev (at least
    asq_read_probe_blocks(n) x 16 bytes), asynchronous.  The read-only ceiling
-   next to which a read-dominated kernel such as the Dslash is judged. */
+   against which a read-dominated kernel such as the Dslash is measured. */
 int asq_read_probe(const void* src_dev, size_t n, void* sink_dev, void* hip_stream);
 size_t asq_read_probe_blocks(size_t n);
 

@@ -1,4 +1,4 @@
-// asq_solver.h -- interfaces between the CG driver and its vector/reduction kernels.
+// asq_solver.h -- interfaces between the CG host loop and its vector/reduction kernels.
 #pragma once
 #include "asq_internal.h"
 

@@ -1,4 +1,4 @@
-// solver.hip -- CG drivers on even sites: plain FP64 CG and mixed-precision
+// solver.hip -- CG solvers on even sites: plain FP64 CG and mixed-precision
 // CG with reliable updates (the paper's inverter does most of its arithmetic
 // in single precision, section "GTX Titan Black"; the QUDA CG it moves to is
 // mixed precision as well, section "CPS & QUDA").
