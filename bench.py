@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--serve-streams", type=int, default=4, help="serving: concurrent runs (streams)")
     ap.add_argument("--rate", type=float, default=50.0, help="serving: Poisson arrival rate (requests/s)")
     ap.add_argument("--no-oracle-check", action="store_true",
-                    help="three-level: skip the host FP64 oracle residual of every column")
+                    help="three-level and asqtad: skip the host FP64 oracle residuals")
     ap.add_argument("--u0", type=float, default=1.0, help="asqtad: tadpole factor of the link construction")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch the Dslash tiers and a 1 GiB copy probe (for hardware-counter runs)")
@@ -614,6 +614,40 @@ def run_asqtad(args, asq, torch):
     st = last.stats[0]
     log(f"mixed32 solve on the built links: {secs * 1e3:.1f} ms, iters={st['iters']} "
         f"resid={st['true_resid']:.3e}")
+    # the full-lattice system M x = b (M = 2m + D) on the built links: even-odd
+    # reduction, the even solve and the odd-site reconstruction
+    bfull = synth.make_sources(dims, 2, synth.source_seed(w["index"]) + 7)  # [even half, odd half]
+    bfd = torch.cat([asq.vec_to_device(bfull[0:1], "f64"), asq.vec_to_device(bfull[1:2], "f64")])
+    xf = torch.empty_like(bfd)
+    work_full = asq.empty_bytes(asq.asq_full_workspace_bytes(g.handle, 1, asq.MODES["mixed32"]))
+    full_times = []
+    rf = None
+    for k in range(1 + max(1, args.steps // 3)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rf = g.solve_full([mass], bfd, mode="mixed32", work=work_full, x=xf, stream=stream)
+        torch.cuda.synchronize()
+        if rf.rc != 0:
+            raise SystemExit(f"full solve failed rc={rf.rc}")
+        if k > 0:
+            full_times.append(time.perf_counter() - t0)
+    sf = rf.stats[0]
+    log(f"full M x = b on the built links: {np.median(full_times) * 1e3:.1f} ms, iters={sf['iters']} "
+        f"|b - M x|/|b|={sf['true_resid']:.3e}")
+    full_oracle = None
+    if not args.no_oracle_check:
+        import oracle
+
+        log("oracle: links of every site and the full residual ...")
+        ofat, olng = oracle.asqtad_links(dims, U, u0)
+        half = V // 2
+        xe = asq.vec_from_device(xf[0:1], 1, half, "f64")[0]
+        xo = asq.vec_from_device(xf[1:2], 1, half, "f64")[0]
+        re = bfull[0] - 2 * mass * xe - oracle.dslash(dims, ofat, olng, 0, xo)
+        ro = bfull[1] - 2 * mass * xo - oracle.dslash(dims, ofat, olng, 1, xe)
+        full_oracle = float(np.sqrt((np.vdot(re, re) + np.vdot(ro, ro)).real /
+                                    (np.vdot(bfull[0], bfull[0]) + np.vdot(bfull[1], bfull[1])).real))
+        log(f"oracle |b - M x|/|b| with its own links: {full_oracle:.3e}")
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -645,7 +679,10 @@ def run_asqtad(args, asq, torch):
                         "flops_per_call": flops, "ms_per_call": dt * 1e3},
            "solve_mixed32": {"ms": secs * 1e3, "time_to_solution": time_stats(times), "iters": st["iters"],
                              "reliable_updates": st["reliable_updates"], "true_resid": st["true_resid"],
-                             "mass": mass}}
+                             "mass": mass},
+           "full_solve_mixed32": {"ms": float(np.median(full_times) * 1e3), "time_to_solution": time_stats(full_times),
+                                  "iters": sf["iters"], "true_resid": sf["true_resid"],
+                                  "oracle_true_resid": full_oracle, "mass": mass}}
     if cpu:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
