@@ -329,3 +329,30 @@ def test_mfma_variant_in_the_solver(asq, monkeypatch):
     assert np.all(resid <= TOL)
     x2, r2 = _solve(asq, g, masses, b, "mixed16")
     assert np.array_equal(x, x2)
+
+
+def test_solver_rejects_bad_arguments(asq):
+    # masses, tolerances, trigger and iteration limits are checked on the host before any launch
+    dims = (4, 4, 4, 8)
+    fat, lng = gauge_arrays(dims, 0.3, 14112223)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    b = asq.vec_to_device(synth.make_sources(dims, 1, 45), "f64")
+    bad = [dict(masses=[0.0]), dict(masses=[-0.1]), dict(masses=[float("nan")]), dict(masses=[float("inf")]),
+           dict(tol=0.0), dict(tol=float("nan")), dict(delta=1.0), dict(delta=-0.5), dict(maxiter=0),
+           dict(mode="mixed16")]  # no FP16-tier links kept: the 16-bit sloppy tier falls back to FP32 links
+    for kw in bad:
+        args = dict(masses=[0.1], mode="mixed32")
+        args.update(kw)
+        masses = args.pop("masses")
+        if kw.get("mode") == "mixed16":
+            res = g.solve(masses, b, **args)  # valid: FP16 vectors with the FP32 links
+            assert res.rc == 0
+            continue
+        with pytest.raises(asq.AsqError) as e:
+            g.solve(masses, b, **args)
+        assert e.value.code == asq.ASQ_EINVAL, kw
+    # a gauge without FP32 links cannot run the mixed modes
+    g64 = asq.Gauge(dims, fat, lng, precs=("f64",), recon=18)
+    with pytest.raises(asq.AsqError) as e:
+        g64.solve([0.1], b, mode="mixed32")
+    assert e.value.code == asq.ASQ_EINVAL
