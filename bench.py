@@ -323,6 +323,14 @@ def run_single(args, asq, torch):
     work64 = g.workspace(1, "f64")
     t64, times64, r64 = solve_series(g, [mass], bd, "f64", w["tol"], 3, 1, stream, work64, x)
     log(f"f64 CG: iters={r64.stats[0]['iters']} resid={r64.stats[0]['true_resid']:.3e} {t64 * 1e3:.1f} ms")
+    # the other sloppy tier for comparison: FP16-with-norm vectors, same FP32 links and arithmetic
+    other = "mixed16" if args.mode == "mixed32" else None
+    t_other = r_other = None
+    if other:
+        work_o = g.workspace(1, other)
+        t_other, times_o, r_other = solve_series(g, [mass], bd, other, w["tol"], 5, 1, stream, work_o, x)
+        log(f"{other} CG: iters={r_other.stats[0]['iters']} resid={r_other.stats[0]['true_resid']:.3e} "
+            f"{t_other * 1e3:.1f} ms")
 
     # dominant kernel: the sloppy single-RHS Dslash
     tprec = {"mixed32": "f32", "f64": "f64", "mixed16": "f16"}[args.mode]
@@ -367,6 +375,8 @@ def run_single(args, asq, torch):
         "f64_cg_ms": t64 * 1e3,
         "f64_cg_iterations": r64.stats[0]["iters"],
         "speedup_vs_f64_cg": t64 / secs,
+        "fp16_vectors_time_to_solution_ms": t_other * 1e3 if t_other else None,
+        "fp16_vectors_iterations": r_other.stats[0]["iters"] if r_other else None,
         "dslash_gbs": achieved,
         "dslash_f64_gbs": f64_gbs,
         "copy_probe_gbs": copy_gbs,
