@@ -242,7 +242,8 @@ int serve_submit(asq_server* s, int gauge_id, int nrhs, const double* masses, co
    per-column stats (host array [nrhs], may be NULL) and latency from submit to
    completion (may be NULL).  A completed ticket is released by this call. */
 int serve_poll(asq_server* s, uint64_t ticket, asq_cg_stats* per_rhs, double* latency_s);
-/* Waits for in-flight work, then frees the server. */
+/* Completes every submitted request, queued ones included (their x_dev is
+   written), then frees the server; tickets not yet polled are discarded. */
 int serve_destroy(asq_server* s);
 
 /* ---- misc ------------------------------------------------------------------ */

@@ -120,3 +120,28 @@ def test_admission_limits(asq):
     res = _wait(srv, {t1: 2, t2: 2})
     assert res[t1][0] == 0 and res[t2][0] == 0
     srv.close()
+
+
+def test_destroy_completes_submitted_requests(asq):
+    # closing the server with requests still queued and running finishes them:
+    # every x is written and meets the tolerance without a poll
+    import torch
+
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    srv = asq.Server(1 << 28, max_streams=1, max_cols=2)
+    gid = srv.register(g)
+    reqs = []
+    for k in range(4):
+        masses = [0.05 + 0.02 * k, 0.1]
+        b = synth.make_sources(dims, 2, 400 + k)
+        bd = asq.vec_to_device(b, "f64")
+        x = torch.zeros_like(bd)
+        srv.submit(gid, masses, bd, x, mode="mixed32")
+        reqs.append((masses, b, bd, x))
+    srv.close()
+    torch.cuda.synchronize()
+    for masses, b, bd, x in reqs:
+        xm = asq.vec_from_device(x, len(masses), g.half, "f64")
+        assert np.all(oracle_resid_cols(dims, fat, lng, masses, b, xm) <= 1e-10)
