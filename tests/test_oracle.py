@@ -8,6 +8,7 @@
 * gauge covariance D[U^g](g psi) = g D[U] psi with random SU(3) g
 * brute-force dense solves against CG, and the CG solution's covariance
 * finite termination of CG on the free field (few distinct eigenvalues)
+* an independent whole-lattice (shifted-array) form of D on random links
 """
 import itertools
 import os
@@ -291,3 +292,55 @@ def test_true_residual_of_exact_solution_and_zero_source():
 def test_oracle_rejects_odd_dims():
     with pytest.raises(ValueError):
         oracle.dslash((5, 4, 4, 4), np.zeros((320, 4, 3, 3)), np.zeros((320, 4, 3, 3)), 0, np.zeros((160, 3)))
+
+
+def _numpy_dslash_full(dims, fat, lng, psi):
+    """D on the whole lattice with whole-lattice shifts: an implementation independent of the
+    oracle's site loop.  fat, lng (V, 4, 3, 3); psi (V, 3) in lexicographic order."""
+    X, Y, Z, T = dims
+    F = fat.reshape(T, Z, Y, X, 4, 3, 3)
+    L = lng.reshape(T, Z, Y, X, 4, 3, 3)
+    P = psi.reshape(T, Z, Y, X, 3)
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    eta = [np.ones_like(x), (-1.0) ** x, (-1.0) ** (x + y), (-1.0) ** (x + y + z)]
+    out = np.zeros_like(P)
+    for mu in range(4):
+        axis = 3 - mu
+
+        def shifted(A, h):
+            # A(x + h mu), periodic (the fermion boundary sign is bc below)
+            return np.roll(A, -h, axis=axis)
+
+        def bc(h):
+            # -1 where x + h mu leaves [0, T) in time (only for mu = t)
+            if mu != 3:
+                return np.ones_like(t)
+            u = t + h
+            return np.where((u < 0) | (u >= T), -1.0, 1.0)
+
+        Fm, Lm = F[..., mu, :, :], L[..., mu, :, :]
+        dag = lambda A: np.conj(np.swapaxes(A, -1, -2))
+        term = np.einsum("...ab,...b->...a", Fm, shifted(P, 1)) * bc(1)[..., None]
+        term -= np.einsum("...ab,...b->...a", dag(shifted(Fm, -1)), shifted(P, -1)) * bc(-1)[..., None]
+        term += np.einsum("...ab,...b->...a", Lm, shifted(P, 3)) * bc(3)[..., None]
+        term -= np.einsum("...ab,...b->...a", dag(shifted(Lm, -3)), shifted(P, -3)) * bc(-3)[..., None]
+        out += eta[mu][..., None] * term
+    return out.reshape(-1, 3)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (6, 4, 4, 8)])
+def test_dslash_matches_independent_numpy_form(dims):
+    # random links and vectors: the oracle's per-site loop against whole-lattice shifts
+    fat, lng = synth.make_gauge(dims, 0.5, 17)
+    V = int(np.prod(dims))
+    rng = np.random.Generator(np.random.PCG64(18))
+    psi = rng.standard_normal((V, 3)) + 1j * rng.standard_normal((V, 3))
+    c = lex_coords(dims)
+    par = c.sum(axis=1) % 2
+    for out_parity in (0, 1):
+        src = psi[par == 1 - out_parity]
+        got = oracle.dslash(dims, fat, lng, out_parity, src)
+        # the numpy form on the whole lattice with the other parity zeroed
+        masked = np.where((par == 1 - out_parity)[:, None], psi, 0)
+        want = _numpy_dslash_full(dims, fat, lng, masked)[par == out_parity]
+        assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
