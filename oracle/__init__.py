@@ -13,7 +13,8 @@ covariance, hand-derived point-source values, brute-force dense solves and the
 finite termination of CG on an operator with few distinct eigenvalues.  The
 asqtad link construction is pinned by the free-field normalisation, the closed
 form for a uniform abelian flux, gauge covariance and an independent nested
-staple evaluation.
+staple evaluation; the plaquette by the free field, the uniform flux and gauge
+invariance.
 """
 from __future__ import annotations
 
@@ -60,6 +61,8 @@ def lib():
         L.oracle_asqtad_links.argtypes = [_iptr, _dptr, ctypes.c_double, ctypes.POINTER(ctypes.c_long),
                                           ctypes.c_long, _dptr, _dptr]
         L.oracle_asqtad_links.restype = ctypes.c_int
+        L.oracle_plaquette.argtypes = [_iptr, _dptr]
+        L.oracle_plaquette.restype = ctypes.c_double
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -154,6 +157,16 @@ def asqtad_links(dims, thin, u0: float = 1.0, sites=None):
     if rc != 0:
         raise ValueError(f"oracle_asqtad_links failed ({rc})")
     return fat, lng
+
+
+def plaquette(dims, thin) -> float:
+    """Mean plaquette (1/3) Re tr of the thin links over every site and plane."""
+    V = int(np.prod(dims))
+    U = _c128(thin, (V, 4, 3, 3))
+    p = float(lib().oracle_plaquette(_dims(dims), _p(U)))
+    if p == -1.0:
+        raise ValueError("oracle_plaquette: invalid extents")
+    return p
 
 
 def num_threads() -> int:

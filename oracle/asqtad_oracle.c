@@ -349,3 +349,27 @@ int oracle_asqtad_links(const int dims[4], const double* thin, double u0, const 
   }
   return 0;
 }
+
+/*
+ * Mean plaquette of thin links (the tadpole factor of the asqtad coefficients
+ * is u0 = P^(1/4)):
+ *   P = 1 / (6 V) sum_x sum_{mu < nu} (1/3) Re tr[ U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag ]
+ * Thin links are periodic in every direction.  Summed serially in site order.
+ */
+double oracle_plaquette(const int dims[4], const double* thin) {
+  if (check_dims(dims)) return -1.0;
+  const long V = vol(dims);
+  double total = 0;
+  for (long lex = 0; lex < V; ++lex) {
+    int c[4];
+    coords_of(dims, lex, c);
+    for (int mu = 0; mu < 4; ++mu)
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        cplx acc[9] = {0};
+        const int loop[4] = {mu + 1, nu + 1, -(mu + 1), -(nu + 1)};
+        add_path(dims, thin, c, loop, 4, 1.0, acc);
+        total += creal(acc[0] + acc[4] + acc[8]) / 3.0;
+      }
+  }
+  return total / (6.0 * (double)V);
+}

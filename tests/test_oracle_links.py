@@ -178,3 +178,23 @@ def test_link_construction_rejects_bad_arguments():
         oracle.asqtad_links(dims, U, 0.0)
     with pytest.raises(ValueError):
         oracle.asqtad_links(dims, U, 1.0, sites=[0, 256])
+
+
+def test_plaquette_free_field_and_flux():
+    # unit links: every plaquette is the identity; a uniform flux B in one plane
+    # gives (2 cos B + cos 2B) / 3 for the charges (1, 1, -2) in that plane, 1 in the others
+    dims = (6, 4, 4, 8)
+    assert oracle.plaquette(dims, lattice_links(synth.unit_links(dims))) == pytest.approx(1.0, abs=1e-15)
+    U, B, q = abelian_flux_links(dims, 0, 2, 1)
+    want = (5 + (2 * np.cos(B) + np.cos(2 * B)) / 3) / 6
+    assert oracle.plaquette(dims, lattice_links(U)) == pytest.approx(want, abs=1e-14)
+
+
+def test_plaquette_gauge_invariant():
+    dims = (4, 6, 4, 4)
+    U = synth.thin_links(dims, 0.4, seed=5)
+    g = synth.random_gauge_transform(dims, seed=6)
+    p = oracle.plaquette(dims, lattice_links(U))
+    pg = oracle.plaquette(dims, lattice_links(synth.gauge_transform_thin(U, g)))
+    assert 0.5 < p < 1.0
+    assert pg == pytest.approx(p, abs=1e-13)
