@@ -613,6 +613,10 @@ def run_asqtad(args, asq, torch):
         e1.record(stream)
     stream.synchronize()
     dt = e0.elapsed_time(e1) / 1e3 / reps
+    t0 = time.perf_counter()
+    plaq = asq.plaquette(dims, thin, stream=stream)
+    t_plaq = time.perf_counter() - t0
+    log(f"mean plaquette {plaq:.12f} (u0 = P^1/4 = {plaq ** 0.25:.6f}), {t_plaq * 1e3:.2f} ms with the host copy")
     flops = 198.0 * LINK_BUILD_PRODUCTS * 4 * V  # per call
     tf = flops / dt / 1e12
     log(f"link construction: {dt * 1e3:.3f} ms, {tf:.1f} TFLOP/s FP64 ({tf / PEAK_FP64_TFLOPS:.0%} of peak)")
@@ -681,7 +685,8 @@ def run_asqtad(args, asq, torch):
         log(f"cpu baseline: {full:.1f} s per construction on {cpu['cores']} threads")
     out = {"metric": METRIC, "workload": "asqtad_20x20x20x64", "value": dt * 1e3,
            "unit": "ms per link construction", "higher_is_better": False, "dtype": "f64", "data": "synthetic",
-           "u0": u0, "config": {"workload": "asqtad_20x20x20x64", "dims": list(dims), "eps": w["eps"]},
+           "u0": u0, "plaquette": plaq, "u0_from_plaquette": plaq ** 0.25, "plaquette_ms": t_plaq * 1e3,
+           "config": {"workload": "asqtad_20x20x20x64", "dims": list(dims), "eps": w["eps"]},
            "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                         "frac": tf / PEAK_FP64_TFLOPS, "traffic": None,
                         "kernel": "asqtad_build_links: transpose, fat-link and long-link kernels (FP64), "

@@ -141,6 +141,21 @@ int asq_gauge_destroy(asq_gauge* g);
 int asqtad_build_links(const int dims[4], const double* thin_dev, double u0, double* fat_dev, double* long_dev,
                        void* hip_stream);
 
+/* Device workspace bytes of asqtad_plaquette for these extents (0 if invalid). */
+size_t asqtad_plaquette_workspace_bytes(const int dims[4]);
+/* Mean plaquette of thin links, the input of the tadpole factor u0 = P^(1/4)
+   that the asqtad coefficients use (MILC's ensembles are tadpole improved; the
+   paper prints no formula):
+     P = 1/(6V) sum_x sum_{mu<nu} (1/3) Re tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag]
+   thin_dev: device, double [V][4][3][3][2] canonical, periodic in every
+   direction, 16-byte aligned.  work_dev: at least
+   asqtad_plaquette_workspace_bytes(dims) bytes of device memory, 8-byte
+   aligned, overwritten.  *plaq (host) receives P in FP64, summed in a fixed
+   order (bitwise reproducible).  Synchronizes the stream.  ASQ_EINVAL or
+   ASQ_ENOMEM on bad arguments, checked before any launch. */
+int asqtad_plaquette(const int dims[4], const double* thin_dev, void* work_dev, size_t work_bytes, double* plaq,
+                     void* hip_stream);
+
 /* ---- operator ------------------------------------------------------------ */
 
 /* out = D restricted to sites of out_parity, acting on in (sites of the other

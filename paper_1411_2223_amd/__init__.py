@@ -88,6 +88,9 @@ _SIGS = {
                                   ctypes.POINTER(ctypes.c_double)]),
     "serve_destroy": (ctypes.c_int, [_vp]),
     "asqtad_build_links": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _vp, ctypes.c_double, _vp, _vp, _vp]),
+    "asqtad_plaquette_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int)]),
+    "asqtad_plaquette": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _vp, _vp, ctypes.c_size_t,
+                                        ctypes.POINTER(ctypes.c_double), _vp]),
     "asq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "asq_last_error": (ctypes.c_char_p, []),
     "asq_copy_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
@@ -253,6 +256,25 @@ def build_links(dims, thin_dev, u0=1.0, fat=None, lng=None, stream=None):
     return fat, lng
 
 
+def plaquette(dims, thin_dev, stream=None) -> float:
+    """Mean plaquette of thin links on the device (asqtad_plaquette); u0 = P ** 0.25."""
+    torch = _torch()
+    load()
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims)) * 4 * 18
+    if thin_dev.dtype != torch.float64 or thin_dev.numel() != n or not thin_dev.is_contiguous():
+        raise AsqError(ASQ_EINVAL, "plaquette: thin links must be a contiguous float64 tensor of V*4*18 reals")
+    d4 = (ctypes.c_int * 4)(*dims)
+    nbytes = asqtad_plaquette_workspace_bytes(d4)
+    if nbytes == 0:
+        raise AsqError(ASQ_EINVAL, "asqtad_plaquette_workspace_bytes")
+    work = torch.empty(nbytes, dtype=torch.uint8, device=thin_dev.device)
+    p = ctypes.c_double(0)
+    check(asqtad_plaquette(d4, thin_dev.data_ptr(), work.data_ptr(), nbytes, ctypes.byref(p), stream_ptr(stream)),
+          "asqtad_plaquette")
+    return p.value
+
+
 @dataclass
 class SolveResult:
     x: object
@@ -304,9 +326,14 @@ class Gauge:
     def from_thin(cls, dims, thin, u0=1.0, precs=("f64", "f32"), device="cuda", stream=None):
         """A resident gauge field whose fat and long links are built on the device from
         canonical thin links (host array or device tensor) by asqtad_build_links.
+        u0 = "plaquette" takes the tadpole factor from the mean plaquette, P ** 0.25.
         The fat links are not SU(3), so the links are kept as 18 reals."""
         torch = _torch()
         thin_d = thin if isinstance(thin, torch.Tensor) else links_to_device(thin, device)
+        if isinstance(u0, str):
+            if u0 != "plaquette":
+                raise AsqError(ASQ_EINVAL, "from_thin: u0 is a number or 'plaquette'")
+            u0 = plaquette(dims, thin_d, stream=stream) ** 0.25
         fat, lng = build_links(dims, thin_d, u0, stream=stream)
         return cls(dims, fat, lng, precs=precs, recon=18, device=device, stream=stream)
 

@@ -34,7 +34,7 @@
 // long link 2.
 #include <math.h>
 
-#include "asq_internal.h"
+#include "asq_reduce.h"
 
 namespace asq {
 namespace {
@@ -343,6 +343,61 @@ __global__ void __launch_bounds__(256) long_link_kernel(const FattenArgs A) {
   for (int k = 0; k < 9; ++k) ql[k] = make_double2(L.e[k / 3][k % 3].re, L.e[k / 3][k % 3].im);
 }
 
+// Mean plaquette, first pass: one thread per site sums (1/3) Re tr over its six
+// planes in a fixed order, then one partial per block (block_sum's tree).
+// Re tr[U_mu(x) U_nu(x+mu) (U_nu(x) U_mu(x+nu))^dag] is the sum over the entries
+// of M1 conj(M2), so the last product is not formed.
+__global__ void __launch_bounds__(kBlock) plaquette_kernel(const FattenArgs A, double* partials) {
+  const long lex = (long)blockIdx.x * kBlock + threadIdx.x;
+  double v = 0;
+  if (lex < A.V) {
+    int x[4];
+    long r = lex;
+    x[0] = (int)(r % A.d[0]);
+    r /= A.d[0];
+    x[1] = (int)(r % A.d[1]);
+    r /= A.d[1];
+    x[2] = (int)(r % A.d[2]);
+    x[3] = (int)(r / A.d[2]);
+    for (int mu = 0; mu < 4; ++mu)
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        int xm[4] = {x[0], x[1], x[2], x[3]}, xn[4] = {x[0], x[1], x[2], x[3]};
+        step(xm, mu, false, A.d);
+        step(xn, nu, false, A.d);
+        const M3 m1 = mul_nn(load_canonical(A, lex, mu), load_canonical(A, lex_of(A.d, xm), nu));
+        const M3 m2 = mul_nn(load_canonical(A, lex, nu), load_canonical(A, lex_of(A.d, xn), mu));
+        double t = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            t = fmaR(m1.e[a][b].re, m2.e[a][b].re, t);
+            t = fmaR(m1.e[a][b].im, m2.e[a][b].im, t);
+          }
+        v += t / 3.0;
+      }
+  }
+  __shared__ double sh[kBlock / 64];
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Second pass: the partials in order, divided by the number of plaquettes.
+__global__ void __launch_bounds__(kBlock) plaquette_final(double* partials, int n, double inv_count) {
+  const double v = strided_sum(partials, n);
+  __shared__ double sh[kBlock / 64];
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[n] = tot * inv_count;
+}
+
+bool valid_extents(const int dims[4]) {
+  if (!dims) return false;
+  for (int mu = 0; mu < 4; ++mu)
+    if (dims[mu] < 4 || (dims[mu] & 1) || dims[mu] > (1 << 14)) return false;
+  const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
+  return V * 36 / 256 + 1 < (1L << 31);
+}
+
 bool overlaps(const void* a, const void* b, size_t n) {
   const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
   return pa < pb + n && pb < pa + n;
@@ -359,16 +414,11 @@ extern "C" int asqtad_build_links(const int dims[4], const double* thin_dev, dou
     set_last_error("asqtad_build_links: null pointer");
     return ASQ_EINVAL;
   }
-  for (int mu = 0; mu < 4; ++mu)
-    if (dims[mu] < 4 || (dims[mu] & 1) || dims[mu] > (1 << 14)) {
-      set_last_error("asqtad_build_links: extents must be even, >= 4 and <= 16384");
-      return ASQ_EINVAL;
-    }
-  const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
-  if (V * 36 / 256 + 1 >= (1L << 31)) {
-    set_last_error("asqtad_build_links: lattice too large");
+  if (!valid_extents(dims)) {
+    set_last_error("asqtad_build_links: extents must be even and >= 4, the lattice not too large");
     return ASQ_EINVAL;
   }
+  const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
   if (!(u0 > 0) || !isfinite(u0)) {
     set_last_error("asqtad_build_links: u0 must be positive and finite");
     return ASQ_EINVAL;
@@ -406,5 +456,41 @@ extern "C" int asqtad_build_links(const int dims[4], const double* thin_dev, dou
   ASQ_HIP_TRY(hipGetLastError());
   long_link_kernel<<<(unsigned)((V * 4 + 255) / 256), 256, 0, s>>>(a);
   ASQ_HIP_TRY(hipGetLastError());
+  return ASQ_OK;
+}
+
+extern "C" size_t asqtad_plaquette_workspace_bytes(const int dims[4]) {
+  if (!valid_extents(dims)) return 0;
+  const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
+  return align_up((size_t)((V + kBlock - 1) / kBlock + 1) * sizeof(double), 256);
+}
+
+extern "C" int asqtad_plaquette(const int dims[4], const double* thin_dev, void* work_dev, size_t work_bytes,
+                                double* plaq, void* hip_stream) {
+  if (!thin_dev || !work_dev || !plaq || !valid_extents(dims)) {
+    set_last_error("asqtad_plaquette: null pointer or invalid extents (even, >= 4)");
+    return ASQ_EINVAL;
+  }
+  if (((uintptr_t)thin_dev & 15) || ((uintptr_t)work_dev & 7)) {
+    set_last_error("asqtad_plaquette: thin links 16-byte and workspace 8-byte aligned");
+    return ASQ_EINVAL;
+  }
+  if (work_bytes < asqtad_plaquette_workspace_bytes(dims)) {
+    set_last_error("asqtad_plaquette: workspace smaller than asqtad_plaquette_workspace_bytes()");
+    return ASQ_ENOMEM;
+  }
+  FattenArgs a{};
+  for (int mu = 0; mu < 4; ++mu) a.d[mu] = dims[mu];
+  a.V = (long)dims[0] * dims[1] * dims[2] * dims[3];
+  a.thin = (const double2*)thin_dev;
+  const int nb = (int)((a.V + kBlock - 1) / kBlock);
+  double* partials = (double*)work_dev;
+  hipStream_t s = (hipStream_t)hip_stream;
+  plaquette_kernel<<<(unsigned)nb, kBlock, 0, s>>>(a, partials);
+  ASQ_HIP_TRY(hipGetLastError());
+  plaquette_final<<<1, kBlock, 0, s>>>(partials, nb, 1.0 / (6.0 * (double)a.V));
+  ASQ_HIP_TRY(hipGetLastError());
+  ASQ_HIP_TRY(hipMemcpyAsync(plaq, partials + nb, sizeof(double), hipMemcpyDeviceToHost, s));
+  ASQ_HIP_TRY(hipStreamSynchronize(s));
   return ASQ_OK;
 }

@@ -101,6 +101,14 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert asq.asqtad_build_links(good, base + 8, 1.0, base + step, base + 2 * step, None) == asq.ASQ_EINVAL
     assert asq.asqtad_build_links(good, base, 1.0, base + 4096, base + 2 * step, None) == asq.ASQ_EINVAL
     assert asq.asqtad_build_links(good, base, 1.0, base + step, base + step + 16, None) == asq.ASQ_EINVAL
+    p = ctypes.c_double(0)
+    nw = asq.asqtad_plaquette_workspace_bytes(good)
+    assert nw >= (256 // 256 + 1) * 8 and asq.asqtad_plaquette_workspace_bytes(bad) == 0
+    assert asq.asqtad_plaquette(bad, base, base + step, nw, ctypes.byref(p), None) == asq.ASQ_EINVAL
+    assert asq.asqtad_plaquette(good, None, base + step, nw, ctypes.byref(p), None) == asq.ASQ_EINVAL
+    assert asq.asqtad_plaquette(good, base, base + step, nw, None, None) == asq.ASQ_EINVAL
+    assert asq.asqtad_plaquette(good, base + 8, base + step, nw, ctypes.byref(p), None) == asq.ASQ_EINVAL
+    assert asq.asqtad_plaquette(good, base, base + step, nw - 8, ctypes.byref(p), None) == asq.ASQ_ENOMEM
 
 
 def test_magic_division_formula():

@@ -109,3 +109,34 @@ def test_constructed_fat_links_refuse_compression(asq):
     with pytest.raises(asq.AsqError) as e:
         asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=12)
     assert e.value.code == asq.ASQ_ENOTSU3
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 4, 10), (20, 20, 20, 64)])
+def test_plaquette_matches_oracle(asq, dims):
+    # FP64 on both sides, different summation orders: 1e-13 absolute on a mean of order 1
+    eps = 0.3 if dims[0] == 20 else 0.5
+    U = synth.thin_links(dims, eps, seed=46)
+    thin = asq.links_to_device(U.reshape(-1, 4, 3, 3))
+    p1 = asq.plaquette(dims, thin)
+    p2 = asq.plaquette(dims, thin)
+    want = oracle.plaquette(dims, U.reshape(-1, 4, 3, 3))
+    print(f"plaquette dims={dims}: gpu {p1!r} oracle {want!r}", flush=True)
+    assert p1 == p2
+    assert abs(p1 - want) < 1e-13
+
+
+def test_tadpole_improved_construction(asq):
+    # u0 from the plaquette: the links match the oracle's at that u0 and a solve meets the tolerance
+    import torch
+
+    dims, mass = (8, 8, 8, 8), 0.05
+    U = synth.thin_links(dims, 0.3, seed=47)
+    u0 = oracle.plaquette(dims, U.reshape(-1, 4, 3, 3)) ** 0.25
+    g = asq.Gauge.from_thin(dims, U.reshape(-1, 4, 3, 3), u0="plaquette")
+    fat, lng = oracle.asqtad_links(dims, U.reshape(-1, 4, 3, 3), u0)
+    b = synth.make_sources(dims, 1, seed=48)
+    res = g.solve([mass], asq.vec_to_device(b, "f64"), mode="mixed32")
+    torch.cuda.synchronize()
+    x = asq.vec_from_device(res.x, 1, g.half, "f64")
+    assert res.rc == 0
+    assert oracle.true_residual(dims, fat, lng, mass, b[0], x[0]) <= 1e-10
