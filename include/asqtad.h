@@ -169,8 +169,9 @@ int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, con
 /* The same operator with a caller-chosen launch variant instead of the tuned
    one (for tests that cover every variant and for tuning studies; every
    variant computes the same result, bit for bit).  variant = cols | pipe << 8 |
-   order << 12: cols = 1, 2, 4 or 8 columns per thread; pipe = 1 for the
-   software-pipelined hop loop; order = 0 walks the column tiles of a site block
+   order << 12: cols = 1, 2, 4, 8 or 12 columns per thread (12 not with FP64
+   vectors); pipe = 1 for the software-pipelined hop loop; order = 0 walks the
+   column tiles of a site block
    together, 1, 2, 3 walk tile by tile inside groups of 16, 64 or all site
    blocks.  variant = 0x10000 | 32 | order << 12 selects the matrix-core form
    (prec F16 with FP32 18-real links only): 32 columns per block, FP32 products

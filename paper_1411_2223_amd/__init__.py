@@ -104,7 +104,7 @@ _lib = None
 
 
 def variant_code(cols: int, pipe: bool = False, order: int = 0) -> int:
-    """Launch variant of asqtad_dslash_eo_variant: columns per thread, pipelined hop
+    """Launch variant of asqtad_dslash_eo_variant: columns per thread (1, 2, 4, 8, 12), pipelined hop
     loop, block order (0 tiles of a site block adjacent; 1, 2, 3 tile by tile in
     groups of 16, 64 or all site blocks)."""
     return int(cols) | (0x100 if pipe else 0) | (int(order) << 12)
@@ -117,7 +117,7 @@ def variant_code_mfma(order: int = 0) -> int:
 
 
 # Every launch variant the library builds: (cols, pipe, order).
-VARIANTS_ALL = [(c, p, o) for o in (0, 1, 2, 3) for p in (False, True) for c in (1, 2, 4, 8)]
+VARIANTS_ALL = [(c, p, o) for o in (0, 1, 2, 3) for p in (False, True) for c in (1, 2, 4, 8, 12)]
 
 
 def load():

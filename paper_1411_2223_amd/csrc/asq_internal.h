@@ -125,7 +125,7 @@ int launch_dslash_f64(int out_kind, int epi, int rtile, const DslashArgs& a, hip
 int launch_dslash_f32r18(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
 int launch_dslash_f32r12(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
 int launch_dslash_i16r12(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
-// Launch variant code: columns per thread (1, 2, 4, 8) in the low byte,
+// Launch variant code: columns per thread (1, 2, 4, 8, 12) in the low byte,
 // kPipeBit for the software-pipelined hop loop, and the block order << kOrderShift:
 // 0 the tiles of a site block adjacent; 1, 2, 3 tile by tile inside groups of
 // 16, 64 or all site blocks.

@@ -12,7 +12,7 @@ bool variant_built(int link_kind, int in_kind, int rtile) {
     return link_kind == LINK_F32_R18 && in_kind == VEC_F16 && cols == kMfmaTile;
   }
   if ((rtile & ~(0xff | kPipeBit | (3 << kOrderShift))) != 0) return false;
-  return cols == 1 || cols == 2 || cols == 4 || cols == 8;
+  return cols == 1 || cols == 2 || cols == 4 || cols == 8 || (cols == 12 && in_kind != VEC_F64);
 }
 
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,

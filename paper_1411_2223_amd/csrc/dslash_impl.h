@@ -460,6 +460,10 @@ int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
     case 2: return pipe ? go<Link, InT, OutT, 2, EPI, true>(a, ord, s) : go<Link, InT, OutT, 2, EPI, false>(a, ord, s);
     case 4: return pipe ? go<Link, InT, OutT, 4, EPI, true>(a, ord, s) : go<Link, InT, OutT, 4, EPI, false>(a, ord, s);
     case 8: return pipe ? go<Link, InT, OutT, 8, EPI, true>(a, ord, s) : go<Link, InT, OutT, 8, EPI, false>(a, ord, s);
+    case 12:
+      // twelve FP64 columns would spill the accumulators: not built
+      if constexpr (std::is_same<InT, VecF64>::value) return ASQ_EINVAL;
+      else return pipe ? go<Link, InT, OutT, 12, EPI, true>(a, ord, s) : go<Link, InT, OutT, 12, EPI, false>(a, ord, s);
   }
   return ASQ_EINVAL;
 }

@@ -128,7 +128,7 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     std::vector<int> cands;
     for (int order = 0; order < 4; ++order)
       for (int pipe = 0; pipe < 2; ++pipe)
-        for (int cols : {1, 2, 4, 8})
+        for (int cols : {1, 2, 4, 8, 12})
           if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, pipe, order));
     for (int r : cands) {
       const int cols = r & 0xff;

@@ -93,6 +93,8 @@ def test_every_launch_variant(asq, prec, recon):
     err = rel_err(asq.vec_from_device(ref_dev, nrhs, half, prec), ref)
     assert err.max() <= TOL[prec]
     for cols, pipe, order in asq.VARIANTS_ALL:
+        if cols == 12 and prec == "f64":
+            continue  # not built for FP64 vectors; refused in test_unbuilt_variant_rejected
         out = g.dslash(1, vin, prec, nrhs, variant=asq.variant_code(cols, pipe, order))
         torch.cuda.synchronize()
         print(f"prec={prec} recon={recon} variant cols={cols} pipe={pipe} order={order}", flush=True)
@@ -104,7 +106,7 @@ def test_unbuilt_variant_rejected(asq):
     dims = (4, 4, 4, 8)
     g, fat, lng = _gauge(asq, dims, 0.3, 14112223, 18)
     vin = asq.vec_to_device(synth.make_sources(dims, 8, 1), "f64")
-    for bad in (3, 16, asq.variant_code(4) | (1 << 14)):
+    for bad in (3, 16, asq.variant_code(4) | (1 << 14), asq.variant_code(12), asq.variant_code(12, True, 2)):
         with pytest.raises(asq.AsqError) as e:
             g.dslash(1, vin, "f64", 8, variant=bad)
         assert e.value.code == asq.ASQ_EINVAL
