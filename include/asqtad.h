@@ -150,7 +150,7 @@ size_t asqtad_plaquette_workspace_bytes(const int dims[4]);
    thin_dev: device, double [V][4][3][3][2] canonical, periodic in every
    direction, 16-byte aligned.  work_dev: at least
    asqtad_plaquette_workspace_bytes(dims) bytes of device memory, 8-byte
-   aligned, overwritten.  *plaq (host) receives P in FP64, summed in a fixed
+   aligned, disjoint from the links, overwritten.  *plaq (host) receives P in FP64, summed in a fixed
    order (bitwise reproducible).  Synchronizes the stream.  ASQ_EINVAL or
    ASQ_ENOMEM on bad arguments, checked before any launch. */
 int asqtad_plaquette(const int dims[4], const double* thin_dev, void* work_dev, size_t work_bytes, double* plaq,

@@ -479,6 +479,12 @@ extern "C" int asqtad_plaquette(const int dims[4], const double* thin_dev, void*
     set_last_error("asqtad_plaquette: workspace smaller than asqtad_plaquette_workspace_bytes()");
     return ASQ_ENOMEM;
   }
+  const size_t thin_bytes = (size_t)dims[0] * dims[1] * dims[2] * dims[3] * 4 * 18 * sizeof(double);
+  const uintptr_t t0 = (uintptr_t)thin_dev, w0 = (uintptr_t)work_dev;
+  if (t0 < w0 + work_bytes && w0 < t0 + thin_bytes) {
+    set_last_error("asqtad_plaquette: workspace must not overlap the thin links");
+    return ASQ_EINVAL;
+  }
   FattenArgs a{};
   for (int mu = 0; mu < 4; ++mu) a.d[mu] = dims[mu];
   a.V = (long)dims[0] * dims[1] * dims[2] * dims[3];

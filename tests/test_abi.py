@@ -109,6 +109,8 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert asq.asqtad_plaquette(good, base, base + step, nw, None, None) == asq.ASQ_EINVAL
     assert asq.asqtad_plaquette(good, base + 8, base + step, nw, ctypes.byref(p), None) == asq.ASQ_EINVAL
     assert asq.asqtad_plaquette(good, base, base + step, nw - 8, ctypes.byref(p), None) == asq.ASQ_ENOMEM
+    assert asq.asqtad_plaquette(good, base, base + 4096, nw, ctypes.byref(p), None) == asq.ASQ_EINVAL
+    assert asq.asqtad_plaquette(good, base + step, base + step - 64, nw, ctypes.byref(p), None) == asq.ASQ_EINVAL
 
 
 def test_magic_division_formula():
