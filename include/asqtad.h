@@ -161,8 +161,10 @@ int asqtad_plaquette(const int dims[4], const double* thin_dev, void* work_dev, 
 /* out = D restricted to sites of out_parity, acting on in (sites of the other
    parity), for nrhs columns in precision prec (device layouts above).  F64 uses
    the F64 links, F32 the F32 links, F16 the F16 links if kept, else the F32
-   ones.  Asynchronous on hip_stream.  The single-parity hopping term of the
-   asqtad operator: the kernel on which the paper's CG spends its time. */
+   ones.  Asynchronous on hip_stream.  in_dev and out_dev: 16-byte aligned and
+   disjoint (ASQ_EINVAL if their nrhs columns share a byte).  The single-parity
+   hopping term of the asqtad operator: the kernel on which the paper's CG
+   spends its time. */
 int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
                      void* out_dev, void* hip_stream);
 
@@ -198,7 +200,9 @@ int cg_solve(const asq_gauge* g, double mass, const double* b_dev, double* x_dev
    together: one multi-column Dslash launch per half-operator, per-column
    alpha/beta/masks on the device.  masses: host double[nrhs] (> 0).  b_dev,
    x_dev: device double [nrhs][3][V/2][2].  stats: host array [nrhs].  Each
-   column's arithmetic does not depend on the other columns. */
+   column's arithmetic does not depend on the other columns.  For this call,
+   cg_solve, cg_solve_multishift and cg_solve_full, b_dev, x_dev and the
+   workspace must be pairwise disjoint (ASQ_EINVAL otherwise). */
 int cg_solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev, double* x_dev,
                    void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
                    void* hip_stream);
@@ -249,8 +253,8 @@ int cg_solve_full(const asq_gauge* g, int nrhs, const double* masses, const doub
 int serve_create(void* arena_dev, size_t arena_bytes, int max_streams, int max_cols, asq_server** out);
 /* The gauge field must outlive the server. */
 int serve_register_gauge(asq_server* s, const asq_gauge* g, int* gauge_id);
-/* Non-blocking.  masses: host double[nrhs]; b_dev/x_dev as for cg_solve_batch,
-   owned by the caller until serve_poll reports completion.  ASQ_EAGAIN if the
+/* Non-blocking.  masses: host double[nrhs]; b_dev/x_dev as for cg_solve_batch
+   (disjoint), owned by the caller until serve_poll reports completion.  ASQ_EAGAIN if the
    queue is full; ASQ_ENOMEM if the request can never fit the arena. */
 int serve_submit(asq_server* s, int gauge_id, int nrhs, const double* masses, const double* b_dev,
                  double* x_dev, const asq_cg_params* params, uint64_t* ticket);

@@ -51,9 +51,10 @@ class asq_cg_stats(ctypes.Structure):
 
 
 class AsqError(RuntimeError):
-    def __init__(self, code, where):
+    def __init__(self, code, where, detail=None):
         self.code = code
-        detail = _lib.asq_last_error().decode() if _lib is not None else ""
+        if detail is None:
+            detail = _lib.asq_last_error().decode() if _lib is not None else ""
         super().__init__(f"{where}: {_lib.asq_strerror(code).decode()} ({code}) {detail}")
 
 
@@ -168,6 +169,21 @@ def stream_ptr(stream=None):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+VEC_SITE_BYTES = {"f64": 48, "f32": 24, "f16": 16}
+
+
+def _need(t, nbytes, where, name):
+    """A caller tensor is checked before its pointer crosses the C ABI, which sees no
+    sizes: a contiguous device tensor of at least nbytes."""
+    if not getattr(t, "is_cuda", False):
+        raise AsqError(ASQ_EINVAL, where, f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise AsqError(ASQ_EINVAL, where, f"{name} must be contiguous")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise AsqError(ASQ_EINVAL, where, f"{name} holds {have} bytes, {nbytes} needed")
 
 
 def empty_bytes(n, device="cuda"):
@@ -354,6 +370,9 @@ class Gauge:
         torch = _torch()
         if out is None:
             out = torch.empty_like(vin)
+        nbytes = int(nrhs) * self.half * VEC_SITE_BYTES.get(prec, 0)
+        _need(vin, nbytes, "dslash", "vin")
+        _need(out, nbytes, "dslash", "out")
         if variant is None:
             rc = asqtad_dslash_eo(self.handle, int(out_parity), PRECS[prec], int(nrhs), vin.data_ptr(),
                                   out.data_ptr(), stream_ptr(stream))
@@ -384,6 +403,10 @@ class Gauge:
             work = self.workspace(nrhs, mode)
         if x is None:
             x = torch.empty_like(b)
+        nbytes = nrhs * self.half * 48
+        _need(b, nbytes, "solve", "b")
+        _need(x, nbytes, "solve", "x")
+        _need(work, 0, "solve", "work")
         if delta is None:
             delta = self.default_delta(mode)
         params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
@@ -403,11 +426,16 @@ class Gauge:
         torch = _torch()
         masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
         nmass = len(masses)
-        nsrc = b.numel() // (6 * self.half)
+        nsrc = b.numel() * b.element_size() // (48 * self.half)
+        if nsrc < 1:
+            raise AsqError(ASQ_EINVAL, "solve_multishift", "b holds less than one column")
         if work is None:
             work = empty_bytes(asq_multishift_workspace_bytes(self.handle, nsrc, nmass, MODES[mode]), self.device)
         if x is None:
-            x = torch.empty(nmass * b.numel(), dtype=b.dtype, device=b.device)
+            x = torch.empty(nmass * nsrc * self.half * 6, dtype=torch.float64, device=b.device)
+        _need(b, nsrc * self.half * 48, "solve_multishift", "b")
+        _need(x, nmass * nsrc * self.half * 48, "solve_multishift", "x")
+        _need(work, 0, "solve_multishift", "work")
         if delta is None:
             delta = self.default_delta(mode)
         params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
@@ -431,6 +459,9 @@ class Gauge:
             work = empty_bytes(asq_full_workspace_bytes(self.handle, nrhs, MODES[mode]), self.device)
         if x is None:
             x = torch.empty_like(b)
+        _need(b, 2 * nrhs * self.half * 48, "solve_full", "b")
+        _need(x, 2 * nrhs * self.half * 48, "solve_full", "x")
+        _need(work, 0, "solve_full", "work")
         if delta is None:
             delta = self.default_delta(mode)
         params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
@@ -470,6 +501,9 @@ class Server:
             delta = self.gauges[gauge_id].default_delta(mode)
         params = asq_cg_params(float(tol), int(maxiter), MODES[mode], float(delta), int(poll_iters),
                                1 if use_graph else 0)
+        half = self.gauges[gauge_id].half if 0 <= gauge_id < len(self.gauges) else 0
+        _need(b, n * half * 48, "serve_submit", "b")
+        _need(x, n * half * 48, "serve_submit", "x")
         t = ctypes.c_uint64()
         rc = serve_submit(self.handle, int(gauge_id), n, (ctypes.c_double * n)(*masses), b.data_ptr(), x.data_ptr(),
                           ctypes.byref(params), ctypes.byref(t))

@@ -7,6 +7,13 @@ namespace asq {
 
 using Gauge_t = asq_gauge;
 
+// Whether the byte ranges [a, a + na) and [b, b + nb) intersect (argument checks
+// of the entry points: an output may not alias an input or the workspace).
+inline bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return na && nb && pa < pb + nb && pb < pa + na;
+}
+
 // Widest batch whose D_eo launch forms alpha itself instead of a scalar launch
 // (its tiles are then at most kFoldAlphaMaxTile columns wide).
 constexpr int kFoldAlphaCols = kFoldAlphaMaxTile;

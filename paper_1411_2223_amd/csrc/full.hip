@@ -100,6 +100,12 @@ extern "C" int cg_solve_full(const asq_gauge* g, int nrhs, const double* masses,
     set_last_error("cg_solve_full: b/x must be 16-byte and work 256-byte aligned");
     return ASQ_EINVAL;
   }
+  const size_t vbytes = (size_t)nrhs * 2 * g->geom.half * 48;  // both parities
+  if (ranges_overlap(b_dev, vbytes, x_dev, vbytes) || ranges_overlap(b_dev, vbytes, work_dev, work_bytes) ||
+      ranges_overlap(x_dev, vbytes, work_dev, work_bytes)) {
+    set_last_error("cg_solve_full: b, x and the workspace must not overlap");
+    return ASQ_EINVAL;
+  }
   if (work_bytes < asq_full_workspace_bytes(g, nrhs, params->mode)) {
     set_last_error("cg_solve_full: workspace smaller than asq_full_workspace_bytes()");
     return ASQ_ENOMEM;

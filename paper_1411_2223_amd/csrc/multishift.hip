@@ -177,6 +177,12 @@ extern "C" int cg_solve_multishift(const asq_gauge* g, int nsrc, int nmass, cons
     set_last_error("cg_solve_multishift: b/x must be 16-byte and work 256-byte aligned");
     return ASQ_EINVAL;
   }
+  const size_t bbytes = (size_t)nsrc * g->geom.half * 48, xbytes = bbytes * nmass;
+  if (ranges_overlap(b_dev, bbytes, x_dev, xbytes) || ranges_overlap(b_dev, bbytes, work_dev, work_bytes) ||
+      ranges_overlap(x_dev, xbytes, work_dev, work_bytes)) {
+    set_last_error("cg_solve_multishift: b, x and the workspace must not overlap");
+    return ASQ_EINVAL;
+  }
   if (work_bytes < asq_multishift_workspace_bytes(g, nsrc, nmass, params->mode)) {
     set_last_error("cg_solve_multishift: workspace smaller than asq_multishift_workspace_bytes()");
     return ASQ_ENOMEM;

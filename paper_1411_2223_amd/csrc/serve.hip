@@ -515,6 +515,8 @@ extern "C" int serve_submit(asq_server* S, int gauge_id, int nrhs, const double*
   for (int c = 0; c < nrhs; ++c)
     if (!(masses[c] > 0) || !isfinite(masses[c])) return ASQ_EINVAL;
   if (((uintptr_t)b_dev & 15) || ((uintptr_t)x_dev & 15)) return ASQ_EINVAL;
+  const size_t vbytes = (size_t)nrhs * g->geom.half * 48;
+  if (ranges_overlap(b_dev, vbytes, x_dev, vbytes)) return ASQ_EINVAL;
   if (nrhs > S->max_cols || batch_bytes(g, S->max_cols, params->mode, true) > S->arena.size) {
     set_last_error("serve_submit: request can never fit (nrhs > max_cols or a batch exceeds the arena)");
     return ASQ_ENOMEM;

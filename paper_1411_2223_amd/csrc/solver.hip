@@ -446,6 +446,12 @@ int asq::solve_batch(const asq_gauge* g, int nrhs, const double* masses, const d
     set_last_error("cg_solve_batch: b/x must be 16-byte and work 256-byte aligned");
     return ASQ_EINVAL;
   }
+  const size_t vbytes = (size_t)nrhs * g->geom.half * 48;
+  if (ranges_overlap(b_dev, vbytes, x_dev, vbytes) || ranges_overlap(b_dev, vbytes, work_dev, work_bytes) ||
+      ranges_overlap(x_dev, vbytes, work_dev, work_bytes)) {
+    set_last_error("cg_solve_batch: b, x and the workspace must not overlap");
+    return ASQ_EINVAL;
+  }
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = (hipStream_t)hip_stream;
   Batch B;
@@ -539,6 +545,11 @@ static int dslash_public(const char* who, const asq_gauge* g, int out_parity, in
     return ASQ_EINVAL;
   }
   const int vk = prec == ASQ_F64 ? VEC_F64 : (prec == ASQ_F32 ? VEC_F32 : VEC_F16);
+  const size_t vbytes = (size_t)nrhs * g->geom.half * vec_site_bytes(vk);
+  if (ranges_overlap(in_dev, vbytes, out_dev, vbytes)) {
+    set_last_error(std::string(who) + ": input and output must not overlap");
+    return ASQ_EINVAL;
+  }
   DslashArgs a;
   memset(&a, 0, sizeof(a));
   a.g = g->geom;

@@ -356,3 +356,71 @@ def test_solver_rejects_bad_arguments(asq):
     with pytest.raises(asq.AsqError) as e:
         g64.solve([0.1], b, mode="mixed32")
     assert e.value.code == asq.ASQ_EINVAL
+
+
+def test_aliased_buffers_rejected(asq):
+    # an output that shares bytes with an input or the workspace is refused on the host
+    import torch
+
+    dims = (4, 4, 4, 8)
+    fat, lng = gauge_arrays(dims, 0.3, 14112223)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    b = asq.vec_to_device(synth.make_sources(dims, 2, 46), "f64")
+    flat = b.view(-1)
+    col = flat.numel() // 2  # doubles per column
+    cases = {
+        "dslash in place": lambda: g.dslash(1, b, "f64", 2, out=b),
+        "dslash shifted": lambda: g.dslash(1, flat[:col], "f64", 1, out=flat[16 : 16 + col]),
+        "solve x = b": lambda: g.solve([0.1, 0.2], b, x=b),
+        "solve x inside b": lambda: g.solve([0.1], flat[:col], x=flat[col - 16 : 2 * col - 16]),
+    }
+    work = g.workspace(2, "mixed32")
+    vb = flat.numel() * 8
+    buf = asq.empty_bytes(work.numel() + vb)
+    b_in_work = buf[:vb].view(torch.float64)
+    b_in_work.copy_(flat)
+    cases["solve b in the workspace"] = lambda: g.solve([0.1, 0.2], b_in_work, work=buf[: work.numel()])
+    cases["solve x in the workspace"] = lambda: g.solve([0.1, 0.2], flat, work=buf[: work.numel()], x=b_in_work)
+    xm = torch.empty(3 * flat.numel(), dtype=torch.float64, device=b.device)
+    bm = xm[flat.numel() : 2 * flat.numel()]
+    bm.copy_(flat)
+    cases["multishift x over b"] = lambda: g.solve_multishift([0.1, 0.2, 0.3], bm, x=xm)
+    bf = asq.vec_to_device(synth.make_sources(dims, 2, 47), "f64")  # even half, odd half of one column
+    cases["full x = b"] = lambda: g.solve_full([0.1], bf, x=bf)
+    for name, call in cases.items():
+        print(f"aliased: {name}", flush=True)
+        with pytest.raises(asq.AsqError) as e:
+            call()
+        assert e.value.code == asq.ASQ_EINVAL, name
+    srv = asq.Server(1 << 26, max_streams=1, max_cols=2)
+    gid = srv.register(g)
+    with pytest.raises(asq.AsqError) as e:
+        srv.submit(gid, [0.1, 0.2], b, b)
+    assert e.value.code == asq.ASQ_EINVAL
+    srv.close()
+    # disjoint buffers still solve
+    x, res = _solve(asq, g, [0.1, 0.2], synth.make_sources(dims, 2, 46), "mixed32")
+    assert res.rc == 0
+
+
+def test_binding_checks_tensor_sizes(asq):
+    # the C ABI sees pointers only: the binding refuses short, host or strided tensors before a call
+    import torch
+
+    dims = (4, 4, 4, 8)
+    fat, lng = gauge_arrays(dims, 0.3, 14112223)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    b = asq.vec_to_device(synth.make_sources(dims, 2, 48), "f64")
+    flat = b.view(-1)
+    cases = {
+        "dslash short out": lambda: g.dslash(1, b, "f64", 2, out=flat[:100]),
+        "dslash host input": lambda: g.dslash(1, b.cpu(), "f64", 2),
+        "solve short x": lambda: g.solve([0.1, 0.2], b, x=flat[: flat.numel() // 2].clone()),
+        "solve strided b": lambda: g.solve([0.1], flat[::2]),
+        "full short b": lambda: g.solve_full([0.1, 0.2], b),
+    }
+    for name, call in cases.items():
+        print(f"binding check: {name}", flush=True)
+        with pytest.raises(asq.AsqError) as e:
+            call()
+        assert e.value.code == asq.ASQ_EINVAL, name
