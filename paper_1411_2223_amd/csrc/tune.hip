@@ -3,7 +3,8 @@
 // for gfx950): times each candidate RHS tile (columns per thread) on the
 // caller's own buffers and keeps the fastest per (device, lattice, link tier,
 // vector tiers, epilogue, columns).  Results live in memory and, when the
-// environment variable ASQ_TUNE_CACHE names a file, in that text file.
+// environment variable ASQ_TUNE_CACHE names a file, in that file as one JSON
+// object mapping each key to its launch variant code.
 // ASQ_TUNE=0 turns timing off and uses the built-in defaults.
 #include <stdio.h>
 #include <stdlib.h>
@@ -42,9 +43,11 @@ void load_cache_locked() {
   if (!path || !*path) return;
   FILE* f = fopen(path, "r");
   if (!f) return;
-  char k[200];
+  // the file this library writes: one "key": code pair per line
+  char line[256], k[200];
   int v;
-  while (fscanf(f, "%199s %d", k, &v) == 2) g_cache[k] = v;
+  while (fgets(line, sizeof(line), f))
+    if (sscanf(line, " \"%199[^\"]\" : %d", k, &v) == 2) g_cache[k] = v;
   fclose(f);
 }
 
@@ -53,7 +56,11 @@ void save_cache_locked() {
   if (!path || !*path) return;
   FILE* f = fopen(path, "w");
   if (!f) return;
-  for (auto& kv : g_cache) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+  fprintf(f, "{\n");
+  size_t n = 0;
+  for (auto& kv : g_cache)
+    fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++n < g_cache.size() ? "," : "");
+  fprintf(f, "}\n");
   fclose(f);
 }
 
@@ -90,7 +97,11 @@ int tuned_rtile(const asq_gauge* g, int link, int in, int out, int epi, int ncol
   std::lock_guard<std::mutex> lk(g_mu);
   load_cache_locked();
   auto it = g_cache.find(key_of(g, link, in, out, epi, ncol));
-  if (it != g_cache.end()) return it->second;
+  // a cache file may come from another build: only variants the tuner itself
+  // could have chosen are taken from it
+  if (it != g_cache.end() && variant_built(link, in, it->second) && !(it->second & kMfmaBit) &&
+      (it->second & 0xff) <= (ncol > 1 ? ncol : 1))
+    return it->second;
   return default_rtile(link, ncol);
 }
 
