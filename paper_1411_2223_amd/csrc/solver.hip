@@ -20,6 +20,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <chrono>
 #include <mutex>
 #include <string>
@@ -563,6 +564,13 @@ static int dslash_public(const char* who, const asq_gauge* g, int out_parity, in
   a.nblk = g->nblk;
   a.coeff_fat = g->desc.fat_scale;
   a.coeff_long = g->desc.long_scale;
+  // successive calls walk the lattice in alternate directions, so each starts on
+  // the links the previous one read last, which the memory-side cache still
+  // holds (as D_oe and D_eo do inside the solver); the result does not depend
+  // on the direction
+  static std::atomic<unsigned> calls{0};
+  static const bool sweep = env_flag("ASQ_SWEEP", true);
+  a.reverse = sweep && (calls.fetch_add(1, std::memory_order_relaxed) & 1) ? 1 : 0;
   int rt = variant;
   if (variant < 0) {
     const int rc0 = tune_dslash(g, link, vk, nrhs, in_dev, out_dev, stream);
