@@ -162,9 +162,11 @@ int asqtad_plaquette(const int dims[4], const double* thin_dev, void* work_dev, 
    parity), for nrhs columns in precision prec (device layouts above).  F64 uses
    the F64 links, F32 the F32 links, F16 the F16 links if kept, else the F32
    ones.  Asynchronous on hip_stream.  in_dev and out_dev: 16-byte aligned and
-   disjoint (ASQ_EINVAL if their nrhs columns share a byte).  The single-parity
-   hopping term of the asqtad operator: the kernel on which the paper's CG
-   spends its time. */
+   disjoint (ASQ_EINVAL if their nrhs columns share a byte).  Successive calls
+   in the process walk the lattice in alternate directions (each starts where
+   the previous one ended, on links the memory-side cache still holds); the
+   result is the same bits either way.  The single-parity hopping term of the
+   asqtad operator: the kernel on which the paper's CG spends its time. */
 int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
                      void* out_dev, void* hip_stream);
 
