@@ -41,6 +41,7 @@ def _check(asq, g, fat, lng, dims, prec, nrhs, seed):
         v = synth.make_sources(dims, nrhs, seed + out_parity)
         vq = quantize_like_device(v, prec)
         vin = asq.vec_to_device(v, prec)
+        # consecutive calls walk the lattice in opposite directions: the same bits either way
         out = g.dslash(out_parity, vin, prec, nrhs)
         out2 = g.dslash(out_parity, vin, prec, nrhs)
         torch.cuda.synchronize()
