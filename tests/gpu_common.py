@@ -17,15 +17,47 @@ def gauge_arrays(dims, eps, seed):
     return fat, lng
 
 
+def f16n_encode(v):
+    """FP16-with-norm encoding written for the tests from its definition, independent of
+    the library: per site and column the six reals rounded to float32, nu = their largest
+    magnitude (float32), then each real times 1/nu (float32 arithmetic) rounded to IEEE
+    binary16 with round-to-nearest-even.  Returns (halves (nrhs, V/2, 3, 2) float16,
+    nu (nrhs, V/2) float32): the canonical layout is the halves followed by the norms."""
+    v = np.asarray(v, dtype=np.complex128)
+    comp = np.stack([v.real, v.imag], axis=-1).astype(np.float32)  # (nrhs, half, 3, 2)
+    nu = np.abs(comp).reshape(comp.shape[:2] + (6,)).max(axis=-1)
+    with np.errstate(divide="ignore"):
+        inv = np.where(nu > 0, np.float32(1.0) / nu, np.float32(0.0)).astype(np.float32)
+    h = (comp * inv[..., None, None]).astype(np.float16)
+    return h, nu
+
+
+def f16n_value(h, nu):
+    """The exact value an FP16-with-norm record represents: nu * h, complex (nrhs, V/2, 3)."""
+    w = h.astype(np.float64) * nu.astype(np.float64)[..., None, None]
+    return w[..., 0] + 1j * w[..., 1]
+
+
+def f16n_bytes(h, nu):
+    """Canonical FP16-with-norm buffer: every column's binary16 values, then every norm."""
+    return np.concatenate([np.ascontiguousarray(h).view(np.uint8).reshape(-1),
+                           np.ascontiguousarray(nu, dtype=np.float32).view(np.uint8).reshape(-1)])
+
+
 def quantize_like_device(v, prec):
     """The values the device actually reads for an input given in `prec`."""
-    import paper_1411_2223_amd as asq
-
     if prec == "f64":
         return v
     if prec == "f32":
         return v.real.astype(np.float32).astype(np.float64) + 1j * v.imag.astype(np.float32).astype(np.float64)
-    return asq.decode_f16n(asq.encode_f16n(v), v.shape[0], v.shape[1])
+    return f16n_value(*f16n_encode(v))
+
+
+def max_err(a, b):
+    """Largest elementwise error per column, relative to the column's largest |b| entry."""
+    num = np.abs(a - b).reshape(a.shape[0], -1).max(axis=1)
+    den = np.abs(b).reshape(b.shape[0], -1).max(axis=1)
+    return num / np.where(den > 0, den, 1)
 
 
 def rel_err(a, b):

@@ -344,3 +344,52 @@ def test_dslash_matches_independent_numpy_form(dims):
         masked = np.where((par == 1 - out_parity)[:, None], psi, 0)
         want = _numpy_dslash_full(dims, fat, lng, masked)[par == out_parity]
         assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
+
+
+def _numpy_dense_A(dims, fat, lng, mass):
+    """Dense A = 4m^2 - D_eo D_oe on even sites, built column by column from the
+    whole-lattice numpy form of D above (no oracle code involved)."""
+    c = lex_coords(dims)
+    par = c.sum(axis=1) % 2
+    V = int(np.prod(dims))
+    even, odd = par == 0, par == 1
+    n = V // 2 * 3
+    A = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros((V, 3), dtype=np.complex128)
+    for k in range(n):
+        e[:] = 0
+        e[np.nonzero(even)[0][k // 3], k % 3] = 1.0
+        t = _numpy_dslash_full(dims, fat, lng, e)  # D_oe e on odd sites
+        t = np.where(odd[:, None], t, 0)
+        u = _numpy_dslash_full(dims, fat, lng, t)  # D_eo t on even sites
+        A[:, k] = (4 * mass**2 * e - u)[even].reshape(-1)
+    return A
+
+
+def test_true_residual_scale_pinned_by_dense_numpy_residual():
+    # The relative true residual decides every full-size solver parity test, so
+    # its scale is pinned against numpy on a dense A built without the oracle:
+    #   x = 0          -> exactly 1 (|b| / |b|)
+    #   x = c x_dense  -> |1 - c| (b - A c x = (1 - c) b)
+    #   random x       -> ||b - A x|| / ||b|| from numpy
+    # A dropped square root (|r|^2/|b|^2) or a |b|^2 denominator fails each.
+    dims, m = (4, 4, 4, 8), 0.1
+    fat, lng = synth.make_gauge(dims, 0.3, 41)
+    half = int(np.prod(dims)) // 2
+    A = _numpy_dense_A(dims, fat, lng, m)
+    b = synth.make_sources(dims, 1, 42)[0]
+    assert oracle.true_residual(dims, fat, lng, m, b, np.zeros_like(b)) == 1.0
+    x_dense = np.linalg.solve(A, b.reshape(-1)).reshape(half, 3)
+    for c in (0.5, 0.9, 1.1):
+        tr = oracle.true_residual(dims, fat, lng, m, b, c * x_dense)
+        assert abs(tr - abs(1 - c)) <= 1e-12, (c, tr)
+    rng = np.random.default_rng(43)
+    for scale in (1e-3, 1.0, 1e3):
+        x = scale * (rng.standard_normal((half, 3)) + 1j * rng.standard_normal((half, 3)))
+        want = np.linalg.norm(b.reshape(-1) - A @ x.reshape(-1)) / np.linalg.norm(b.reshape(-1))
+        got = oracle.true_residual(dims, fat, lng, m, b, x)
+        assert abs(got - want) <= 1e-14 * want, (scale, got, want)
+    # the scale of b cancels: the residual is relative
+    tr1 = oracle.true_residual(dims, fat, lng, m, b, 0.7 * x_dense)
+    tr2 = oracle.true_residual(dims, fat, lng, m, 5.0 * b, 3.5 * x_dense)
+    assert abs(tr1 - 0.3) <= 1e-12 and abs(tr2 - 0.3) <= 1e-12
