@@ -26,6 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "asqtad_oracle.c")
+_SRCS = (_SRC, os.path.join(_HERE, "npr_oracle.c"))
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _dptr = ctypes.POINTER(ctypes.c_double)
@@ -34,8 +35,8 @@ _iptr = ctypes.POINTER(ctypes.c_int)
 
 def build(force: bool = False) -> str:
     """Compile the oracle shared library with gcc (-O2, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", _SRC, "-o", _LIB + ".tmp", "-lm"]
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", *_SRCS, "-o", _LIB + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -63,6 +64,13 @@ def lib():
         L.oracle_asqtad_links.restype = ctypes.c_int
         L.oracle_plaquette.argtypes = [_iptr, _dptr]
         L.oracle_plaquette.restype = ctypes.c_double
+        L.oracle_spin_taste.argtypes = [ctypes.c_int, ctypes.c_int, _dptr]
+        L.oracle_spin_taste.restype = ctypes.c_int
+        L.oracle_link_average.argtypes = [_iptr, _dptr, _iptr, ctypes.c_int, ctypes.c_int, _dptr]
+        L.oracle_link_average.restype = ctypes.c_int
+        L.oracle_npr_fourfermion.argtypes = [_iptr, _dptr, _dptr, _dptr, _dptr, _dptr, ctypes.c_int, _iptr,
+                                             ctypes.POINTER(ctypes.c_long), ctypes.c_long, _dptr]
+        L.oracle_npr_fourfermion.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -183,3 +191,51 @@ def dense_operator(apply, n_sites: int) -> np.ndarray:
         M[:, k] = apply(e.reshape(n_sites, 3)).reshape(n)
         e[k] = 0.0
     return M
+
+
+# ---- NPR: the one-colour four-fermion operator of the paper's Eq. (1) ------------
+
+def spin_taste(S: int, F: int) -> np.ndarray:
+    """(gamma_S (x) xi_F)bar as a 16 x 16 complex matrix (row A, column B), from the trace
+    (1/4) Tr[gamma_A^dag gamma_S gamma_B gamma_F^dag] with explicit 4 x 4 Dirac matrices."""
+    out = np.empty((16, 16), dtype=np.complex128)
+    if lib().oracle_spin_taste(int(S), int(F), _p(out)) != 0:
+        raise ValueError("oracle_spin_taste: S and F are 4-bit masks")
+    return out
+
+
+def link_average(dims, thin, z, A: int, D: int) -> np.ndarray:
+    """U_AD(z): the mean over every shortest path from corner A to corner D of hypercube z
+    of the ordered link products; thin is complex (V, 4, 3, 3)."""
+    V = int(np.prod(dims))
+    U = _c128(thin, (V, 4, 3, 3))
+    out = np.empty((3, 3), dtype=np.complex128)
+    zc = (ctypes.c_int * 4)(*[int(v) for v in z])
+    if lib().oracle_link_average(_dims(dims), _p(U), zc, int(A), int(D), _p(out)) != 0:
+        raise ValueError("oracle_link_average: bad arguments")
+    return out
+
+
+def npr_fourfermion(dims, thin, props, ops, zs=None) -> np.ndarray:
+    """V_I(z)[a1, a2, a3, a4] of Eq. (1) for operators ops = [(S1, F1, S2, F2), ...] and
+    propagators props = (G1, G2, G3, G4), each complex (V, 3, 3) [site colour, source colour],
+    at every hypercube (zs=None, lexicographic, zx fastest) or the listed ones.
+    Returns complex (nop, nz, 3, 3, 3, 3)."""
+    V = int(np.prod(dims))
+    U = _c128(thin, (V, 4, 3, 3))
+    G = [_c128(g, (V, 3, 3)) for g in props]
+    op = np.ascontiguousarray(np.asarray(ops, dtype=np.int32).reshape(-1, 4))
+    nop = op.shape[0]
+    if zs is None:
+        nz = V // 16
+        zp = None
+    else:
+        zarr = np.ascontiguousarray(zs, dtype=np.int64)
+        nz = len(zarr)
+        zp = zarr.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
+    out = np.empty((nop, nz, 3, 3, 3, 3), dtype=np.complex128)
+    rc = lib().oracle_npr_fourfermion(_dims(dims), _p(U), _p(G[0]), _p(G[1]), _p(G[2]), _p(G[3]), int(nop),
+                                      op.ctypes.data_as(_iptr), zp, int(nz), _p(out))
+    if rc != 0:
+        raise ValueError(f"oracle_npr_fourfermion failed ({rc})")
+    return out
