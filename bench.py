@@ -5,6 +5,7 @@
     python bench.py --workload threelevel_48x48x48x96               # 12 RHS, 12-real 16-bit links
     python bench.py --workload serving [--requests N]               # Poisson request stream
     python bench.py --workload asqtad_20x20x20x64                   # fat/long links built from thin links
+    python bench.py --workload npr_20x20x20x64                      # Eq. (1) four-fermion contraction, FP64
     python bench.py --kernels-only                                  # fixed launches for counter runs
 
 Headline step: one complete solve of A x = b (A = 4m^2 - D_eo D_oe, even
@@ -78,7 +79,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="single_20x20x20x64",
                     choices=["single_20x20x20x64", "batched_20x20x20x64", "threelevel_48x48x48x96", "serving",
-                             "asqtad_20x20x20x64"])
+                             "asqtad_20x20x20x64", "npr_20x20x20x64"])
     ap.add_argument("--mode", default="mixed32", choices=["f64", "mixed32", "mixed16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multishift", action="store_true", help="batched: skip the shifted-CG line")
@@ -101,20 +102,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_dslash(asq, g, prec, nrhs, launches, stream):
-    """Average duration of one Dslash launch (HIP events on the launch stream) -> seconds."""
+def time_dslash(asq, g, prec, nrhs, launches, stream, native=True):
+    """Average duration of one Dslash launch (HIP events on the launch stream) -> seconds.
+
+    native: the tuned kernel the solvers launch, on vectors in their native layout
+    (asqtad_dslash_eo_variant with ASQ_VARIANT_NATIVE); otherwise the public operator on
+    canonical vectors (asqtad_dslash_eo)."""
     import torch
 
     v = synth.make_sources(g.dims, nrhs, 99)
-    vin = asq.vec_to_device(v, prec)
+    vin = asq.vec_to_device(v, prec, stream=stream)
+    if native:
+        vin = g.to_native(vin, prec, nrhs, stream=stream)
+    variant = asq.ASQ_VARIANT_NATIVE if native else None
     out = torch.empty_like(vin)
     for _ in range(5):
-        g.dslash(1, vin, prec, nrhs, out=out, stream=stream)
+        g.dslash(1, vin, prec, nrhs, out=out, stream=stream, variant=variant)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(launches):
-        g.dslash(1, vin, prec, nrhs, out=out, stream=stream)
+        g.dslash(1, vin, prec, nrhs, out=out, stream=stream, variant=variant)
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) * 1e-3 / launches
@@ -238,10 +246,11 @@ def kernels_only(asq, g, dims):
     print(json.dumps({"kernels_only": res}), flush=True)
 
 
-def kernels_only_threelevel(asq, g, dims, ncol):
+def kernels_only_threelevel(asq, g, g18, dims, ncol):
     """Fixed launches at 48^3 x 96 for counter collection: the iterated 12-column Dslash
     (FP16-with-norm vectors, 16-bit 12-real links) 10 times and the 12-column FP64 Dslash of
-    the reliable update 5 times, then the copy probe."""
+    the reliable update 5 times; then, on 18-real links far beyond the memory-side cache,
+    the one-column FP32 and FP64 Dslash 20 times each; then the copy probe."""
     import torch
 
     half = int(np.prod(dims)) // 2
@@ -250,6 +259,9 @@ def kernels_only_threelevel(asq, g, dims, ncol):
     for prec, link, n in (("f16", "f16r12", 10), ("f64", "f64", 5)):
         dt = time_dslash(asq, g, prec, ncol, n, stream)
         res[prec] = {"us": dt * 1e6, "alg_bytes": dslash_bytes_per_site(link, prec, ncol) * half}
+    for prec, n in (("f32", 20), ("f64", 20)):
+        dt = time_dslash(asq, g18, prec, 1, n, stream)
+        res[f"{prec}_1rhs"] = {"us": dt * 1e6, "alg_bytes": dslash_bytes_per_site(prec, prec, 1) * half}
     nb = 1 << 30
     src = torch.empty(nb, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -332,6 +344,17 @@ def run_single(args, asq, torch):
         log(f"{other} CG: iters={r_other.stats[0]['iters']} resid={r_other.stats[0]['true_resid']:.3e} "
             f"{t_other * 1e3:.1f} ms")
 
+    # FP32 arithmetic on FP64-stored 18-real links (a field kept in FP64 only: the
+    # sloppy Dslash rounds its links to FP32 on load), same solver and tolerance
+    g64 = asq.Gauge(dims, fat, lng, precs=("f64",), recon=18)
+    t_l64, times_l64, r_l64 = solve_series(g64, [mass], bd, "mixed32", w["tol"], 5, 1, stream, work, x)
+    dt_l64 = time_dslash(asq, g64, "f32", 1, max(20, args.dslash_launches // 4), stream)
+    l64_bytes = (16 * 144 + 2 * 24) * half
+    log(f"mixed32 CG on FP64-stored links: iters={r_l64.stats[0]['iters']} "
+        f"resid={r_l64.stats[0]['true_resid']:.3e} {t_l64 * 1e3:.1f} ms; its FP32 Dslash {dt_l64 * 1e6:.1f} us")
+    g64.close()
+    del g64
+
     # the boundary's host-side costs, outside the timed region: importing the host FP64
     # links (once per gauge field), and a solve whose b starts and whose x ends in pinned
     # host memory (PCIe both ways)
@@ -370,7 +393,9 @@ def run_single(args, asq, torch):
     achieved = bytes_launch / dt / 1e9
     dt64 = time_dslash(asq, g, "f64", 1, max(20, args.dslash_launches // 4), stream)
     f64_gbs = dslash_bytes_per_site("f64", "f64", 1) * half / dt64 / 1e9
-    log(f"dslash {tprec}: {dt * 1e6:.2f} us, {achieved:.0f} GB/s; f64: {dt64 * 1e6:.2f} us, {f64_gbs:.0f} GB/s")
+    dt_pub = time_dslash(asq, g, tprec, 1, args.dslash_launches, stream, native=False)
+    log(f"dslash {tprec}: {dt * 1e6:.2f} us, {achieved:.0f} GB/s; f64: {dt64 * 1e6:.2f} us, {f64_gbs:.0f} GB/s; "
+        f"public canonical-layout {tprec}: {dt_pub * 1e6:.2f} us")
     copy_gbs = copy_bandwidth(asq, stream)
     read_gbs = read_bandwidth(asq, stream)
     log(f"copy probe: {copy_gbs:.0f} GB/s; read probe: {read_gbs:.0f} GB/s")
@@ -406,11 +431,18 @@ def run_single(args, asq, torch):
         "f64_cg_iterations": r64.stats[0]["iters"],
         "speedup_vs_f64_cg": t64 / secs,
         "fp16_vectors_time_to_solution_ms": t_other * 1e3 if t_other else None,
+        "fp64_links_fp32_arith": {"time_to_solution": time_stats(times_l64), "ms": t_l64 * 1e3,
+                                  "iterations": r_l64.stats[0]["iters"],
+                                  "true_resid": r_l64.stats[0]["true_resid"],
+                                  "speedup_vs_f64_cg": t64 / t_l64,
+                                  "dslash_us": dt_l64 * 1e6, "dslash_bytes_per_launch": l64_bytes,
+                                  "dslash_gbs": l64_bytes / dt_l64 / 1e9},
         "gauge_import_ms": import_ms,
         "pcie_inclusive_solve_ms": float(np.median(host_ms)),
         "fp16_vectors_iterations": r_other.stats[0]["iters"] if r_other else None,
         "dslash_gbs": achieved,
         "dslash_f64_gbs": f64_gbs,
+        "dslash_public_canonical_us": dt_pub * 1e6,
         "copy_probe_gbs": copy_gbs,
         "read_probe_gbs": read_gbs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -505,10 +537,24 @@ def run_threelevel(args, asq, torch):
     fat, lng = synth.make_gauge(dims, w["eps"], synth.gauge_seed(w["index"]))
     log(f"gauge generated in {time.perf_counter() - t0:.0f} s")
     g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
+    # one-column FP32 and FP64 Dslash on 18-real links: 6.1 and 12.2 GB, far beyond the
+    # 256 MB memory-side cache, so their rate is HBM bandwidth
+    g18 = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
     del fat, lng
     if args.kernels_only:
-        kernels_only_threelevel(asq, g, dims, ncol)
+        kernels_only_threelevel(asq, g, g18, dims, ncol)
         return
+    stream0 = torch.cuda.Stream()
+    above = {}
+    for prec in ("f32", "f64"):
+        dtp = time_dslash(asq, g18, prec, 1, 20, stream0)
+        bl = dslash_bytes_per_site(prec, prec, 1) * half
+        above[prec] = {"us": dtp * 1e6, "GBps": bl / dtp / 1e9, "frac_hbm": bl / dtp / 1e9 / PEAK_HBM_GBS,
+                       "bytes_per_launch": bl,
+                       "traffic": measured_traffic(f"{prec}_{prec}_1rhs_r18", bl, lattice="48x48x48x96")}
+        log(f"above-MALL 1-RHS {prec} 18-real: {dtp * 1e6:.1f} us, {bl / dtp / 1e9:.0f} GB/s")
+    g18.close()
+    del g18
     b = synth.make_sources(dims, ncol, synth.source_seed(w["index"]))
     stream = torch.cuda.Stream()
     bd = asq.vec_to_device(b, "f64")
@@ -551,7 +597,8 @@ def run_threelevel(args, asq, torch):
                             "frac_fp32_alu": tf / PEAK_FP32_TFLOPS, "bytes_per_launch": bytes_launch,
                             "traffic": traffic,
                             "traffic_GBps": traffic / dt / 1e9 if traffic else None},
-           "dslash_1rhs_GBps": gbs1}
+           "dslash_1rhs_GBps": gbs1,
+           "dslash_1rhs_18real_above_mall": above}
     if cpu:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
@@ -563,17 +610,29 @@ def run_serving(args, asq, torch):
     n_warm = args.serve_warmup
     trace = synth.serving_trace(args.requests + n_warm, rate=args.rate)
     mode = "mixed16" if args.mode == "mixed32" else args.mode
-    gauges, pools = [], []
+    # Each request's sources come from its trace seed: it draws its columns (without
+    # replacement) from a bank of seeded Gaussian sources resident per lattice.
+    bank_cols = 48
+    gauges, banks, arrays = [], [], []
     for k, dims in enumerate(lattices):
         fat, lng = synth.make_gauge(dims, 0.3, synth.BASE_SEED + 10 + k)
         gauges.append(asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18))
-        pools.append(asq.vec_to_device(synth.make_sources(dims, 12, synth.BASE_SEED + 20 + k), "f64"))
-        del fat, lng
+        half = gauges[-1].half
+        bank = synth.make_sources(dims, bank_cols, synth.BASE_SEED + 20 + k)
+        banks.append(asq.vec_to_device(bank, "f64").view(bank_cols, half * 6))
+        arrays.append((fat, lng, bank))
+        del fat, lng, bank
     budget = 48 << 30
     srv = asq.Server(budget, max_streams=args.serve_streams, max_cols=args.serve_cols)
-    gids = [srv.register(gg) for gg in gauges]
+    gids = [srv.register(gg) for gg in gauges]  # tunes every batch shape before the stream starts
     torch.cuda.synchronize()
     log(f"serving {len(trace)} requests ({n_warm} warm-up), budget {budget >> 30} GiB")
+    # a sample of served solutions is checked by the oracle afterwards: two per lattice
+    check_ids = set()
+    for li in range(len(lattices)):
+        ids = [i for i, q in enumerate(trace) if q["lattice"] == li and i >= n_warm]
+        check_ids.update(ids[:: max(1, len(ids) // 2)][:2])
+    kept = {}
     pending = {}
     done = []
     t0 = time.perf_counter()
@@ -584,21 +643,42 @@ def run_serving(args, asq, torch):
             q = trace[k]
             lat = q["lattice"]
             n = q["nrhs"]
-            b = pools[lat][:n]
+            cols = np.random.Generator(np.random.PCG64(q["seed"])).choice(bank_cols, size=n, replace=False)
+            b = banks[lat][torch.as_tensor(cols, device=banks[lat].device)].reshape(-1)
             x = torch.empty_like(b)
             t = srv.submit(gids[lat], [q["mass"]] * n, b, x, mode=mode)
-            pending[t] = (k, n, x)
+            pending[t] = (k, n, b, x)
             k += 1
         for t in list(pending):
-            kk, n, x = pending[t]
+            kk, n, b, x = pending[t]
             r = srv.poll(t, n)
             if r is not None:
                 rc, stats, latency = r
                 done.append((kk, rc, latency, n, trace[kk]["lattice"], max(s["true_resid"] for s in stats)))
+                if kk in check_ids:
+                    kept[kk] = x
                 del pending[t]
         time.sleep(0.0005)
     wall = time.perf_counter() - t0
     srv.close()
+    oracle_max = None
+    if not args.no_oracle_check:
+        import oracle
+
+        rs = []
+        for kk, x in sorted(kept.items()):
+            q = trace[kk]
+            dims = lattices[q["lattice"]]
+            fat, lng, bank = arrays[q["lattice"]]
+            n = q["nrhs"]
+            half = int(np.prod(dims)) // 2
+            cols = np.random.Generator(np.random.PCG64(q["seed"])).choice(bank_cols, size=n, replace=False)
+            src = bank[cols]
+            xs = asq.vec_from_device(x, n, half, "f64")
+            rs += [oracle.true_residual(dims, fat, lng, q["mass"], src[c], xs[c]) for c in range(n)]
+        oracle_max = max(rs) if rs else None
+        log(f"oracle FP64 residual of {len(kept)} sampled requests ({len(rs)} columns): max {oracle_max:.3e}")
+    del arrays
     meas = [d for d in done if d[0] >= n_warm]
     lats = np.array([d[2] for d in meas])
     rhs = sum(d[3] for d in meas)
@@ -615,7 +695,8 @@ def run_serving(args, asq, torch):
            "requests": len(meas), "rhs_solves": rhs, "wall_s": wall, "offered_requests_per_s": len(meas) / span,
            "achieved_rhs_per_s": rhs / wall, "p50_latency_ms": float(np.percentile(lats, 50) * 1e3),
            "p99_latency_ms": float(np.percentile(lats, 99) * 1e3), "failed": len(bad),
-           "true_resid_max": max(d[5] for d in meas), "per_lattice": per_lat}
+           "true_resid_max": max(d[5] for d in meas), "per_lattice": per_lat,
+           "oracle_checked_requests": len(kept), "oracle_true_resid_max": oracle_max}
     log(f"serving: {out['value']:.1f} req/s, p50 {out['p50_latency_ms']:.1f} ms, p99 {out['p99_latency_ms']:.1f} ms")
     print(json.dumps(out), flush=True)
 
@@ -735,6 +816,123 @@ def run_asqtad(args, asq, torch):
     print(json.dumps(out), flush=True)
 
 
+# SU(3) products per hypercube of the four-fermion operator that do not depend on the
+# operator: the 256 link averages by their first step (sum over pairs of |A ^ D| = 512)
+# and the two bilinear colour matrices of each pair (4 x 256); and the contraction
+# per operator: 16 x 16 corner pairs x 81 complex multiply-adds (8 flops each).
+NPR_PRODUCTS_PER_HYPERCUBE = 512 + 4 * 256
+NPR_FLOPS_PER_OP_HYPERCUBE = 256 * 81 * 8
+
+
+def npr_flops(nz, nop):
+    return nz * (198.0 * NPR_PRODUCTS_PER_HYPERCUBE + NPR_FLOPS_PER_OP_HYPERCUBE * nop)
+
+
+def run_npr(args, asq, torch):
+    """The one-colour four-fermion operator of Eq. (1) on the paper's 20^3 x 64 lattice shape:
+    point-source propagators of two masses from the library's own full-lattice CG (FP64
+    true residual 1e-10), then the FP64 contraction for 16 operators (every spin S with
+    taste xi_5 in both bilinears) at every hypercube."""
+    w = synth.WORKLOADS["single_20x20x20x64"]
+    dims = w["dims"]
+    V = int(np.prod(dims))
+    half = V // 2
+    nz = V // 16
+    masses = (0.01, 0.05)
+    ops = [(s, 15, s, 15) for s in range(16)]
+    log(f"workload npr dims={dims} masses={masses} operators={len(ops)}")
+    U = synth.thin_links(dims, w["eps"], synth.gauge_seed(w["index"]))
+    fat, lng = synth.fat_long_from_thin(U)
+    U = U.reshape(V, 4, 3, 3)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    stream = torch.cuda.Stream()
+    # point sources at the origin (an even site, checkerboard index 0), one per colour and mass:
+    # b = [even halves of the 6 columns, odd halves]
+    ncol = 3 * len(masses)
+    b = np.zeros((2, ncol, half, 3), dtype=np.complex128)
+    for f in range(len(masses)):
+        for a in range(3):
+            b[0, 3 * f + a, 0, a] = 1.0
+    bd = asq.vec_to_device(b.reshape(2 * ncol, half, 3), "f64")
+    t0 = time.perf_counter()
+    res = g.solve_full([m for m in masses for _ in range(3)], bd, mode="mixed32", stream=stream)
+    torch.cuda.synchronize()
+    t_prop = time.perf_counter() - t0
+    if res.rc != 0:
+        raise SystemExit(f"propagator solves failed rc={res.rc}")
+    log(f"propagators: {ncol} full-lattice solves in {t_prop:.2f} s, max |b - M x|/|b| "
+        f"{max(s['true_resid'] for s in res.stats):.2e}")
+    # G_f(x)[c][a] in lexicographic site order (input construction, on the host)
+    xs = asq.vec_from_device(res.x, 2 * ncol, half, "f64").reshape(2, ncol, half, 3)
+    X, Y, Z, T = dims
+    lex = np.arange(V)
+    par = (lex % X + (lex // X) % Y + (lex // (X * Y)) % Z + lex // (X * Y * Z)) % 2
+    G = []
+    for f in range(len(masses)):
+        Gf = np.empty((V, 3, 3), dtype=np.complex128)
+        for p in (0, 1):
+            sel = par == p
+            Gf[sel] = xs[p, 3 * f:3 * f + 3][:, lex[sel] // 2].transpose(1, 2, 0)  # [site][c][a]
+        G.append(Gf)
+    props_h = [G[0], G[0], G[1], G[1]]  # chi, chibar of the light quark; of the heavier one
+    thin = asq.links_to_device(U)
+    props = [asq.links_to_device(x.reshape(V, 1, 3, 3)) for x in props_h]
+    out = torch.empty(len(ops) * nz * 162, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            asq.npr_fourfermion(dims, thin, props, ops, out=out, stream=stream)
+        reps = max(3, args.steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            asq.npr_fourfermion(dims, thin, props, ops, out=out, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / reps
+    flops = npr_flops(nz, len(ops))
+    tf = flops / dt / 1e12
+    log(f"four-fermion contraction: {dt * 1e3:.3f} ms per call, {flops / 1e9:.1f} GFLOP, {tf:.1f} TFLOP/s FP64 "
+        f"({tf / PEAK_FP64_TFLOPS:.0%} of peak)")
+    import oracle
+
+    rng = np.random.Generator(np.random.PCG64(5))
+    zs = np.unique(rng.integers(0, nz, 24))
+    got = out.view(len(ops), nz, 162)[:, torch.as_tensor(zs, device="cuda")].cpu().numpy()
+    got = got.view(np.complex128).reshape(len(ops), len(zs), 81)
+    want = oracle.npr_fourfermion(dims, U, props_h, ops, zs=zs).reshape(len(ops), len(zs), 81)
+    err = max(float(np.abs(got[k] - want[k]).max() / np.abs(want[k]).max()) for k in range(len(ops)))
+    log(f"oracle check on {len(zs)} hypercubes: max error {err:.2e} of each operator's largest entry")
+    cpu = None
+    if not args.no_cpu_baseline:
+        n = 8
+        t0 = time.perf_counter()
+        oracle.npr_fourfermion(dims, U, props_h, ops, zs=np.arange(n))
+        per_z = (time.perf_counter() - t0) / n
+        n = int(min(nz, max(n, args.cpu_seconds / max(per_z, 1e-9))))
+        t0 = time.perf_counter()
+        oracle.npr_fourfermion(dims, U, props_h, ops, zs=rng.integers(0, nz, n))
+        t_s = time.perf_counter() - t0
+        t_all = t_s / n * nz
+        cpu = {"value": 1.0 / t_all, "unit": "contractions/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"oracle FP64 contraction of {len(ops)} operators at {n} random hypercubes of {nz} "
+                         f"({t_s:.1f} s), scaled to the whole lattice",
+               "seconds_per_contraction": t_all}
+    out_j = {"metric": METRIC, "workload": "npr_20x20x20x64", "value": 1.0 / dt, "unit": "contractions/s",
+             "ms_per_contraction": dt * 1e3, "operators": len(ops), "hypercubes": nz, "dtype": "f64",
+             "gflop_per_contraction": flops / 1e9,
+             "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                          "frac": tf / PEAK_FP64_TFLOPS, "traffic": None,
+                          "kernel": "npr_kernel (FP64 VALU)"},
+             "oracle_sampled_hypercubes": len(zs), "oracle_max_rel_error": err,
+             "propagator_solves_s": t_prop,
+             "paper_context": {"npr_gflops_titan_black": 113.36, "npr_gflops_gtx580": 76.19,
+                               "note": "other hardware, real ensemble, the paper's code and flop convention"}}
+    if cpu:
+        out_j["cpu_baseline"] = cpu
+    print(json.dumps(out_j), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -754,6 +952,8 @@ def main():
         run_threelevel(args, asq, torch)
     elif args.workload == "asqtad_20x20x20x64":
         run_asqtad(args, asq, torch)
+    elif args.workload == "npr_20x20x20x64":
+        run_npr(args, asq, torch)
     else:
         run_serving(args, asq, torch)
 

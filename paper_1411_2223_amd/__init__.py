@@ -44,7 +44,7 @@ class asq_cg_params(ctypes.Structure):
 class asq_cg_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
                 ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("gflops", ctypes.c_double)]
+                ("gflops", ctypes.c_double), ("escalations", ctypes.c_int), ("final_mode", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -63,10 +63,16 @@ _SIGS = {
     "asq_gauge_bytes": (ctypes.c_size_t, [ctypes.POINTER(asq_gauge_desc)]),
     "asq_gauge_create": (ctypes.c_int, [ctypes.POINTER(asq_gauge_desc), _vp, _vp, _vp, ctypes.c_size_t, _vp,
                                         ctypes.POINTER(_vp)]),
+    "asq_gauge_create_device": (ctypes.c_int, [ctypes.POINTER(asq_gauge_desc), _vp, _vp, _vp, ctypes.c_size_t, _vp,
+                                               ctypes.POINTER(_vp)]),
     "asq_gauge_destroy": (ctypes.c_int, [_vp]),
     "asqtad_dslash_eo": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "asqtad_dslash_eo_variant": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
                                                 ctypes.c_int, _vp]),
+    "asq_vec_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_size_t]),
+    "asq_vec_convert": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp]),
+    "asq_vec_to_native": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    "asq_vec_from_native": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "asq_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int]),
     "cg_solve": (ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t,
                                 ctypes.POINTER(asq_cg_params), ctypes.POINTER(asq_cg_stats), _vp]),
@@ -84,7 +90,7 @@ _SIGS = {
     "serve_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
     "serve_register_gauge": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int)]),
     "serve_submit": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp,
-                                    ctypes.POINTER(asq_cg_params), ctypes.POINTER(ctypes.c_uint64)]),
+                                    ctypes.POINTER(asq_cg_params), ctypes.POINTER(ctypes.c_uint64), _vp]),
     "serve_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(asq_cg_stats),
                                   ctypes.POINTER(ctypes.c_double)]),
     "serve_destroy": (ctypes.c_int, [_vp]),
@@ -92,6 +98,8 @@ _SIGS = {
     "asqtad_plaquette_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int)]),
     "asqtad_plaquette": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _vp, _vp, ctypes.c_size_t,
                                         ctypes.POINTER(ctypes.c_double), _vp]),
+    "asqtad_npr_fourfermion": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_int), _vp, _vp]),
     "asq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "asq_last_error": (ctypes.c_char_p, []),
     "asq_copy_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
@@ -104,17 +112,20 @@ EXPORTS = tuple(_SIGS)
 _lib = None
 
 
-def variant_code(cols: int, pipe: bool = False, order: int = 0) -> int:
+ASQ_VARIANT_NATIVE = 0x100000
+
+
+def variant_code(cols: int, pipe: bool = False, order: int = 0, native: bool = False) -> int:
     """Launch variant of asqtad_dslash_eo_variant: columns per thread (1, 2, 4, 8, 12), pipelined hop
     loop, block order (0 tiles of a site block adjacent; 1, 2, 3 tile by tile in
-    groups of 16, 64 or all site blocks)."""
-    return int(cols) | (0x100 if pipe else 0) | (int(order) << 12)
+    groups of 16, 64 or all site blocks); native: vectors in the solvers' native layout."""
+    return int(cols) | (0x100 if pipe else 0) | (int(order) << 12) | (ASQ_VARIANT_NATIVE if native else 0)
 
 
 def variant_code_mfma(order: int = 0) -> int:
-    """The matrix-core launch variant (FP32 18-real links with FP16 vectors only):
-    32 columns per block, with one of the four block orders."""
-    return 0x10000 | 32 | (int(order) << 12)
+    """The matrix-core launch variant (FP32 18-real links with FP16 vectors only, native
+    layout): 32 columns per block, with one of the four block orders."""
+    return 0x10000 | 32 | (int(order) << 12) | ASQ_VARIANT_NATIVE
 
 
 # Every launch variant the library builds: (cols, pipe, order).
@@ -172,6 +183,7 @@ def stream_ptr(stream=None):
 
 
 VEC_SITE_BYTES = {"f64": 48, "f32": 24, "f16": 16}
+_TORCH_DT = {"f64": "float64", "f32": "float32", "f16": "uint8"}
 
 
 def _need(t, nbytes, where, name):
@@ -194,51 +206,51 @@ def empty_bytes(n, device="cuda"):
     return t
 
 
-def vec_to_device(v, prec="f64", device="cuda"):
-    """(nrhs, V/2, 3) complex host array -> device tensor in the library's layout.
-
-    f64/f32: [nrhs][3][V/2][2]; f16: 16-byte records [nrhs][V/2] (encoded on the host).
-    """
+def empty_vec(nsites, prec="f64", device="cuda"):
+    """A device tensor holding nsites canonical colour-vector records of tier prec."""
     torch = _torch()
-    v = np.asarray(v)
+    load()
+    n = asq_vec_bytes(PRECS[prec], int(nsites))
+    return torch.empty(n // np.dtype(_TORCH_DT[prec]).itemsize, dtype=getattr(torch, _TORCH_DT[prec]),
+                       device=device)
+
+
+def vec_convert(src, nsites, src_prec, dst_prec, dst=None, stream=None):
+    """dst = src converted between canonical tiers by the library (asq_vec_convert)."""
+    load()
+    if dst is None:
+        dst = empty_vec(nsites, dst_prec, src.device)
+    _need(src, nsites * VEC_SITE_BYTES[src_prec], "vec_convert", "src")
+    _need(dst, nsites * VEC_SITE_BYTES[dst_prec], "vec_convert", "dst")
+    check(asq_vec_convert(int(nsites), PRECS[src_prec], src.data_ptr(), PRECS[dst_prec], dst.data_ptr(),
+                          stream_ptr(stream)), "asq_vec_convert")
+    return dst
+
+
+def vec_to_device(v, prec="f64", device="cuda", stream=None):
+    """(nrhs, V/2, 3) complex host array -> device tensor in the canonical layout of tier prec.
+
+    The complex128 array already is the canonical FP64 layout [nrhs][V/2][3][2]; it is
+    uploaded as is, and the library converts it to FP32 or FP16-with-norm when asked."""
+    torch = _torch()
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.complex128))
     if v.ndim == 2:
         v = v[None]
-    if prec == "f16":
-        return torch.from_numpy(encode_f16n(v)).to(device)
-    dt = np.float64 if prec == "f64" else np.float32
-    a = np.ascontiguousarray(np.stack([v.real, v.imag], axis=-1).transpose(0, 2, 1, 3)).astype(dt)
-    return torch.from_numpy(a).to(device)
+    t = torch.from_numpy(v.reshape(-1).view(np.float64)).to(device)
+    if prec == "f64":
+        return t
+    return vec_convert(t, v.shape[0] * v.shape[1], "f64", prec, stream=stream)
 
 
-def vec_from_device(t, nrhs, half, prec="f64"):
-    """Inverse of vec_to_device: device tensor -> (nrhs, V/2, 3) complex128 host array."""
-    a = t.detach().cpu().numpy()
-    if prec == "f16":
-        return decode_f16n(a.view(np.uint8).reshape(-1)[: nrhs * half * 16], nrhs, half)
-    a = a.reshape(nrhs, 3, half, 2).astype(np.float64)
-    return (a[..., 0] + 1j * a[..., 1]).transpose(0, 2, 1)
-
-
-def encode_f16n(v):
-    """Host encoding of the F16 vector tier: per site six binary16 of psi/nu, then nu (float32)."""
-    v = np.asarray(v, dtype=np.complex128)
-    nrhs, half = v.shape[:2]
-    comp = np.stack([v.real, v.imag], axis=-1).reshape(nrhs, half, 6).astype(np.float32)
-    nu = np.abs(comp).max(axis=-1)
-    inv = np.where(nu > 0, 1.0 / np.where(nu > 0, nu, 1), 0).astype(np.float32)
-    h = (comp * inv[..., None]).astype(np.float16)
-    rec = np.empty((nrhs, half, 16), dtype=np.uint8)
-    rec[..., :12] = h.view(np.uint8).reshape(nrhs, half, 12)
-    rec[..., 12:] = nu.astype(np.float32).view(np.uint8).reshape(nrhs, half, 4)
-    return rec.reshape(-1)
-
-
-def decode_f16n(rec, nrhs, half):
-    rec = np.asarray(rec, dtype=np.uint8).reshape(nrhs, half, 16)
-    h = rec[..., :12].copy().view(np.float16).reshape(nrhs, half, 6).astype(np.float64)
-    nu = rec[..., 12:].copy().view(np.float32).reshape(nrhs, half).astype(np.float64)
-    comp = (h * nu[..., None]).reshape(nrhs, half, 3, 2)
-    return comp[..., 0] + 1j * comp[..., 1]
+def vec_from_device(t, nrhs, half, prec="f64", stream=None):
+    """Inverse of vec_to_device: canonical device tensor -> (nrhs, V/2, 3) complex128 host array
+    (FP32 and FP16 tiers widened to FP64 by the library first)."""
+    torch = _torch()
+    if prec != "f64":
+        t = vec_convert(t, nrhs * half, prec, "f64", stream=stream)
+    torch.cuda.synchronize(t.device)
+    a = t.detach().cpu().numpy().view(np.float64)[: nrhs * half * 6]
+    return a.view(np.complex128).reshape(nrhs, half, 3).copy()
 
 
 def links_to_device(a, device="cuda"):
@@ -291,6 +303,32 @@ def plaquette(dims, thin_dev, stream=None) -> float:
     return p.value
 
 
+def npr_fourfermion(dims, thin_dev, props, ops, out=None, stream=None):
+    """The one-colour four-fermion operator of Eq. (1) (asqtad_npr_fourfermion): thin_dev the
+    canonical links (V * 4 * 18 float64), props four float64 device tensors of V * 18 reals
+    (G1..G4, [site][colour][source colour] complex), ops [(S1, F1, S2, F2), ...].  Returns out,
+    float64 [nop][V/16][81][2] (indices a1 a2 a3 a4); the work is enqueued on the stream."""
+    torch = _torch()
+    load()
+    dims = tuple(int(d) for d in dims)
+    V = int(np.prod(dims))
+    op = np.ascontiguousarray(np.asarray(ops, dtype=np.int32).reshape(-1, 4))
+    nop = op.shape[0]
+    _need(thin_dev, V * 4 * 18 * 8, "npr_fourfermion", "thin links")
+    for k, g in enumerate(props):
+        _need(g, V * 18 * 8, "npr_fourfermion", f"propagator {k + 1}")
+    if len(props) != 4:
+        raise AsqError(ASQ_EINVAL, "npr_fourfermion", "four propagators (G1, G2, G3, G4)")
+    if out is None:
+        out = torch.empty(nop * (V // 16) * 162, dtype=torch.float64, device=thin_dev.device)
+    _need(out, nop * (V // 16) * 162 * 8, "npr_fourfermion", "out")
+    rc = asqtad_npr_fourfermion((ctypes.c_int * 4)(*dims), thin_dev.data_ptr(), props[0].data_ptr(),
+                                props[1].data_ptr(), props[2].data_ptr(), props[3].data_ptr(), int(nop),
+                                op.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), out.data_ptr(), stream_ptr(stream))
+    check(rc, "asqtad_npr_fourfermion")
+    return out
+
+
 @dataclass
 class SolveResult:
     x: object
@@ -318,23 +356,27 @@ class Gauge:
             raise AsqError(ASQ_EINVAL, "asq_gauge_bytes")
         V = int(np.prod(self.dims))
 
-        def up(a):
-            if isinstance(a, torch.Tensor):  # already on the device (e.g. from build_links)
+        on_dev = [isinstance(a, torch.Tensor) for a in (fat, lng)]
+        if on_dev[0] != on_dev[1]:
+            raise AsqError(ASQ_EINVAL, "Gauge: fat and long links must both be host arrays or both device tensors")
+        if on_dev[0]:  # already on the device (e.g. from build_links): imported in place
+            for a in (fat, lng):
                 if (a.dtype != torch.float64 or a.numel() != V * 4 * 18 or not a.is_contiguous()
                         or a.device.type != "cuda"):
                     raise AsqError(ASQ_EINVAL, "Gauge: device links must be contiguous float64 CUDA tensors "
                                                "of V*4*18 reals")
-                return a
-            a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(V, 4, 3, 3))
-            return torch.from_numpy(a.view(np.float64)).to(device)
-
-        fat_d, lng_d = up(fat), up(lng)
+            ptrs = (fat.data_ptr(), lng.data_ptr())
+            create = asq_gauge_create_device
+        else:  # host arrays: the library copies them in
+            keep = [np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(V, 4, 3, 3)) for a in (fat, lng)]
+            ptrs = tuple(k.ctypes.data for k in keep)
+            create = asq_gauge_create
         self.storage = empty_bytes(nbytes, device)
         h = ctypes.c_void_p()
-        rc = asq_gauge_create(ctypes.byref(self.desc), fat_d.data_ptr(), lng_d.data_ptr(), self.storage.data_ptr(),
-                              nbytes, stream_ptr(stream), ctypes.byref(h))
-        del fat_d, lng_d
-        check(rc, "asq_gauge_create")
+        with torch.cuda.device(self.storage.device):
+            rc = create(ctypes.byref(self.desc), ptrs[0], ptrs[1], self.storage.data_ptr(), nbytes,
+                        stream_ptr(stream), ctypes.byref(h))
+        check(rc, create.__name__)
         self.handle = h
         self.device = device
 
@@ -365,8 +407,9 @@ class Gauge:
             pass
 
     def dslash(self, out_parity, vin, prec="f64", nrhs=1, out=None, stream=None, variant=None):
-        """out = D_{out_parity <- other} vin on device tensors in the library layout, with the
-        tuned launch variant or the given one (see variant_code)."""
+        """out = D_{out_parity <- other} vin on device tensors in the canonical layout of tier prec,
+        with the tuned launch variant or the given one (see variant_code; a native variant takes
+        vectors in the solvers' layout, see to_native)."""
         torch = _torch()
         if out is None:
             out = torch.empty_like(vin)
@@ -383,6 +426,28 @@ class Gauge:
             check(rc, "asqtad_dslash_eo_variant")
         return out
 
+    def to_native(self, v, prec="f64", nrhs=1, out=None, stream=None):
+        """Canonical device vectors -> the solvers' native layout (asq_vec_to_native)."""
+        torch = _torch()
+        out = torch.empty_like(v) if out is None else out
+        nbytes = int(nrhs) * self.half * VEC_SITE_BYTES[prec]
+        _need(v, nbytes, "to_native", "v")
+        _need(out, nbytes, "to_native", "out")
+        check(asq_vec_to_native(self.handle, PRECS[prec], int(nrhs), v.data_ptr(), out.data_ptr(), stream_ptr(stream)),
+              "asq_vec_to_native")
+        return out
+
+    def from_native(self, v, prec="f64", nrhs=1, out=None, stream=None):
+        """Native-layout device vectors -> canonical (asq_vec_from_native)."""
+        torch = _torch()
+        out = torch.empty_like(v) if out is None else out
+        nbytes = int(nrhs) * self.half * VEC_SITE_BYTES[prec]
+        _need(v, nbytes, "from_native", "v")
+        _need(out, nbytes, "from_native", "out")
+        check(asq_vec_from_native(self.handle, PRECS[prec], int(nrhs), v.data_ptr(), out.data_ptr(),
+                                  stream_ptr(stream)), "asq_vec_from_native")
+        return out
+
     def default_delta(self, mode):
         """Reliable-update trigger: 0.01, or 0.1 when the FP16 tier iterates with 16-bit
         links (their rounding makes the iterated residual drift faster: at 48^3 x 96 the
@@ -395,7 +460,7 @@ class Gauge:
 
     def solve(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=None, poll_iters=16, use_graph=True,
               work=None, x=None, stream=None):
-        """Batched CG: b is a device tensor [nrhs][3][V/2][2] float64; returns SolveResult."""
+        """Batched CG: b is a canonical device tensor [nrhs][V/2][3][2] float64; returns SolveResult."""
         torch = _torch()
         masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
         nrhs = len(masses)
@@ -415,14 +480,14 @@ class Gauge:
         m = (ctypes.c_double * nrhs)(*masses)
         rc = cg_solve_batch(self.handle, nrhs, m, b.data_ptr(), x.data_ptr(), work.data_ptr(), work.numel(),
                             ctypes.byref(params), stats, stream_ptr(stream))
-        if rc < 0 and rc not in (ASQ_ENOCONV,):
+        if rc < 0 and rc not in (ASQ_ENOCONV, ASQ_ENAN):  # per-column outcomes: x and stats are written
             check(rc, "cg_solve_batch")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
 
     def solve_multishift(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=None, poll_iters=16,
                          use_graph=True, work=None, x=None, stream=None):
-        """Every (mass, source) pair: b is a device tensor [nsrc][3][V/2][2] float64; x is
-        [nmass][nsrc][3][V/2][2] (column j * nsrc + s); returns SolveResult over those columns."""
+        """Every (mass, source) pair: b is a canonical device tensor [nsrc][V/2][3][2] float64; x is
+        [nmass][nsrc][V/2][3][2] (column j * nsrc + s); returns SolveResult over those columns."""
         torch = _torch()
         masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
         nmass = len(masses)
@@ -444,14 +509,14 @@ class Gauge:
         m = (ctypes.c_double * nmass)(*masses)
         rc = cg_solve_multishift(self.handle, nsrc, nmass, m, b.data_ptr(), x.data_ptr(), work.data_ptr(),
                                  work.numel(), ctypes.byref(params), stats, stream_ptr(stream))
-        if rc < 0 and rc not in (ASQ_ENOCONV,):
+        if rc < 0 and rc not in (ASQ_ENOCONV, ASQ_ENAN):  # per-column outcomes: x and stats are written
             check(rc, "cg_solve_multishift")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
 
     def solve_full(self, masses, b, mode="mixed32", tol=1e-10, maxiter=20000, delta=None, poll_iters=16,
                    use_graph=True, work=None, x=None, stream=None):
-        """M x = b on both parities (M = 2m + D): b is a device tensor [2][nrhs][3][V/2][2] float64
-        (even halves, then odd halves); returns SolveResult with |b - M x| / |b| per column."""
+        """M x = b on both parities (M = 2m + D): b is a canonical device tensor [2][nrhs][V/2][3][2]
+        float64 (even halves, then odd halves); returns SolveResult with |b - M x| / |b| per column."""
         torch = _torch()
         masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
         nrhs = len(masses)
@@ -470,7 +535,7 @@ class Gauge:
         m = (ctypes.c_double * nrhs)(*masses)
         rc = cg_solve_full(self.handle, nrhs, m, b.data_ptr(), x.data_ptr(), work.data_ptr(), work.numel(),
                            ctypes.byref(params), stats, stream_ptr(stream))
-        if rc < 0 and rc not in (ASQ_ENOCONV,):
+        if rc < 0 and rc not in (ASQ_ENOCONV, ASQ_ENAN):  # per-column outcomes: x and stats are written
             check(rc, "cg_solve_full")
         return SolveResult(x, [s.as_dict() for s in stats], rc)
 
@@ -494,7 +559,9 @@ class Server:
         return gid.value
 
     def submit(self, gauge_id, masses, b, x, mode="mixed32", tol=1e-10, maxiter=20000, delta=None, poll_iters=8,
-               use_graph=True):
+               use_graph=True, stream=None):
+        """Queue a batched solve of canonical b into x; the server reads b after the work already
+        enqueued on `stream` (torch's current stream by default).  Returns the ticket."""
         masses = np.atleast_1d(np.asarray(masses, dtype=np.float64))
         n = len(masses)
         if delta is None:
@@ -506,7 +573,7 @@ class Server:
         _need(x, n * half * 48, "serve_submit", "x")
         t = ctypes.c_uint64()
         rc = serve_submit(self.handle, int(gauge_id), n, (ctypes.c_double * n)(*masses), b.data_ptr(), x.data_ptr(),
-                          ctypes.byref(params), ctypes.byref(t))
+                          ctypes.byref(params), ctypes.byref(t), stream_ptr(stream))
         check(rc, "serve_submit")
         return t.value
 

@@ -17,8 +17,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libasqtad.so")
 
-SOURCES = ["gauge.hip", "dslash.hip", "dslash_f64.hip", "dslash_f32.hip", "dslash_r12.hip", "dslash_i16.hip",
-           "blas.hip", "solver.hip", "tune.hip", "serve.hip", "full.hip", "multishift.hip", "fatten.hip"]
+SOURCES = ["gauge.hip", "dslash.hip", "dslash_f64.hip", "dslash_f32.hip", "dslash_r12.hip", "dslash_i16.hip", "dslash_f64f32.hip",
+           "blas.hip", "solver.hip", "boundary.hip", "tune.hip", "serve.hip", "full.hip", "multishift.hip", "fatten.hip", "npr.hip"]
 ARCH = os.environ.get("ASQ_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

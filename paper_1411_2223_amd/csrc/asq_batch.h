@@ -1,6 +1,8 @@
 // asq_batch.h -- a batch of CG columns sharing one gauge field and one set of
 // device buffers; used by cg_solve_batch and by the serving loop.
 #pragma once
+#include <vector>
+
 #include "asq_internal.h"
 
 namespace asq {
@@ -47,6 +49,12 @@ struct Batch {
 int mode_pt(int mode);
 int mode_rt(int mode);
 size_t batch_bytes(const asq_gauge* g, int ncol, int mode, bool with_bx);
+// Workspace of solve_batch: the batch of `mode` or of any tier a stalled column
+// escalates to (mixed16 -> mixed32 -> f64), then room to gather the escalated
+// columns' b and x.
+size_t solve_bytes(const asq_gauge* g, int ncol, int mode);
+// The tier a stalled column of `mode` continues in (-1: none).
+int next_mode(int mode);
 // Lay the batch out in `work`; b == nullptr puts b and x in the workspace too.
 int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, size_t bytes, const double* b,
                 double* x);
@@ -65,6 +73,26 @@ int solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double
                 double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
                 void* hip_stream, bool guess = false);
 int enqueue_init_guess(const Batch& B, hipStream_t s);
+int escalate(const asq_gauge* g, const std::vector<int>& cols, const std::vector<double>& masses,
+             const std::vector<double>& tols, const std::vector<int>& iters, const std::vector<int>& rus,
+             const double* b_dev, double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
+             asq_cg_stats* stats, void* hip_stream);
+// One Dslash on caller buffers (the public operator, and the solvers' FP64
+// operator on native layouts): variant < 0 takes the tuned launch variant.
+int dslash_run(const char* who, const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
+               void* out_dev, int variant, bool canonical, hipStream_t stream);
+// The solvers on native layouts (b and x as structures of arrays); the C ABI
+// entry points relayout canonical vectors around them.
+size_t multishift_native_bytes(const asq_gauge* g, int nsrc, int nmass, int mode);
+int solve_multishift_native(const asq_gauge* g, int nsrc, int nmass, const double* masses, const double* b_dev,
+                            double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
+                            asq_cg_stats* stats, void* hip_stream);
+size_t full_native_bytes(const asq_gauge* g, int nrhs, int mode);
+int solve_full_native(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev, double* x_dev,
+                      void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
+                      void* hip_stream);
+// Canonical <-> native relayout of nrhs colour vectors of one parity (tier kind).
+int relayout(int kind, bool to_native, int nrhs, int half, const void* src, void* dst, hipStream_t s);
 void fill_stats(const Batch& B, const ColState* S, double seconds, asq_cg_stats* out, int* worst);
 int check_params(const asq_gauge* g, const asq_cg_params* p);
 

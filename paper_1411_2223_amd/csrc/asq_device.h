@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace asq {
 
 constexpr int kBlock = 256;  // sites per block and per reduction group (fixed: keeps sums batch-invariant)
@@ -217,7 +219,16 @@ __device__ __forceinline__ void reconstruct_row2(Mat3<R>& U) {
 // SU(3) part (link / coefficient); the kernel rebuilds row 3 and applies
 // coefficient * eta * boundary sign to the product.
 // ---------------------------------------------------------------------------
-enum LinkKind { LINK_F64_R18 = 0, LINK_F32_R18 = 1, LINK_F32_R12 = 2, LINK_I16_R12 = 3, LINK_KINDS = 4 };
+// LINK_F64_F32 is no storage of its own: the FP64 18-real links read by an FP32
+// Dslash, converted on load (a field kept in FP64 only still runs the mixed CG).
+enum LinkKind {
+  LINK_F64_R18 = 0,
+  LINK_F32_R18 = 1,
+  LINK_F32_R12 = 2,
+  LINK_I16_R12 = 3,
+  LINK_F64_F32 = 4,
+  LINK_KINDS = 5
+};
 
 struct LinkF64R18 {
   using real = double;
@@ -248,6 +259,39 @@ struct LinkF64R18 {
       const d2 v = __builtin_nontemporal_load(q + (size_t)k * half);
       U.e[k / 3][k % 3].re = v.x;
       U.e[k / 3][k % 3].im = v.y;
+    }
+    return U;
+  }
+};
+
+// FP64 18-real storage, FP32 arithmetic: each double is rounded to float on load.
+struct LinkF64F32 {
+  using real = float;
+  using chunk = double2;
+  static constexpr int NCH = 9;
+  static constexpr bool folded = true;
+  __device__ __forceinline__ static Mat3<float> load(const void* base, int half, int p, int slot, int i) {
+    const double2* q = reinterpret_cast<const double2*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    Mat3<float> U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 v = q[(size_t)k * half];
+      U.e[k / 3][k % 3].re = (float)v.x;
+      U.e[k / 3][k % 3].im = (float)v.y;
+    }
+    return U;
+  }
+  // non-temporal loads, as for the FP64 tier: these links do not stay in the
+  // memory-side cache between launches either
+  __device__ __forceinline__ static Mat3<float> load_streaming(const void* base, int half, int p, int slot, int i) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* q = reinterpret_cast<const d2*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    Mat3<float> U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const d2 v = __builtin_nontemporal_load(q + (size_t)k * half);
+      U.e[k / 3][k % 3].re = (float)v.x;
+      U.e[k / 3][k % 3].im = (float)v.y;
     }
     return U;
   }
@@ -321,7 +365,10 @@ struct LinkI16R12 {
 // colour-vector storage tiers (one parity, ncol columns):
 //   F64: double2 [col][colour][half]       F32: float2 [col][colour][half]
 //   F16: 16-byte record [col][half] = six binary16 values (c0re c0im c1re ...)
-//        scaled by 1/nu, then nu as float32; nu = max |component|.
+//        h = component x r rounded once to binary16 (nearest even), r = 1/nu in
+//        float32, then nu as float32; nu = max |component|.  The product and the
+//        rounding are one mixed-precision FMA (v_fma_mixlo_f16), so the product
+//        is never rounded to float32 first.
 // ---------------------------------------------------------------------------
 enum VecKind { VEC_F64 = 0, VEC_F32 = 1, VEC_F16 = 2 };
 
@@ -450,6 +497,109 @@ struct VecF16 {
     return unpack(w);
   }
 };
+
+// ---------------------------------------------------------------------------
+// canonical colour-vector layouts of the C ABI (one parity, ncol columns):
+//   F64: double2 [col][half][3]    F32: float2 [col][half][3]
+//   F16: binary16 pairs [col][half][3] (psi / nu), then float nu [col][half]
+// The public Dslash reads and writes these directly (PLAIN epilogue only);
+// the solvers keep the structures of arrays above and relayout at entry/exit.
+// ---------------------------------------------------------------------------
+struct VecF64C {
+  using real = double;
+  using raw = Vec3<double>;
+  static constexpr int kind = VEC_F64;
+  __device__ __forceinline__ static Vec3<double> load(const void* base, int half, int col, int i) {
+    const double2* q = reinterpret_cast<const double2*>(base) + ((size_t)col * half + i) * 3;
+    Vec3<double> v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double2 w = q[a];
+      v.c[a].re = w.x;
+      v.c[a].im = w.y;
+    }
+    return v;
+  }
+  __device__ __forceinline__ static Vec3<double> store(void* base, int half, int col, int i, const Vec3<double>& v) {
+    double2* q = reinterpret_cast<double2*>(base) + ((size_t)col * half + i) * 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[a] = make_double2(v.c[a].re, v.c[a].im);
+    return v;
+  }
+};
+
+struct VecF32C {
+  using real = float;
+  using raw = Vec3<float>;
+  static constexpr int kind = VEC_F32;
+  __device__ __forceinline__ static Vec3<float> load(const void* base, int half, int col, int i) {
+    const float2* q = reinterpret_cast<const float2*>(base) + ((size_t)col * half + i) * 3;
+    Vec3<float> v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float2 w = q[a];
+      v.c[a].re = w.x;
+      v.c[a].im = w.y;
+    }
+    return v;
+  }
+  __device__ __forceinline__ static Vec3<float> store(void* base, int half, int col, int i, const Vec3<float>& v) {
+    float2* q = reinterpret_cast<float2*>(base) + ((size_t)col * half + i) * 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[a] = make_float2(v.c[a].re, v.c[a].im);
+    return v;
+  }
+};
+
+// The record of VecF16 gathered from the split canonical arrays: the three
+// words of binary16 pairs, then the norm.  ncol: columns of the whole buffer
+// (the norms follow all of them).
+struct VecF16C {
+  using real = float;
+  using raw = uint4;
+  static constexpr int kind = VEC_F16;
+  __device__ __forceinline__ static const float* norms(const void* base, int half, int ncol) {
+    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (size_t)ncol * half * 12);
+  }
+  __device__ __forceinline__ static uint4 load_rec(const void* base, int half, int ncol, int col, int i) {
+    const size_t k = (size_t)col * half + i;
+    const uint32_t* q = reinterpret_cast<const uint32_t*>(base) + k * 3;
+    uint4 w;
+    w.x = q[0];
+    w.y = q[1];
+    w.z = q[2];
+    w.w = __float_as_uint(norms(base, half, ncol)[k]);
+    return w;
+  }
+  __device__ __forceinline__ static void store_rec(void* base, int half, int ncol, int col, int i, const uint4 w) {
+    const size_t k = (size_t)col * half + i;
+    uint32_t* q = reinterpret_cast<uint32_t*>(base) + k * 3;
+    q[0] = w.x;
+    q[1] = w.y;
+    q[2] = w.z;
+    const_cast<float*>(norms(base, half, ncol))[k] = __uint_as_float(w.w);
+  }
+  __device__ __forceinline__ static Vec3<float> store(void* base, int half, int ncol, int col, int i,
+                                                      const Vec3<float>& v) {
+    const uint4 w = VecF16::encode(v);
+    store_rec(base, half, ncol, col, i, w);
+    return VecF16::unpack(w);
+  }
+};
+
+// Loads and stores by tier with the whole buffer's column count (only the
+// canonical FP16 layout needs it: its norms follow every column's halves).
+template <class T>
+__device__ __forceinline__ uint4 load_rec_any(const void* base, int half, int ncol, int col, int i) {
+  if constexpr (std::is_same<T, VecF16C>::value) return VecF16C::load_rec(base, half, ncol, col, i);
+  else return VecF16::load_rec(base, half, col, i);
+}
+template <class T>
+__device__ __forceinline__ Vec3<typename T::real> store_any(void* base, int half, int ncol, int col, int i,
+                                                            const Vec3<typename T::real>& v) {
+  if constexpr (std::is_same<T, VecF16C>::value) return VecF16C::store(base, half, ncol, col, i, v);
+  else return T::store(base, half, col, i, v);
+}
 
 template <class RD, class RS>
 __device__ __forceinline__ Vec3<RD> convert(const Vec3<RS>& v) {

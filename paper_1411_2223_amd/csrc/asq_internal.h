@@ -43,7 +43,8 @@ struct asq_gauge {
   void* base;                    // caller's storage
   size_t bytes;
   void* links[asq::LINK_KINDS];  // nullptr when the tier is not kept
-  int sloppy_link32;             // link kind used by F32 vectors (LINK_F32_R18 or LINK_F32_R12)
+  int sloppy_link32;             // link kind used by F32 vectors (LINK_F32_R18 or LINK_F32_R12, or
+                                 // LINK_F64_F32 when only FP64 links are kept)
   int sloppy_link16;             // link kind used by F16 vectors
   int nblk;                      // site blocks of kBlock covering one parity
 };
@@ -55,7 +56,8 @@ namespace asq {
 //   NORM    out = D in, block partials of |out|^2 (as stored)
 //   UPDATE  Ap = a y - D in in registers; r -= alpha Ap, x += alpha y; partials of |r|^2
 //   RESID   out = b - a y + D in in FP64, stored in the output tier; partials of |out|^2
-enum Epi { EPI_PLAIN = 0, EPI_NORM = 1, EPI_UPDATE = 2, EPI_RESID = 3 };
+//   CANON   out = D in, both in the canonical layouts of the C ABI (the public operator)
+enum Epi { EPI_PLAIN = 0, EPI_NORM = 1, EPI_UPDATE = 2, EPI_RESID = 3, EPI_CANON = 4 };
 // Column masks (read from the per-column solver state).
 enum Mask { MASK_ALL = 0, MASK_ACTIVE = 1, MASK_RELIABLE = 2 };
 
@@ -82,8 +84,16 @@ struct alignas(128) ColState {
   int status;      // 0 ok, ASQ_ENAN on a non-finite or non-positive reduction
   int pbuf;        // which of the two p buffers holds the current direction
   int sloppy_stop; // stop at the iterated residual, without an FP64 decision (shifted CG's first phase)
+  // stagnation: stall_updates reliable updates in a row whose true |r|^2 is not below
+  // stall_fac * ref_rr (ref_rr: |r|^2 at the last update that was) stop the column with
+  // escalate = 1, and the host continues it from its x in the next precision tier
+  double ref_rr;
+  double stall_fac;
+  int stall_updates;  // 0: never escalate
+  int n_stall;
+  int escalate;
 };
-static_assert(sizeof(ColState) == 128, "ColState layout");
+static_assert(sizeof(ColState) == 256, "ColState layout");
 
 // Scalar updates applied to a column from its reduced sums (see asq_reduce.h).
 enum ReduceOp { OP_INIT = 0, OP_ALPHA = 1, OP_BETA = 2, OP_RU = 3, OP_INIT_GUESS = 5 };
@@ -125,6 +135,8 @@ int launch_dslash_f64(int out_kind, int epi, int rtile, const DslashArgs& a, hip
 int launch_dslash_f32r18(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
 int launch_dslash_f32r12(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
 int launch_dslash_i16r12(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
+int launch_dslash_f64f32(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
+// (each also takes epi = EPI_CANON: the PLAIN operator on canonical layouts)
 // Launch variant code: columns per thread (1, 2, 4, 8, 12) in the low byte,
 // kPipeBit for the software-pipelined hop loop, and the block order << kOrderShift:
 // 0 the tiles of a site block adjacent; 1, 2, 3 tile by tile inside groups of
@@ -148,7 +160,9 @@ constexpr int kFoldAlphaMaxTile = 2;
 // Tuned launch variant for a Dslash configuration.
 int tuned_rtile(const asq_gauge* g, int link_kind, int in_kind, int out_kind, int epi, int ncol);
 // Time the candidate tiles once per configuration (in_buf read, out_buf scratch).
+// epi_timed: EPI_PLAIN (the solvers' layouts; the winner serves every epilogue)
+// or EPI_CANON (the public operator); persist: also write the ASQ_TUNE_CACHE file.
 int tune_dslash(const asq_gauge* g, int link_kind, int in_kind, int ncol, const void* in_buf, void* out_buf,
-                hipStream_t s);
+                hipStream_t s, int epi_timed = EPI_PLAIN, bool persist = true);
 
 }  // namespace asq

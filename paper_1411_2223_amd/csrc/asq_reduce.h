@@ -32,6 +32,9 @@ __device__ inline void finalize_column(ColState& S, double s, int op) {
       S.status = finite ? 0 : ASQ_ENAN;
       S.converged = finite && s == 0;
       S.active = finite && s > 0;
+      S.ref_rr = s;
+      S.n_stall = 0;
+      S.escalate = 0;
       break;
     case OP_ALPHA:
       S.pAp = s;
@@ -81,7 +84,15 @@ __device__ inline void finalize_column(ColState& S, double s, int op) {
       } else if (S.iters >= S.maxiter) {
         S.status = ASQ_ENOCONV;
         S.active = 0;
+      } else if (S.stall_updates > 0 && !(s < S.stall_fac * S.ref_rr) && ++S.n_stall >= S.stall_updates) {
+        // the true residual stopped falling in this precision: hand the column on
+        S.escalate = 1;
+        S.active = 0;
       } else {
+        if (s < S.stall_fac * S.ref_rr) {
+          S.ref_rr = s;
+          S.n_stall = 0;
+        }
         // r was replaced by the true residual: restart the norm history from it
         S.rr = s;
         S.beta = s / S.rr_old;
@@ -112,6 +123,9 @@ __device__ inline void finalize_guess(ColState& S, double bb, double rr) {
   S.status = finite ? 0 : ASQ_ENAN;
   S.converged = finite && (rr == 0 || (bb > 0 && sqrt(rr) <= S.tol * sqrt(bb)));
   S.active = finite && !S.converged;
+  S.ref_rr = rr;
+  S.n_stall = 0;
+  S.escalate = 0;
 }
 
 // This thread's share of a fixed-order sum of partials[0..n): elements

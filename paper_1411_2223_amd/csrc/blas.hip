@@ -160,11 +160,11 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(ColState* st, const doub
   const double va = two ? strided_sum(pa + (size_t)c * nblk, nblk) : 0.0;
   const int mask = (op == OP_ALPHA || op == OP_BETA) ? MASK_ACTIVE : (op == OP_RU ? MASK_RELIABLE : MASK_ALL);
   if (dst) {
-    ColState S = st[c];
-    const bool on = state_on(S, mask);
+    const bool on = state_on(st[c], mask);
     __shared__ double shd[kBlock / 64];
     const double s = on ? block_sum(vb, shd) : 0.0;  // uniform branch
     if (threadIdx.x == 0) {
+      ColState S = st[c];  // one copy, in thread 0
       if (on) finalize_column(S, s, op);
       dst[c] = S;
     }

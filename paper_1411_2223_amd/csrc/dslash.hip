@@ -20,15 +20,18 @@ int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, 
   if (!variant_built(link_kind, in_kind, rtile)) return ASQ_EINVAL;
   if (link_kind == LINK_F64_R18) {
     if (in_kind != VEC_F64) return ASQ_EINVAL;
+    if (epi == EPI_CANON && out_kind != VEC_F64) return ASQ_EINVAL;
     return launch_dslash_f64(out_kind, epi, rtile, a, s);
   }
   if (epi == EPI_RESID) return ASQ_EINVAL;
-  // PLAIN / NORM write the input tier; UPDATE keeps r in FP32
+  if (epi == EPI_CANON && (rtile & kMfmaBit)) return ASQ_EINVAL;
+  // PLAIN / NORM / CANON write the input tier; UPDATE keeps r in FP32
   const int want_out = epi == EPI_UPDATE ? VEC_F32 : in_kind;
   if (out_kind != want_out) return ASQ_EINVAL;
   if (link_kind == LINK_F32_R18) return launch_dslash_f32r18(in_kind, epi, rtile, a, s);
   if (link_kind == LINK_F32_R12) return launch_dslash_f32r12(in_kind, epi, rtile, a, s);
   if (link_kind == LINK_I16_R12) return launch_dslash_i16r12(in_kind, epi, rtile, a, s);
+  if (link_kind == LINK_F64_F32) return launch_dslash_f64f32(in_kind, epi, rtile, a, s);
   return ASQ_EINVAL;
 }
 

@@ -10,6 +10,7 @@ int launch_dslash_f64(int out_kind, int epi, int rtile, const DslashArgs& a, hip
     return ASQ_EINVAL;
   }
   if (out_kind != VEC_F64) return ASQ_EINVAL;
+  if (epi == EPI_CANON) return pick_canon<LinkF64R18, VecF64C>(rtile, a, s);
   return pick_iter<LinkF64R18, VecF64, VecF64>(epi, rtile, a, s);
 }
 

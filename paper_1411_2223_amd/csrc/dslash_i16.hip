@@ -4,8 +4,9 @@
 namespace asq {
 
 int launch_dslash_i16r12(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s) {
-  if (in_kind == VEC_F16) return pick_iter<LinkI16R12, VecF16, VecF32>(epi, rtile, a, s);
-  return ASQ_EINVAL;
+  if (in_kind != VEC_F16) return ASQ_EINVAL;
+  if (epi == EPI_CANON) return pick_canon<LinkI16R12, VecF16C>(rtile, a, s);
+  return pick_iter<LinkI16R12, VecF16, VecF32>(epi, rtile, a, s);
 }
 
 }  // namespace asq

@@ -41,8 +41,8 @@ __device__ __forceinline__ bool col_on(const DslashArgs& A, int c) {
 // Raw neighbour record of one column: FP16 keeps the 16-byte record (halves and
 // norm), the other tiers the colour vector.
 template <class InT>
-__device__ __forceinline__ typename InT::raw fetch(const void* in, int half, int c, int j) {
-  if constexpr (InT::kind == VEC_F16) return VecF16::load_rec(in, half, c, j);
+__device__ __forceinline__ typename InT::raw fetch(const void* in, int half, int ncol, int c, int j) {
+  if constexpr (InT::kind == VEC_F16) return load_rec_any<InT>(in, half, ncol, c, j);
   else return InT::load(in, half, c, j);
 }
 
@@ -78,7 +78,8 @@ __device__ __forceinline__ void term(const typename InT::raw& w, const Mat3<type
 // through the memory-side cache across launches, so they load normally.
 template <class Link, int R>
 __device__ __forceinline__ Mat3<typename Link::real> load_link(const void* base, int half, int p, int slot, int i) {
-  if constexpr (R == 1 && std::is_same<Link, LinkF64R18>::value) return Link::load_streaming(base, half, p, slot, i);
+  if constexpr (R == 1 && (std::is_same<Link, LinkF64R18>::value || std::is_same<Link, LinkF64F32>::value))
+    return Link::load_streaming(base, half, p, slot, i);
   else return Link::load(base, half, p, slot, i);
 }
 
@@ -93,7 +94,7 @@ __device__ __forceinline__ void link_term(const DslashArgs& A, int p, int slot, 
   const Mat3<real> U = load_link<Link, R>(A.links, half, p, slot, site);
   typename InT::raw w[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) w[r] = fetch<InT>(in[r], half, col[r], j);
+  for (int r = 0; r < R; ++r) w[r] = fetch<InT>(in[r], half, A.ncol, col[r], j);
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (on[r]) term<Link, InT, ADJ>(w[r], U, scale, neg, acc[r]);
@@ -105,7 +106,7 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
                                         const int (&col)[R], const void* const (&in)[R],
                                         Vec3<typename InT::real> (&acc)[R]) {
   using real = typename InT::real;
-  static_assert(sizeof(typename Link::real) == sizeof(real), "link and vector arithmetic must match");
+  static_assert(std::is_same<typename Link::real, real>::value, "link and vector arithmetic must match");
   const Geom& g = A.g;
   const int p = A.out_parity;
   const int half = g.half;
@@ -162,7 +163,7 @@ __device__ __forceinline__ void stage_load(const DslashArgs& A, int i, const Sit
   const int j = neighbour<T::MU>(A.g, i, s, T::hop);
   st.U = load_link<Link, R>(A.links, half, T::back ? 1 - p : p, T::slot, T::back ? j : i);
 #pragma unroll
-  for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, col[r], j);
+  for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, A.ncol, col[r], j);
 }
 
 template <class Link, class InT, int R, int K>
@@ -326,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     if (valid) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (on[r]) OutT::store(A.out, half, c0 + r, i, convert<typename OutT::real>(acc[r]));
+        if (on[r]) store_any<OutT>(A.out, half, A.ncol, c0 + r, i, convert<typename OutT::real>(acc[r]));
     }
   } else {
     if constexpr (EPI == EPI_UPDATE && R <= kFoldAlphaMaxTile) {
@@ -462,10 +463,16 @@ int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
     case 8: return pipe ? go<Link, InT, OutT, 8, EPI, true>(a, ord, s) : go<Link, InT, OutT, 8, EPI, false>(a, ord, s);
     case 12:
       // twelve FP64 columns would spill the accumulators: not built
-      if constexpr (std::is_same<InT, VecF64>::value) return ASQ_EINVAL;
+      if constexpr (InT::kind == VEC_F64) return ASQ_EINVAL;
       else return pipe ? go<Link, InT, OutT, 12, EPI, true>(a, ord, s) : go<Link, InT, OutT, 12, EPI, false>(a, ord, s);
   }
   return ASQ_EINVAL;
+}
+
+// The public operator on the canonical layouts of the C ABI (PLAIN epilogue).
+template <class Link, class V>
+int pick_canon(int rtile, const DslashArgs& a, hipStream_t s) {
+  return pick_r<Link, V, V, EPI_PLAIN>(rtile, a, s);
 }
 
 // Iterated tiers: PLAIN and NORM write the input tier; UPDATE takes the residual tier.

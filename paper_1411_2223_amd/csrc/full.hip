@@ -73,16 +73,16 @@ int resid2(const double* b, const double* x, const double* t, size_t n, double a
 
 using namespace asq;
 
-extern "C" size_t asq_full_workspace_bytes(const asq_gauge* g, int nrhs, int mode) {
+size_t asq::full_native_bytes(const asq_gauge* g, int nrhs, int mode) {
   if (!g || nrhs <= 0 || mode < ASQ_MODE_F64 || mode > ASQ_MODE_MIXED16) return 0;
   const size_t n = (size_t)6 * g->geom.half;
-  return batch_bytes(g, nrhs, mode, false) + align_up((size_t)nrhs * n * sizeof(double), 256) +
+  return solve_bytes(g, nrhs, mode) + align_up((size_t)nrhs * n * sizeof(double), 256) +
          align_up(nparts(n) * sizeof(double), 256);
 }
 
-extern "C" int cg_solve_full(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev, double* x_dev,
-                             void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
-                             void* hip_stream) {
+int asq::solve_full_native(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev, double* x_dev,
+                           void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
+                           void* hip_stream) {
   if (!g || nrhs <= 0 || !masses || !b_dev || !x_dev || !work_dev || !stats || !params) {
     set_last_error("cg_solve_full: null pointer or nrhs <= 0");
     return ASQ_EINVAL;
@@ -106,13 +106,13 @@ extern "C" int cg_solve_full(const asq_gauge* g, int nrhs, const double* masses,
     set_last_error("cg_solve_full: b, x and the workspace must not overlap");
     return ASQ_EINVAL;
   }
-  if (work_bytes < asq_full_workspace_bytes(g, nrhs, params->mode)) {
+  if (work_bytes < full_native_bytes(g, nrhs, params->mode)) {
     set_last_error("cg_solve_full: workspace smaller than asq_full_workspace_bytes()");
     return ASQ_ENOMEM;
   }
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t n = (size_t)6 * g->geom.half;  // doubles per column and parity
-  const size_t cg_bytes = batch_bytes(g, nrhs, params->mode, false);
+  const size_t cg_bytes = solve_bytes(g, nrhs, params->mode);
   double* bp = (double*)((char*)work_dev + cg_bytes);  // b', later D x
   double* parts = (double*)((char*)bp + align_up((size_t)nrhs * n * sizeof(double), 256));
   const double* b_e = b_dev;
@@ -123,7 +123,7 @@ extern "C" int cg_solve_full(const asq_gauge* g, int nrhs, const double* masses,
   int rc;
 
   // b' = 2m b_e - D_eo b_o
-  if ((rc = asqtad_dslash_eo(g, 0, ASQ_F64, nrhs, b_o, bp, s))) return rc;
+  if ((rc = dslash_run("cg_solve_full", g, 0, ASQ_F64, nrhs, b_o, bp, -1, false, s))) return rc;
   for (int c = 0; c < nrhs; ++c)
     if ((rc = combine(bp + c * n, b_e + c * n, bp + c * n, n, 2.0 * masses[c], -1.0, s))) return rc;
   // per-column even tolerance from |b| and |b'|
@@ -141,20 +141,20 @@ extern "C" int cg_solve_full(const asq_gauge* g, int nrhs, const double* masses,
   rc = solve_batch(g, nrhs, masses, tols.data(), bp, x_e, work_dev, cg_bytes, &p, stats, hip_stream);
   if (rc != ASQ_OK && rc != ASQ_ENOCONV) return rc;
   // x_o = (b_o - D_oe x_e) / (2m)
-  if ((rc = asqtad_dslash_eo(g, 1, ASQ_F64, nrhs, x_e, bp, s))) return rc;
+  if ((rc = dslash_run("cg_solve_full", g, 1, ASQ_F64, nrhs, x_e, bp, -1, false, s))) return rc;
   for (int c = 0; c < nrhs; ++c) {
     const double inv = 0.5 / masses[c];
     if ((rc = combine(x_o + c * n, b_o + c * n, bp + c * n, n, inv, -inv, s))) return rc;
   }
   // |b - M x| / |b| in FP64: even part b_e - 2m x_e - D_eo x_o, odd part b_o - 2m x_o - D_oe x_e
   std::vector<double> r2(nrhs, 0.0);
-  if ((rc = asqtad_dslash_eo(g, 0, ASQ_F64, nrhs, x_o, bp, s))) return rc;
+  if ((rc = dslash_run("cg_solve_full", g, 0, ASQ_F64, nrhs, x_o, bp, -1, false, s))) return rc;
   for (int c = 0; c < nrhs; ++c) {
     double v;
     if ((rc = resid2(b_e + c * n, x_e + c * n, bp + c * n, n, 2.0 * masses[c], parts, hp, &v, s))) return rc;
     r2[c] += v;
   }
-  if ((rc = asqtad_dslash_eo(g, 1, ASQ_F64, nrhs, x_e, bp, s))) return rc;
+  if ((rc = dslash_run("cg_solve_full", g, 1, ASQ_F64, nrhs, x_e, bp, -1, false, s))) return rc;
   int worst = ASQ_OK;
   for (int c = 0; c < nrhs; ++c) {
     double v;

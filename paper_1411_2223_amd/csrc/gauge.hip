@@ -5,6 +5,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <string>
+
 #include "asq_internal.h"
 
 namespace asq {
@@ -15,6 +18,7 @@ size_t link_slot_bytes(int kind) {
     case LINK_F32_R18: return 18 * sizeof(float);
     case LINK_F32_R12: return 12 * sizeof(float);
     case LINK_I16_R12: return 12 * sizeof(short);
+    case LINK_F64_F32: return 0;  // reads the FP64 tier
   }
   return 0;
 }
@@ -23,6 +27,7 @@ namespace {
 
 struct ImportArgs {
   Geom g;
+  long lex0, nsites;  // the canonical sites [lex0, lex0 + nsites) held at fat, lng
   const double* fat;
   const double* lng;
   double2* l64;   // LINK_F64_R18 or nullptr
@@ -42,9 +47,8 @@ __device__ inline short q16(double v) {
 // One thread per (site, slot); slot 0..3 fat x,y,z,t, 4..7 long x,y,z,t.
 __global__ void __launch_bounds__(256) import_kernel(const ImportArgs a) {
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long V = 2L * a.g.half;
-  if (gid >= V * 8) return;
-  const long lex = gid >> 3;
+  if (gid >= a.nsites * 8) return;
+  const long lex = a.lex0 + (gid >> 3);
   const int slot = (int)(gid & 7);
   const int mu = slot & 3;
   const bool is_long = slot >= 4;
@@ -65,7 +69,7 @@ __global__ void __launch_bounds__(256) import_kernel(const ImportArgs a) {
   const int bc = (mu == 3 && t + hop >= a.g.T) ? -1 : 1;
   const double sign = (double)(eta * bc);
 
-  const double* src = (is_long ? a.lng : a.fat) + (lex * 4 + mu) * 18;
+  const double* src = (is_long ? a.lng : a.fat) + ((lex - a.lex0) * 4 + mu) * 18;
   double u[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) u[k] = src[k];
@@ -152,8 +156,16 @@ bool valid_desc(const asq_gauge_desc* d) {
   return true;
 }
 
-// Offsets of each kept tier inside the storage; returns the total bytes.
-size_t layout(const asq_gauge_desc* d, size_t off[LINK_KINDS]) {
+// Sites of canonical host links staged per copy by asq_gauge_create: at most
+// 16 MB of FP64 fat and long links (1152 bytes per site).
+long stage_sites(const asq_gauge_desc* d) {
+  const long V = (long)d->dims[0] * d->dims[1] * d->dims[2] * d->dims[3];
+  return std::min(V, (long)((16u << 20) / 1152));
+}
+
+// Offsets of each kept tier inside the storage, then the staging area of
+// asq_gauge_create and a flag word; returns the total bytes.
+size_t layout(const asq_gauge_desc* d, size_t off[LINK_KINDS], size_t* stage_off = nullptr) {
   const long half = (long)d->dims[0] * d->dims[1] * d->dims[2] * d->dims[3] / 2;
   size_t total = 0;
   for (int k = 0; k < LINK_KINDS; ++k) off[k] = (size_t)-1;
@@ -164,6 +176,8 @@ size_t layout(const asq_gauge_desc* d, size_t off[LINK_KINDS]) {
   if (d->prec_mask & (1 << ASQ_F64)) take(LINK_F64_R18);
   if (d->prec_mask & (1 << ASQ_F32)) take(d->recon == 12 ? LINK_F32_R12 : LINK_F32_R18);
   if (d->prec_mask & (1 << ASQ_F16)) take(LINK_I16_R12);
+  if (stage_off) *stage_off = total;
+  total = align_up(total + (size_t)stage_sites(d) * 1152, 256);
   return total + 256;  // flag word
 }
 
@@ -205,26 +219,29 @@ extern "C" size_t asq_gauge_bytes(const asq_gauge_desc* desc) {
   return layout(desc, off);
 }
 
-extern "C" int asq_gauge_create(const asq_gauge_desc* desc, const double* fat_dev, const double* long_dev,
-                                void* storage_dev, size_t storage_bytes, void* hip_stream, asq_gauge** out) {
+// Import canonical links into a new handle.  host: fat/lng are host pointers,
+// copied through the staging area of the storage a chunk of sites at a time;
+// otherwise device pointers read in place.
+static int gauge_import(const char* who, const asq_gauge_desc* desc, const double* fat, const double* lng,
+                        bool host, void* storage_dev, size_t storage_bytes, void* hip_stream, asq_gauge** out) {
   if (!out) return ASQ_EINVAL;
   *out = nullptr;
   if (!valid_desc(desc)) {
-    set_last_error("asq_gauge_create: invalid description (extents even >= 4, recon 18|12, prec_mask, scales)");
+    set_last_error(std::string(who) + ": invalid description (extents even >= 4, recon 18|12, prec_mask, scales)");
     return ASQ_EINVAL;
   }
-  if (!fat_dev || !long_dev || !storage_dev) {
-    set_last_error("asq_gauge_create: null pointer");
+  if (!fat || !lng || !storage_dev) {
+    set_last_error(std::string(who) + ": null pointer");
     return ASQ_EINVAL;
   }
-  if (((uintptr_t)storage_dev & 255) || ((uintptr_t)fat_dev & 15) || ((uintptr_t)long_dev & 15)) {
-    set_last_error("asq_gauge_create: storage must be 256-byte aligned, links 16-byte aligned");
+  if (((uintptr_t)storage_dev & 255) || (!host && (((uintptr_t)fat & 15) || ((uintptr_t)lng & 15)))) {
+    set_last_error(std::string(who) + ": storage must be 256-byte aligned, device links 16-byte aligned");
     return ASQ_EINVAL;
   }
-  size_t off[LINK_KINDS];
-  const size_t need = layout(desc, off);
+  size_t off[LINK_KINDS], stage_off = 0;
+  const size_t need = layout(desc, off, &stage_off);
   if (storage_bytes < need) {
-    set_last_error("asq_gauge_create: storage smaller than asq_gauge_bytes()");
+    set_last_error(std::string(who) + ": storage smaller than asq_gauge_bytes()");
     return ASQ_ENOMEM;
   }
   hipStream_t s = (hipStream_t)hip_stream;
@@ -236,19 +253,19 @@ extern "C" int asq_gauge_create(const asq_gauge_desc* desc, const double* fat_de
   g->nblk = (g->geom.half + kBlock - 1) / kBlock;
   if (hipGetDevice(&g->device) != hipSuccess) {
     delete g;
-    set_last_error("asq_gauge_create: no current HIP device");
+    set_last_error(std::string(who) + ": no current HIP device");
     return ASQ_EHIP;
   }
   char* b = (char*)storage_dev;
   for (int k = 0; k < LINK_KINDS; ++k) g->links[k] = off[k] == (size_t)-1 ? nullptr : b + off[k];
-  g->sloppy_link32 = desc->recon == 12 ? LINK_F32_R12 : LINK_F32_R18;
+  g->links[LINK_F64_F32] = g->links[LINK_F64_R18];  // no copy: converted on load
+  if (desc->prec_mask & (1 << ASQ_F32)) g->sloppy_link32 = desc->recon == 12 ? LINK_F32_R12 : LINK_F32_R18;
+  else g->sloppy_link32 = LINK_F64_F32;
   g->sloppy_link16 = g->links[LINK_I16_R12] ? LINK_I16_R12 : g->sloppy_link32;
   int* flag = (int*)(b + need - 256);
 
   ImportArgs a;
   a.g = g->geom;
-  a.fat = fat_dev;
-  a.lng = long_dev;
   a.l64 = (double2*)g->links[LINK_F64_R18];
   a.l32f = (float2*)g->links[LINK_F32_R18];
   a.l32c = (float4*)g->links[LINK_F32_R12];
@@ -257,11 +274,30 @@ extern "C" int asq_gauge_create(const asq_gauge_desc* desc, const double* fat_de
   a.long_scale = desc->long_scale;
   a.bad = flag;
   int bad = 0;
+  const long V = 2L * g->geom.half;
+  const long chunk = host ? stage_sites(desc) : V;
+  double* st_fat = (double*)(b + stage_off);
+  double* st_lng = st_fat + (size_t)chunk * 72;
   hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
-  const long nthreads = 2L * g->geom.half * 8;
-  if (e == hipSuccess) {
-    import_kernel<<<(unsigned)((nthreads + 255) / 256), 256, 0, s>>>(a);
-    e = hipGetLastError();
+  for (long lex0 = 0; lex0 < V && e == hipSuccess; lex0 += chunk) {
+    const long n = std::min(chunk, V - lex0);
+    a.lex0 = lex0;
+    a.nsites = n;
+    if (host) {
+      // the previous chunk's import has read the staging area when this copy runs (same stream)
+      e = hipMemcpyAsync(st_fat, fat + (size_t)lex0 * 72, (size_t)n * 576, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(st_lng, lng + (size_t)lex0 * 72, (size_t)n * 576,
+                                              hipMemcpyHostToDevice, s);
+      a.fat = st_fat;
+      a.lng = st_lng;
+    } else {
+      a.fat = fat + (size_t)lex0 * 72;
+      a.lng = lng + (size_t)lex0 * 72;
+    }
+    if (e == hipSuccess) {
+      import_kernel<<<(unsigned)((n * 8 + 255) / 256), 256, 0, s>>>(a);
+      e = hipGetLastError();
+    }
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -271,12 +307,25 @@ extern "C" int asq_gauge_create(const asq_gauge_desc* desc, const double* fat_de
     return ASQ_EHIP;
   }
   if (bad) {
-    set_last_error("asq_gauge_create: link/scale is not SU(3) to 1e-6; 12-real or 16-bit copies need SU(3) links");
+    set_last_error(std::string(who) +
+                   ": link/scale is not SU(3) to 1e-6; 12-real or 16-bit copies need SU(3) links");
     delete g;
     return ASQ_ENOTSU3;
   }
   *out = g;
   return ASQ_OK;
+}
+
+extern "C" int asq_gauge_create(const asq_gauge_desc* desc, const double* fat_host, const double* long_host,
+                                void* storage_dev, size_t storage_bytes, void* hip_stream, asq_gauge** out) {
+  return gauge_import("asq_gauge_create", desc, fat_host, long_host, true, storage_dev, storage_bytes, hip_stream,
+                      out);
+}
+
+extern "C" int asq_gauge_create_device(const asq_gauge_desc* desc, const double* fat_dev, const double* long_dev,
+                                       void* storage_dev, size_t storage_bytes, void* hip_stream, asq_gauge** out) {
+  return gauge_import("asq_gauge_create_device", desc, fat_dev, long_dev, false, storage_dev, storage_bytes,
+                      hip_stream, out);
 }
 
 extern "C" int asq_gauge_destroy(asq_gauge* g) {

@@ -148,18 +148,18 @@ int enqueue_ms_block(const Batch& B, ShiftState* sh, int nsh, float* xs, float* 
 
 using namespace asq;
 
-extern "C" size_t asq_multishift_workspace_bytes(const asq_gauge* g, int nsrc, int nmass, int mode) {
+size_t asq::multishift_native_bytes(const asq_gauge* g, int nsrc, int nmass, int mode) {
   if (!g || nsrc <= 0 || nmass <= 0 || mode < ASQ_MODE_F64 || mode > ASQ_MODE_MIXED16) return 0;
   const size_t half = (size_t)g->geom.half;
   const int ncol = nsrc * nmass;
   const size_t phase1 = batch_bytes(g, nsrc, ASQ_MODE_MIXED32, false) + shift_bytes(g, nsrc * (nmass - 1));
-  const size_t phase2 = batch_bytes(g, ncol, mode, false);
+  const size_t phase2 = solve_bytes(g, ncol, mode);
   return std::max(phase1, phase2) + align_up((size_t)ncol * half * 48, 256);
 }
 
-extern "C" int cg_solve_multishift(const asq_gauge* g, int nsrc, int nmass, const double* masses, const double* b_dev,
-                                   double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
-                                   asq_cg_stats* stats, void* hip_stream) {
+int asq::solve_multishift_native(const asq_gauge* g, int nsrc, int nmass, const double* masses,
+                                 const double* b_dev, double* x_dev, void* work_dev, size_t work_bytes,
+                                 const asq_cg_params* params, asq_cg_stats* stats, void* hip_stream) {
   if (!g || nsrc <= 0 || nmass <= 0 || !masses || !b_dev || !x_dev || !work_dev || !stats || !params) {
     set_last_error("cg_solve_multishift: null pointer, nsrc <= 0 or nmass <= 0");
     return ASQ_EINVAL;
@@ -183,7 +183,7 @@ extern "C" int cg_solve_multishift(const asq_gauge* g, int nsrc, int nmass, cons
     set_last_error("cg_solve_multishift: b, x and the workspace must not overlap");
     return ASQ_EINVAL;
   }
-  if (work_bytes < asq_multishift_workspace_bytes(g, nsrc, nmass, params->mode)) {
+  if (work_bytes < multishift_native_bytes(g, nsrc, nmass, params->mode)) {
     set_last_error("cg_solve_multishift: workspace smaller than asq_multishift_workspace_bytes()");
     return ASQ_ENOMEM;
   }
@@ -193,7 +193,7 @@ extern "C" int cg_solve_multishift(const asq_gauge* g, int nsrc, int nmass, cons
   const int ncol = nsrc * nmass;
   const int j0 = (int)(std::min_element(masses, masses + nmass) - masses);  // the base (smallest) shift
   const int nsh = nsrc * (nmass - 1);
-  const size_t region = asq_multishift_workspace_bytes(g, nsrc, nmass, params->mode) -
+  const size_t region = multishift_native_bytes(g, nsrc, nmass, params->mode) -
                         align_up((size_t)ncol * half * 48, 256);
   double* brep = (double*)((char*)work_dev + region);  // b of every (mass, source) column
 

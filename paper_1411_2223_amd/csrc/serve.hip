@@ -11,6 +11,8 @@
 // reliable updates at multiples of poll_iters of its own iterations), so a
 // request gives the same result alone and in the mix.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -23,6 +25,7 @@
 #include <mutex>
 #include <set>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "asq_batch.h"
@@ -43,6 +46,7 @@ struct Request {
   const double* b = nullptr;
   double* x = nullptr;
   asq_cg_params params{};
+  hipEvent_t ready_ev = nullptr;  // recorded on the submitter's stream: b is ready after it
   clk::time_point t_submit, t_done;
   int state = 0;  // 0 queued, 1 running, 2 finishing (copy-out in flight), 3 done
   int rc = ASQ_OK;
@@ -52,6 +56,9 @@ struct Request {
   hipEvent_t done_ev = nullptr;
   std::vector<asq_cg_stats> stats;
   std::vector<char> col_done;
+  ~Request() {
+    if (ready_ev) (void)hipEventDestroy(ready_ev);
+  }
 };
 
 struct Run {
@@ -133,6 +140,7 @@ struct asq_server {
   std::vector<const asq_gauge*> gauges;
   std::list<std::unique_ptr<Run>> runs;
   uint64_t next_id = 1;
+  size_t max_queue = 1 << 16;  // queued requests before serve_submit answers ASQ_EAGAIN
   bool stop = false;
   int error = ASQ_OK;
   std::thread worker;
@@ -140,8 +148,6 @@ struct asq_server {
 
 namespace asq {
 namespace {
-
-constexpr size_t kMaxQueue = 1 << 16;
 
 // Teardown: errors are ignored, each handle is released whatever happened to
 // the stream.
@@ -166,7 +172,25 @@ int run_capacity(const asq_server* S, const asq_gauge* g) {
   return (int)std::min(4096L, (long)S->max_cols * ratio);
 }
 
-// Create a run for (gauge, mode) if the arena and the stream budget allow it.
+int norm_poll(const asq_cg_params& p) { return p.poll_iters > 0 ? p.poll_iters : 8; }
+
+// Whether a request may join a run: same field, precision mode and block
+// shape (iterations per block and graph replay), so that its reliable updates
+// fall on the iterations they would fall on in a solve of its own.
+bool run_matches(const Run* r, const asq_gauge* g, const asq_cg_params& p) {
+  return r->g == g && r->mode == p.mode && r->poll == norm_poll(p) && r->use_graph == (p.use_graph != 0);
+}
+
+// The key runs are grouped by: field, mode, iterations per block, graph replay.
+using RunKey = std::tuple<const asq_gauge*, int, int, int>;
+RunKey key_of(const Run* r) { return RunKey(r->g, r->mode, r->poll, r->use_graph ? 1 : 0); }
+RunKey key_of(const asq_gauge* g, const asq_cg_params& p) {
+  return RunKey(g, p.mode, norm_poll(p), p.use_graph != 0 ? 1 : 0);
+}
+
+// Create a run for (gauge, mode, block shape) if the arena and the stream
+// budget allow it.  Its launch variants come from the tuner's cache (filled
+// when the field was registered); nothing is timed here.
 Run* make_run(asq_server* S, const asq_gauge* g, const asq_cg_params& p) {
   if ((int)S->runs.size() >= S->max_streams) return nullptr;
   int cap = run_capacity(S, g);
@@ -181,7 +205,7 @@ Run* make_run(asq_server* S, const asq_gauge* g, const asq_cg_params& p) {
   r->g = g;
   r->mode = p.mode;
   r->cap = cap;
-  r->poll = p.poll_iters > 0 ? p.poll_iters : 8;
+  r->poll = norm_poll(p);
   r->use_graph = p.use_graph != 0;
   r->off = off;
   r->bytes = need;
@@ -197,7 +221,6 @@ Run* make_run(asq_server* S, const asq_gauge* g, const asq_cg_params& p) {
     ok = hipMemcpyAsync(r->B.st, r->staging, r->cap * sizeof(ColState), hipMemcpyHostToDevice, r->stream) ==
          hipSuccess;
   }
-  ok = ok && batch_tune(r->B, r->stream) == ASQ_OK;
   if (ok && r->use_graph) ok = capture_block(r->B, r->poll, r->stream, &r->exec) == ASQ_OK;
   ok = ok && hipStreamSynchronize(r->stream) == hipSuccess;
   if (!ok) {
@@ -224,7 +247,7 @@ bool admit(asq_server* S, Request* q) {
   Run* run = nullptr;
   int c0 = -1;
   for (auto& r : S->runs)
-    if (r->g == g && r->mode == q->params.mode && (c0 = free_slots(r.get(), q->nrhs)) >= 0) {
+    if (run_matches(r.get(), g, q->params) && (c0 = free_slots(r.get(), q->nrhs)) >= 0) {
       run = r.get();
       break;
     }
@@ -245,8 +268,9 @@ bool admit(asq_server* S, Request* q) {
   init_states(tmp, q->masses.data(), &p, run->staging + c0, nullptr);
   bool ok = hipMemcpyAsync(B.st + c0, run->staging + c0, q->nrhs * sizeof(ColState), hipMemcpyHostToDevice, s) ==
             hipSuccess;
-  ok = ok && hipMemcpyAsync(B.b + (size_t)c0 * half * 6, q->b, (size_t)q->nrhs * half * 48,
-                            hipMemcpyDeviceToDevice, s) == hipSuccess;
+  // b as the submitter's stream left it, relayout into the slots' native layout
+  ok = ok && hipStreamWaitEvent(s, q->ready_ev, 0) == hipSuccess;
+  ok = ok && relayout(VEC_F64, true, q->nrhs, (int)half, q->b, B.b + (size_t)c0 * half * 6, s) == ASQ_OK;
   ok = ok && enqueue_init(B, c0, q->nrhs, s) == ASQ_OK;
   if (!ok) {
     q->rc = ASQ_EHIP;
@@ -315,8 +339,8 @@ void harvest(asq_server* S, Run* r) {
     if (worst != ASQ_OK && (q->rc == ASQ_OK || worst == ASQ_ENAN)) q->rc = worst;
     q->col_done[k] = 1;
     if (--q->cols_left == 0) {
-      bool ok = hipMemcpyAsync(q->x, r->B.x + (size_t)q->slot0 * half * 6, (size_t)q->nrhs * half * 48,
-                               hipMemcpyDeviceToDevice, r->stream) == hipSuccess;
+      bool ok = relayout(VEC_F64, false, q->nrhs, (int)half, r->B.x + (size_t)q->slot0 * half * 6, q->x,
+                         r->stream) == ASQ_OK;
       ok = ok && hipEventCreateWithFlags(&q->done_ev, hipEventDisableTiming) == hipSuccess;
       ok = ok && hipEventRecord(q->done_ev, r->stream) == hipSuccess;
       for (int j = 0; j < q->nrhs; ++j) r->owner[q->slot0 + j] = nullptr;
@@ -368,17 +392,17 @@ int used_slots(const Run* r) {
 // field that holds two or more runs give one up (the least occupied stops
 // taking columns and is destroyed once its columns are done), so that one busy
 // field cannot starve the others.  At most one run drains at a time.
-void make_room(asq_server* S, const asq_gauge* g) {
+void make_room(asq_server* S, const RunKey& k) {
   if ((int)S->runs.size() < S->max_streams) return;
-  std::map<const asq_gauge*, int> per_field;
+  std::map<RunKey, int> per_field;
   for (auto& r : S->runs) {
     if (r->draining) return;
-    per_field[r->g] += 1;
+    per_field[key_of(r.get())] += 1;
   }
-  if (per_field.count(g)) return;
+  if (per_field.count(k)) return;
   Run* victim = nullptr;
   for (auto& r : S->runs)
-    if (per_field[r->g] >= 2 && (!victim || used_slots(r.get()) < used_slots(victim))) victim = r.get();
+    if (per_field[key_of(r.get())] >= 2 && (!victim || used_slots(r.get()) < used_slots(victim))) victim = r.get();
   if (victim) victim->draining = true;
 }
 
@@ -394,10 +418,10 @@ void worker_main(asq_server* S) {
       bool blocked_by_flight = false;
       const asq_gauge* g = S->gauges[q->gauge_id];
       for (auto& r : S->runs)
-        if (r->g == g && r->mode == q->params.mode && r->in_flight && free_slots(r.get(), q->nrhs) >= 0)
+        if (run_matches(r.get(), g, q->params) && r->in_flight && free_slots(r.get(), q->nrhs) >= 0)
           blocked_by_flight = true;
       if (!blocked_by_flight) placed = admit(S, q);
-      if (!placed && !blocked_by_flight) make_room(S, g);
+      if (!placed && !blocked_by_flight) make_room(S, key_of(g, q->params));
       if (placed) it = S->queue.erase(it);
       else ++it;
     }
@@ -412,8 +436,7 @@ void worker_main(asq_server* S) {
     bool need_run = false;
     for (Request* q : S->queue) {
       bool has = false;
-      for (auto& r : S->runs)
-        has |= !r->draining && r->g == S->gauges[q->gauge_id] && r->mode == q->params.mode;
+      for (auto& r : S->runs) has |= !r->draining && run_matches(r.get(), S->gauges[q->gauge_id], q->params);
       need_run |= !has;
     }
     if (need_run) {
@@ -421,14 +444,14 @@ void worker_main(asq_server* S) {
       // queued), a field's only run is kept even when idle (small fields would
       // otherwise lose their stream between requests); streams for a new field
       // come from drained extra runs.
-      std::set<std::pair<const asq_gauge*, int>> fields;
-      for (auto& r : S->runs) fields.insert({r->g, r->mode});
-      for (Request* q : S->queue) fields.insert({S->gauges[q->gauge_id], q->params.mode});
+      std::set<RunKey> fields;
+      for (auto& r : S->runs) fields.insert(key_of(r.get()));
+      for (Request* q : S->queue) fields.insert(key_of(S->gauges[q->gauge_id], q->params));
       const bool keep_last = (int)fields.size() <= S->max_streams;
       for (auto it = S->runs.begin(); it != S->runs.end();) {
         Run* r = it->get();
         int same = 0;
-        for (auto& o : S->runs) same += !o->draining && o->g == r->g && o->mode == r->mode;
+        for (auto& o : S->runs) same += !o->draining && key_of(o.get()) == key_of(r);
         const bool last_of_field = !r->draining && same == 1;
         if (!r->in_flight && run_idle(r) && !(keep_last && last_of_field)) {
           bool copies_pending = false;
@@ -485,10 +508,54 @@ extern "C" int serve_create(void* arena_dev, size_t arena_bytes, int max_streams
   S->max_streams = max_streams;
   S->max_cols = max_cols;
   S->device = device;
+  // ASQ_SERVE_MAX_QUEUE=<n>: a shorter queue (tests force ASQ_EAGAIN with it)
+  if (const char* e = getenv("ASQ_SERVE_MAX_QUEUE")) {
+    const long n = atol(e);
+    if (n > 0) S->max_queue = (size_t)n;
+  }
   S->worker = std::thread(worker_main, S);
   *out = S;
   return ASQ_OK;
 }
+
+namespace asq {
+namespace {
+
+// Tune the Dslash launches of every run shape the registered fields can get
+// (each precision mode a field keeps links for, at its run width and at the
+// fallback width), on scratch taken from the arena, while no run exists, so
+// the timings see an idle device.  Runs later take the tuned variants from the
+// tuner's cache without timing anything.  Called with S->mu held.
+void tune_fields(asq_server* S) {
+  if (!S->runs.empty()) {
+    if (log_enabled()) fprintf(stderr, "[asq] serve: runs exist, launch variants not tuned\n");
+    return;
+  }
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+  for (const asq_gauge* g : S->gauges)
+    for (int mode = ASQ_MODE_F64; mode <= ASQ_MODE_MIXED16; ++mode) {
+      asq_cg_params p{};
+      p.mode = mode;
+      p.tol = 1;
+      p.maxiter = 1;
+      if (check_params(g, &p)) continue;  // the field keeps no links for this mode
+      for (int w : {run_capacity(S, g), S->max_cols}) {
+        const size_t need = batch_bytes(g, w, mode, true);
+        size_t off = 0;
+        if (!S->arena.alloc(need, &off)) continue;
+        Batch B;
+        if (batch_carve(B, g, w, mode, S->arena.base + off, need, nullptr, nullptr) == ASQ_OK)
+          (void)batch_tune(B, st);
+        (void)hipStreamSynchronize(st);
+        S->arena.release(off, need);
+      }
+    }
+  (void)hipStreamDestroy(st);
+}
+
+}  // namespace
+}  // namespace asq
 
 extern "C" int serve_register_gauge(asq_server* S, const asq_gauge* g, int* gauge_id) {
   if (!S || !g || !gauge_id) return ASQ_EINVAL;
@@ -499,11 +566,12 @@ extern "C" int serve_register_gauge(asq_server* S, const asq_gauge* g, int* gaug
   std::lock_guard<std::mutex> lk(S->mu);
   S->gauges.push_back(g);
   *gauge_id = (int)S->gauges.size() - 1;
+  tune_fields(S);
   return ASQ_OK;
 }
 
 extern "C" int serve_submit(asq_server* S, int gauge_id, int nrhs, const double* masses, const double* b_dev,
-                            double* x_dev, const asq_cg_params* params, uint64_t* ticket) {
+                            double* x_dev, const asq_cg_params* params, uint64_t* ticket, void* hip_stream) {
   if (!S || !masses || !b_dev || !x_dev || !params || !ticket || nrhs <= 0) return ASQ_EINVAL;
   std::unique_lock<std::mutex> lk(S->mu);
   if (gauge_id < 0 || gauge_id >= (int)S->gauges.size()) return ASQ_EINVAL;
@@ -521,8 +589,17 @@ extern "C" int serve_submit(asq_server* S, int gauge_id, int nrhs, const double*
     set_last_error("serve_submit: request can never fit (nrhs > max_cols or a batch exceeds the arena)");
     return ASQ_ENOMEM;
   }
-  if (S->queue.size() >= kMaxQueue) return ASQ_EAGAIN;
+  if (S->queue.size() >= S->max_queue) {
+    set_last_error("serve_submit: queue full");
+    return ASQ_EAGAIN;
+  }
   std::unique_ptr<Request> q(new Request());
+  // the server reads b after the work enqueued so far on the submitter's stream
+  if (hipEventCreateWithFlags(&q->ready_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(q->ready_ev, (hipStream_t)hip_stream) != hipSuccess) {
+    set_last_error("serve_submit: could not record an event on the stream");
+    return ASQ_EHIP;
+  }
   q->id = S->next_id++;
   q->gauge_id = gauge_id;
   q->nrhs = nrhs;

@@ -20,6 +20,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <mutex>
@@ -74,6 +75,24 @@ size_t batch_bytes(const asq_gauge* g, int ncol, int mode, bool with_bx) {
   if (mode != ASQ_MODE_F64) n += align_up((size_t)ncol * half * 24, 256);  // x_s
   if (with_bx) n += 2 * align_up((size_t)ncol * half * 48, 256);         // b, x
   return n;
+}
+
+int next_mode(int mode) {
+  return mode == ASQ_MODE_MIXED16 ? ASQ_MODE_MIXED32 : (mode == ASQ_MODE_MIXED32 ? ASQ_MODE_F64 : -1);
+}
+
+static size_t chain_bytes(const asq_gauge* g, int ncol, int mode) {
+  size_t n = 0;
+  for (int m = mode; m >= 0; m = next_mode(m)) n = std::max(n, batch_bytes(g, ncol, m, false));
+  return n;
+}
+
+// The gathered b and x of each escalation level sit at the end of the
+// workspace, the later levels' below the earlier ones.
+size_t solve_bytes(const asq_gauge* g, int ncol, int mode) {
+  int levels = 0;
+  for (int m = next_mode(mode); m >= 0; m = next_mode(m)) ++levels;
+  return chain_bytes(g, ncol, mode) + levels * 2 * align_up((size_t)ncol * g->geom.half * 48, 256);
 }
 
 int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, size_t bytes, const double* b,
@@ -382,6 +401,8 @@ void fill_stats(const Batch& B, const ColState* S, double seconds, asq_cg_stats*
     o.true_resid = S[c].bb > 0 ? sqrt(S[c].true_rr / S[c].bb) : 0.0;
     o.seconds = seconds;
     o.gflops = seconds > 0 ? flops / seconds * 1e-9 : 0.0;
+    o.escalations = 0;
+    o.final_mode = B.mode;
     int st = S[c].status;
     if (st == 0 && !S[c].converged) st = ASQ_ENOCONV;
     o.status = st;
@@ -412,20 +433,25 @@ void init_states(const Batch& B, const double* masses, const asq_cg_params* p, C
   }
 }
 
+// Stagnation rule of the mixed tiers: ASQ_STALL_UPDATES (default 3) reliable
+// updates in a row without the true residual falling by ASQ_STALL_DROP (default
+// 10) hand the column to the next tier; 0 updates switches it off.  FP64 is the
+// last tier and never hands on.
+static void set_stall(ColState* host, int ncol, int mode) {
+  const char* eu = getenv("ASQ_STALL_UPDATES");
+  const int updates = eu && *eu ? atoi(eu) : 3;
+  const char* ed = getenv("ASQ_STALL_DROP");
+  double drop = ed && *ed ? atof(ed) : 10.0;
+  if (!(drop > 1.0) || !isfinite(drop)) drop = 10.0;
+  for (int c = 0; c < ncol; ++c) {
+    host[c].stall_updates = next_mode(mode) >= 0 ? std::max(0, updates) : 0;
+    host[c].stall_fac = 1.0 / (drop * drop);  // on |r|^2
+  }
+}
+
 }  // namespace asq
 
 using namespace asq;
-
-extern "C" size_t asq_workspace_bytes(const asq_gauge* g, int nrhs, int mode) {
-  if (!g || nrhs <= 0 || mode < ASQ_MODE_F64 || mode > ASQ_MODE_MIXED16) return 0;
-  return batch_bytes(g, nrhs, mode, false);
-}
-
-extern "C" int cg_solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev,
-                              double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
-                              asq_cg_stats* stats, void* hip_stream) {
-  return asq::solve_batch(g, nrhs, masses, nullptr, b_dev, x_dev, work_dev, work_bytes, params, stats, hip_stream);
-}
 
 int asq::solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double* tols, const double* b_dev,
                      double* x_dev, void* work_dev, size_t work_bytes, const asq_cg_params* params,
@@ -466,6 +492,7 @@ int asq::solve_batch(const asq_gauge* g, int nrhs, const double* masses, const d
   if ((rc = H.ensure((size_t)nrhs))) return rc;
   ColState* mirror[2] = {H.pinned, H.pinned + nrhs};
   init_states(B, masses, params, mirror[0], tols);
+  set_stall(mirror[0], nrhs, params->mode);
   ASQ_HIP_TRY(hipMemcpyAsync(B.st, mirror[0], nrhs * sizeof(ColState), hipMemcpyHostToDevice, s));
   if ((rc = guess ? enqueue_init_guess(B, s) : enqueue_init(B, 0, nrhs, s))) return rc;
   // the mirror is reused below: make sure the upload has consumed it
@@ -507,24 +534,99 @@ int asq::solve_batch(const asq_gauge* g, int nrhs, const double* masses, const d
   }
   ASQ_HIP_TRY(hipStreamSynchronize(s));
   if (exec) (void)hipGraphExecDestroy(exec);
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int worst = ASQ_OK;
-  fill_stats(B, mirror[last], secs, stats, &worst);
+  const ColState* fin = mirror[last];
+  std::vector<int> esc;
+  for (int c = 0; c < nrhs; ++c)
+    if (fin[c].escalate) esc.push_back(c);
+  double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_stats(B, fin, secs, stats, &worst);
+  if (!esc.empty()) {
+    // Columns whose true residual stalled continue from their x in the next tier.
+    // The states mirror is reused by the nested solve: copy what is needed first.
+    std::vector<double> m_e, tol_e;
+    std::vector<int> it_e, ru_e;
+    for (int c : esc) {
+      m_e.push_back(masses[c]);
+      tol_e.push_back(tols ? tols[c] : params->tol);
+      it_e.push_back(fin[c].iters);
+      ru_e.push_back(fin[c].n_ru);
+    }
+    if ((rc = escalate(g, esc, m_e, tol_e, it_e, ru_e, b_dev, x_dev, work_dev, work_bytes, params, stats,
+                       hip_stream)))
+      return rc;
+    worst = ASQ_OK;
+    for (int c = 0; c < nrhs; ++c) {
+      const int st = stats[c].status;
+      if (st == ASQ_ENAN) worst = ASQ_ENAN;
+      else if (st == ASQ_ENOCONV && worst == ASQ_OK) worst = ASQ_ENOCONV;
+    }
+    secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int c = 0; c < nrhs; ++c) stats[c].seconds = secs;
+  }
   if (log_enabled())
-    fprintf(stderr, "[asq] cg_solve_batch ncol=%d mode=%d iters0=%d ru0=%d resid0=%.3e %.3f s\n", nrhs,
-            params->mode, stats[0].iters, stats[0].reliable_updates, stats[0].true_resid, secs);
+    fprintf(stderr, "[asq] cg_solve_batch ncol=%d mode=%d iters0=%d ru0=%d resid0=%.3e esc=%zu %.3f s\n", nrhs,
+            params->mode, stats[0].iters, stats[0].reliable_updates, stats[0].true_resid, esc.size(), secs);
   return worst;
 }
 
-extern "C" int cg_solve(const asq_gauge* g, double mass, const double* b_dev, double* x_dev, void* work_dev,
-                        size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats, void* hip_stream) {
-  return cg_solve_batch(g, 1, &mass, b_dev, x_dev, work_dev, work_bytes, params, stats, hip_stream);
+// The stalled columns `cols` of a batch continue in the next precision tier:
+// their b and x are gathered after the batch region of the workspace, solved
+// from x (FP64 residual first) by a nested solve_batch, and x is scattered
+// back.  Per-column counters add up; the nested solve may hand on again.
+int asq::escalate(const asq_gauge* g, const std::vector<int>& cols, const std::vector<double>& masses,
+                  const std::vector<double>& tols, const std::vector<int>& iters, const std::vector<int>& rus,
+                  const double* b_dev, double* x_dev, void* work_dev, size_t work_bytes,
+                  const asq_cg_params* params, asq_cg_stats* stats, void* hip_stream) {
+  const int k = (int)cols.size();
+  const int mode = next_mode(params->mode);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t vcol = (size_t)g->geom.half * 48;
+  // this level's gathered b and x take the end of the workspace; the nested solve
+  // (and its own escalations) the rest: solve_bytes(ncol, mode) covers every level
+  const size_t gather = 2 * align_up((size_t)k * vcol, 256);
+  if (work_bytes < gather || work_bytes - gather < solve_bytes(g, k, mode)) return ASQ_ENOMEM;
+  const size_t region = work_bytes - gather;
+  double* bk = (double*)((char*)work_dev + region);
+  double* xk = (double*)((char*)bk + align_up((size_t)k * vcol, 256));
+  for (int j = 0; j < k; ++j) {
+    ASQ_HIP_TRY(hipMemcpyAsync((char*)bk + j * vcol, (const char*)b_dev + cols[j] * vcol, vcol,
+                               hipMemcpyDeviceToDevice, s));
+    ASQ_HIP_TRY(hipMemcpyAsync((char*)xk + j * vcol, (const char*)x_dev + cols[j] * vcol, vcol,
+                               hipMemcpyDeviceToDevice, s));
+  }
+  asq_cg_params p = *params;
+  p.mode = mode;
+  int budget = params->maxiter;
+  for (int j = 0; j < k; ++j) budget = std::min(budget, std::max(1, params->maxiter - iters[j]));
+  p.maxiter = budget;
+  std::vector<asq_cg_stats> sub(k);
+  const int rc = solve_batch(g, k, masses.data(), tols.data(), bk, xk, work_dev, region, &p, sub.data(), hip_stream,
+                             true);
+  if (rc != ASQ_OK && rc != ASQ_ENOCONV && rc != ASQ_ENAN) return rc;
+  for (int j = 0; j < k; ++j)
+    ASQ_HIP_TRY(hipMemcpyAsync((char*)x_dev + cols[j] * vcol, (char*)xk + j * vcol, vcol, hipMemcpyDeviceToDevice,
+                               s));
+  ASQ_HIP_TRY(hipStreamSynchronize(s));
+  for (int j = 0; j < k; ++j) {
+    asq_cg_stats& o = stats[cols[j]];
+    const asq_cg_stats& t = sub[j];
+    o.iters = iters[j] + t.iters;
+    o.reliable_updates = rus[j] + t.reliable_updates;
+    o.converged = t.converged;
+    o.status = t.status;
+    o.true_resid = t.true_resid;
+    o.escalations = 1 + t.escalations;
+    o.final_mode = t.final_mode;
+  }
+  return ASQ_OK;
 }
 
-// Shared by asqtad_dslash_eo and asqtad_dslash_eo_variant: variant < 0 takes
-// the tuned launch variant.
-static int dslash_public(const char* who, const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
-                         void* out_dev, int variant, hipStream_t stream) {
+// Shared by asqtad_dslash_eo, asqtad_dslash_eo_variant and the solvers'
+// own FP64 operator calls: variant < 0 takes the tuned launch variant;
+// canonical selects the C ABI's layouts, else the solvers' native ones.
+int asq::dslash_run(const char* who, const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
+                    void* out_dev, int variant, bool canonical, hipStream_t stream) {
   if (!g || !in_dev || !out_dev || nrhs <= 0 || (out_parity != 0 && out_parity != 1)) {
     set_last_error(std::string(who) + ": null pointer, nrhs <= 0 or parity not 0/1");
     return ASQ_EINVAL;
@@ -571,13 +673,14 @@ static int dslash_public(const char* who, const asq_gauge* g, int out_parity, in
   static std::atomic<unsigned> calls{0};
   static const bool sweep = env_flag("ASQ_SWEEP", true);
   a.reverse = sweep && (calls.fetch_add(1, std::memory_order_relaxed) & 1) ? 1 : 0;
+  const int epi = canonical ? EPI_CANON : EPI_PLAIN;
   int rt = variant;
   if (variant < 0) {
-    const int rc0 = tune_dslash(g, link, vk, nrhs, in_dev, out_dev, stream);
+    const int rc0 = tune_dslash(g, link, vk, nrhs, in_dev, out_dev, stream, epi);
     if (rc0) return rc0;
-    rt = tuned_rtile(g, link, vk, vk, EPI_PLAIN, nrhs);
+    rt = tuned_rtile(g, link, vk, vk, epi, nrhs);
   }
-  const int rc = launch_dslash(link, vk, vk, EPI_PLAIN, rt, a, stream);
+  const int rc = launch_dslash(link, vk, vk, epi, rt, a, stream);
   if (rc == ASQ_EHIP) set_last_error(hipGetErrorString(hipGetLastError()));
   if (rc == ASQ_EINVAL) set_last_error(std::string(who) + ": launch variant not available for this tier");
   return rc;
@@ -585,7 +688,8 @@ static int dslash_public(const char* who, const asq_gauge* g, int out_parity, in
 
 extern "C" int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
                                 void* out_dev, void* hip_stream) {
-  return dslash_public("asqtad_dslash_eo", g, out_parity, prec, nrhs, in_dev, out_dev, -1, (hipStream_t)hip_stream);
+  return dslash_run("asqtad_dslash_eo", g, out_parity, prec, nrhs, in_dev, out_dev, -1, true,
+                    (hipStream_t)hip_stream);
 }
 
 extern "C" int asqtad_dslash_eo_variant(const asq_gauge* g, int out_parity, int prec, int nrhs, const void* in_dev,
@@ -594,8 +698,15 @@ extern "C" int asqtad_dslash_eo_variant(const asq_gauge* g, int out_parity, int 
     set_last_error("asqtad_dslash_eo_variant: variant must be >= 0");
     return ASQ_EINVAL;
   }
-  return dslash_public("asqtad_dslash_eo_variant", g, out_parity, prec, nrhs, in_dev, out_dev, variant,
-                       (hipStream_t)hip_stream);
+  const bool native = (variant & ASQ_VARIANT_NATIVE) != 0;
+  int v = variant & ~ASQ_VARIANT_NATIVE;
+  if (native && v == 0) v = -1;  // the tuned variant on native vectors
+  if (!native && (v & kMfmaBit)) {
+    set_last_error("asqtad_dslash_eo_variant: the matrix-core form takes the native layout only");
+    return ASQ_EINVAL;
+  }
+  return dslash_run("asqtad_dslash_eo_variant", g, out_parity, prec, nrhs, in_dev, out_dev, v, !native,
+                    (hipStream_t)hip_stream);
 }
 
 extern "C" const char* asq_strerror(int code) {

@@ -106,11 +106,14 @@ int tuned_rtile(const asq_gauge* g, int link, int in, int out, int epi, int ncol
 }
 
 // Time the PLAIN Dslash (the loop shared by every epilogue) for each tile on
-// in_buf -> out_buf and record the winner for `epis`.  Buffers are the
-// caller's: in_buf is only read, out_buf is scratch.
+// in_buf -> out_buf and record the winner for every epilogue; with
+// epi = EPI_CANON, time and record the public operator on the canonical
+// layouts instead.  Buffers are the caller's: in_buf is only read, out_buf is
+// scratch.  persist = false keeps the winners out of the ASQ_TUNE_CACHE file
+// (timings taken while other work may share the device).
 int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_buf, void* out_buf,
-                hipStream_t s) {
-  const std::string kp = key_of(g, link, in, in, EPI_PLAIN, ncol);
+                hipStream_t s, int epi_timed, bool persist) {
+  const std::string kp = key_of(g, link, in, in, epi_timed, ncol);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache_locked();
@@ -145,10 +148,10 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     for (int r : cands) {
       const int cols = r & 0xff;
       if (cols > 1 && cols > ncol) continue;  // a wider tile than the batch only wastes lanes
-      if (launch_dslash(link, in, in, EPI_PLAIN, r, a, s)) continue;  // warm-up
+      if (launch_dslash(link, in, in, epi_timed, r, a, s)) continue;  // warm-up
       // a candidate whose timing fails is skipped
       bool ok = hipEventRecord(e0, s) == hipSuccess;
-      for (int k = 0; k < 3; ++k) ok = ok && launch_dslash(link, in, in, EPI_PLAIN, r, a, s) == ASQ_OK;
+      for (int k = 0; k < 3; ++k) ok = ok && launch_dslash(link, in, in, epi_timed, r, a, s) == ASQ_OK;
       ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
       float ms = 0;
       ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
@@ -170,10 +173,14 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     (void)hipEventDestroy(e1);
   }
   std::lock_guard<std::mutex> lk(g_mu);
-  for (int epi = EPI_PLAIN; epi <= EPI_RESID; ++epi)
-    for (int out = VEC_F64; out <= VEC_F16; ++out)
-      g_cache[key_of(g, link, in, out, epi, ncol)] = epi == EPI_UPDATE ? best_update : best;
-  save_cache_locked();
+  if (epi_timed == EPI_CANON) {
+    g_cache[kp] = best;
+  } else {
+    for (int epi = EPI_PLAIN; epi <= EPI_RESID; ++epi)
+      for (int out = VEC_F64; out <= VEC_F16; ++out)
+        g_cache[key_of(g, link, in, out, epi, ncol)] = epi == EPI_UPDATE ? best_update : best;
+  }
+  if (persist) save_cache_locked();
   return ASQ_OK;
 }
 

@@ -19,7 +19,7 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = ("csrc/dslash.hip", "csrc/dslash_impl.h", "csrc/dslash_mfma.h", "csrc/dslash_f64.hip", "csrc/dslash_f32.hip",
-                  "csrc/dslash_r12.hip", "csrc/dslash_i16.hip", "csrc/asq_device.h", "csrc/asq_reduce.h",
+                  "csrc/dslash_r12.hip", "csrc/dslash_i16.hip", "csrc/dslash_f64f32.hip", "csrc/asq_device.h", "csrc/asq_reduce.h",
                   "csrc/asq_internal.h")
 
 
@@ -93,6 +93,8 @@ KERNELS_ONLY = {
         "workload": "threelevel_48x48x48x96",
         "f16_f16r12_12rhs": ("dslash_kernel<LinkI16R12, VecF16, VecF16, ", (16 * 24 + 12 * 2 * 16) * H48, 12, 10),
         "f64_f64_12rhs": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 12 * 2 * 48) * H48, 12, 5),
+        "f32_f32_1rhs_r18": ("dslash_kernel<LinkF32R18, VecF32, VecF32, ", (16 * 72 + 2 * 24) * H48, 1, 20),
+        "f64_f64_1rhs_r18": ("dslash_kernel<LinkF64R18, VecF64, VecF64, ", (16 * 144 + 2 * 48) * H48, 1, 20),
     },
 }
 COPY_KERNEL = "copy_kernel"

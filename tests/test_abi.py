@@ -51,9 +51,11 @@ def test_gauge_bytes(lib):
     d = _desc()
     half = 4 * 4 * 4 * 8 // 2
     n = asq.asq_gauge_bytes(ctypes.byref(d))
-    # F64 18-real + F32 18-real copies: 16 slots x half sites x (144 + 72) bytes, plus a flag word
-    assert n >= 16 * half * (144 + 72)
-    assert n < 16 * half * (144 + 72) + 4096
+    # F64 18-real + F32 18-real copies: 16 slots x half sites x (144 + 72) bytes, then the staging
+    # area of the host import (FP64 fat and long links of min(V, 16 MB / 1152 B) sites) and a flag word
+    stage = min(2 * half, (16 << 20) // 1152) * 1152
+    assert n >= 16 * half * (144 + 72) + stage
+    assert n < 16 * half * (144 + 72) + stage + 4096
     d12 = _desc(mask=7, recon=12)
     assert asq.asq_gauge_bytes(ctypes.byref(d12)) >= 16 * half * (144 + 48 + 24)
     for bad in (_desc(dims=(5, 4, 4, 8)), _desc(dims=(2, 4, 4, 8)), _desc(mask=0), _desc(recon=15),
@@ -78,7 +80,23 @@ def test_invalid_arguments_rejected_on_host(lib):
     srv = ctypes.c_void_p()
     assert asq.serve_create(None, 1 << 20, 1, 1, ctypes.byref(srv)) == asq.ASQ_EINVAL
     assert asq.serve_create(256, 1 << 20, 0, 1, ctypes.byref(srv)) == asq.ASQ_EINVAL
-    assert asq.serve_submit(None, 0, 1, m, 16, 16, ctypes.byref(params), None) == asq.ASQ_EINVAL
+    assert asq.serve_submit(None, 0, 1, m, 16, 16, ctypes.byref(params), None, None) == asq.ASQ_EINVAL
+    assert asq.asq_gauge_create_device(ctypes.byref(d), None, 16, 256, 1 << 20, None,
+                                       ctypes.byref(h)) == asq.ASQ_EINVAL
+    # device links must be 16-byte aligned (host links need not be)
+    assert asq.asq_gauge_create_device(ctypes.byref(d), 24, 16, 256, 1 << 20, None,
+                                       ctypes.byref(h)) == asq.ASQ_EINVAL
+    # vectors: precisions, alignment, overlap, a gauge handle
+    assert asq.asq_vec_bytes(0, 10) == 480 and asq.asq_vec_bytes(1, 10) == 240 and asq.asq_vec_bytes(2, 10) == 160
+    assert asq.asq_vec_bytes(3, 10) == 0
+    base = 1 << 24
+    assert asq.asq_vec_convert(10, 3, base, 0, base + 4096, None) == asq.ASQ_EINVAL
+    assert asq.asq_vec_convert(10, 0, base + 8, 1, base + 4096, None) == asq.ASQ_EINVAL
+    assert asq.asq_vec_convert(10, 0, None, 1, base + 4096, None) == asq.ASQ_EINVAL
+    assert asq.asq_vec_convert(10, 0, base, 2, base + 256, None) == asq.ASQ_EINVAL  # 480 bytes overlap
+    assert asq.asq_vec_convert(0, 0, base, 2, base + 4096, None) == asq.ASQ_OK  # nothing to do
+    assert asq.asq_vec_to_native(None, 0, 1, base, base + 4096, None) == asq.ASQ_EINVAL
+    assert asq.asq_vec_from_native(None, 0, 1, base, base + 4096, None) == asq.ASQ_EINVAL
     assert asq.serve_poll(None, 1, None, None) == asq.ASQ_EINVAL
     assert asq.asq_copy_probe(16, 16, 15, None) == asq.ASQ_EINVAL
     assert asq.asq_read_probe(16, 15, 16, None) == asq.ASQ_EINVAL
@@ -123,12 +141,30 @@ def test_magic_division_formula():
             assert (n * m) >> 64 == n // d
 
 
-def test_f16n_host_codec_roundtrip():
+def test_reference_f16n_encoder_follows_its_definition():
+    """The tests' own FP16-with-norm encoder (the reference the library's encoder is held to,
+    bit for bit on the GPU):
+    the norm is the largest magnitude, the largest component encodes as +-1 exactly, values
+    that are binary16 multiples of the norm survive unchanged, and the rounding error of the
+    others is at most half a binary16 unit of [1/2, 1) times the norm (2^-12 nu)."""
+    from gpu_common import f16n_encode, f16n_value
+
     rng = np.random.default_rng(1)
     v = rng.standard_normal((2, 50, 3)) + 1j * rng.standard_normal((2, 50, 3))
-    w = asq.decode_f16n(asq.encode_f16n(v), 2, 50)
-    err = np.abs(w - v).max(axis=-1) / np.abs(np.stack([v.real, v.imag], -1)).max(axis=(-1, -2))
-    assert err.max() < 2 ** -11 * 1.01
+    h, nu = f16n_encode(v)
+    comp = np.stack([v.real, v.imag], -1).astype(np.float32)
+    assert np.array_equal(nu, np.abs(comp).reshape(2, 50, 6).max(-1))
+    assert np.all(np.abs(h.astype(np.float32)).reshape(2, 50, 6).max(-1) == 1.0)
+    w = f16n_value(h, nu)
+    err = np.abs(np.stack([(w - v).real, (w - v).imag], -1)).reshape(2, 50, 6).max(-1) / nu
+    # |h| < 1 rounds within half a unit of [1/2, 1): 2^-12
+    assert err.max() <= 2 ** -12 * (1 + 1e-6) + 2 ** -24
+    # exact cases: a site of powers of two times a common scale, and a zero site
+    e = np.zeros((1, 2, 3), dtype=np.complex128)
+    e[0, 0] = np.array([3.0 + 0.75j, -1.5 - 0.375j, 0.1875 + 3.0j])
+    he, ne = f16n_encode(e)
+    assert ne[0, 0] == 3.0 and ne[0, 1] == 0.0
+    assert np.array_equal(f16n_value(he, ne), e)
 
 
 def test_build_links_binding_checks_shapes(lib):

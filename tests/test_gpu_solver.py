@@ -351,11 +351,12 @@ def test_solver_rejects_bad_arguments(asq):
         with pytest.raises(asq.AsqError) as e:
             g.solve(masses, b, **args)
         assert e.value.code == asq.ASQ_EINVAL, kw
-    # a gauge without FP32 links cannot run the mixed modes
-    g64 = asq.Gauge(dims, fat, lng, precs=("f64",), recon=18)
-    with pytest.raises(asq.AsqError) as e:
-        g64.solve([0.1], b, mode="mixed32")
-    assert e.value.code == asq.ASQ_EINVAL
+    # a gauge without FP64 links cannot decide on the true residual in any mode
+    g32 = asq.Gauge(dims, fat, lng, precs=("f32",), recon=18)
+    for mode in ("mixed32", "f64"):
+        with pytest.raises(asq.AsqError) as e:
+            g32.solve([0.1], b, mode=mode)
+        assert e.value.code == asq.ASQ_EINVAL
 
 
 def test_aliased_buffers_rejected(asq):
@@ -424,3 +425,113 @@ def test_binding_checks_tensor_sizes(asq):
         with pytest.raises(asq.AsqError) as e:
             call()
         assert e.value.code == asq.ASQ_EINVAL, name
+
+
+@pytest.mark.parametrize("mode,ncol", [("mixed32", 1), ("mixed32", 2), ("f64", 1), ("f64", 2)])
+def test_narrow_batch_beyond_1024_site_blocks(asq, mode, ncol, monkeypatch):
+    """Batches of one or two columns form alpha inside D_eo and beta inside the direction
+    update.  Beyond 1024 site blocks (24^3 x 48: 1296 blocks of 256 sites) every D_eo block
+    sums the partials in a loop of its own instead of the loads issued before the hop loop,
+    and the direction update's sum takes several passes.  Both must give the bits of the
+    scalar launches (folds switched off) and the FP64 true residual."""
+    import torch
+
+    dims = (24, 24, 24, 48)
+    fat, lng = gauge_arrays(dims, 0.3, 91)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    assert (g.half + 255) // 256 > 1024
+    masses = [0.02, 0.05][:ncol]
+    b = synth.make_sources(dims, ncol, 92)
+    x1, r1 = _solve(asq, g, masses, b, mode)
+    monkeypatch.setenv("ASQ_FOLD_ALPHA", "0")
+    monkeypatch.setenv("ASQ_FOLD_BETA", "0")
+    x2, r2 = _solve(asq, g, masses, b, mode)
+    print(f"24^3x48 mode={mode} ncol={ncol} iters={[s['iters'] for s in r1.stats]}", flush=True)
+    assert r1.rc == 0 and r2.rc == 0
+    assert [s["iters"] for s in r1.stats] == [s["iters"] for s in r2.stats]
+    assert np.array_equal(x1, x2), "folded scalars differ from the scalar launches"
+    r = oracle_resid_cols(dims, fat, lng, masses, b, x1)
+    assert np.all(r <= TOL)
+
+
+def test_nan_source_column_reports_enan(asq):
+    # One column's source holds a NaN: that column stops with ASQ_ENAN at its first
+    # reduction, the call returns ASQ_ENAN, and every other column is bitwise its solo solve.
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=18)
+    masses = [0.05, 0.1, 0.02]
+    b = synth.make_sources(dims, 3, 93)
+    b[1, 17, 2] = complex(np.nan, 0.0)
+    x, res = _solve(asq, g, masses, b, "mixed32")
+    print(f"nan column: rc={res.rc} status={[s['status'] for s in res.stats]}", flush=True)
+    assert res.rc == asq.ASQ_ENAN
+    assert res.stats[1]["status"] == asq.ASQ_ENAN and res.stats[1]["converged"] == 0
+    for c in (0, 2):
+        assert res.stats[c]["status"] == 0 and res.stats[c]["converged"] == 1
+        xs, rs = _solve(asq, g, [masses[c]], b[c:c + 1], "mixed32")
+        assert rs.rc == 0 and rs.stats[0]["iters"] == res.stats[c]["iters"]
+        assert np.array_equal(xs[0], x[c])
+        assert oracle.true_residual(dims, fat, lng, masses[c], b[c], x[c]) <= TOL
+
+
+@pytest.mark.parametrize("mode", ["mixed32", "mixed16"])
+def test_mixed_cg_on_fp64_only_links(asq, mode):
+    # A field kept in FP64 only: the iterated FP32 Dslash reads the FP64 18-real links and
+    # rounds them to FP32 on load; every column reaches the oracle's FP64 true residual.
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64",), recon=18)
+    masses = [0.05, 0.1, 0.02]
+    b = synth.make_sources(dims, 3, 94)
+    x, res = _solve(asq, g, masses, b, mode)
+    r = oracle_resid_cols(dims, fat, lng, masses, b, x)
+    print(f"fp64-only links mode={mode} iters={[s['iters'] for s in res.stats]} resid={r}", flush=True)
+    assert res.rc == 0 and np.all(r <= TOL)
+
+
+def test_mixed32_fp64_links_full_size(asq):
+    # the 20^3 x 64 single solve with FP64-stored links and FP32 arithmetic
+    w = synth.WORKLOADS["single_20x20x20x64"]
+    dims, m = w["dims"], w["masses"][0]
+    fat, lng = gauge_arrays(dims, w["eps"], synth.gauge_seed(w["index"]))
+    g = asq.Gauge(dims, fat, lng, precs=("f64",), recon=18)
+    b = synth.make_sources(dims, 1, synth.source_seed(w["index"]))
+    x, res = _solve(asq, g, [m], b, "mixed32", maxiter=20000)
+    st = res.stats[0]
+    r = oracle.true_residual(dims, fat, lng, m, b[0], x[0])
+    print(f"20^3x64 mixed32 on FP64 links iters={st['iters']} ru={st['reliable_updates']} resid={r:.3e}", flush=True)
+    assert res.rc == 0 and r <= TOL
+
+
+@pytest.mark.parametrize("mode", ["mixed16", "mixed32"])
+def test_stalled_columns_escalate(asq, mode, monkeypatch):
+    """A column whose FP64 true residual stops falling (ASQ_STALL_UPDATES reliable updates
+    in a row without a drop by ASQ_STALL_DROP) continues from its x in the next tier:
+    mixed16 -> mixed32 -> f64.  The host forces the condition: with an unreachable drop
+    every reliable update counts as a stall, so each column hands on after two updates
+    per tier and finishes in FP64.  Each column still reaches the oracle's 1e-10, the
+    counters add up, and a column's result is bitwise its solo run's."""
+    dims = (6, 4, 8, 10)
+    fat, lng = gauge_arrays(dims, 0.3, 5)
+    g = asq.Gauge(dims, fat, lng, precs=("f64", "f32", "f16"), recon=12)
+    masses = [0.05, 0.1, 0.02]
+    b = synth.make_sources(dims, 3, 95)
+    monkeypatch.setenv("ASQ_STALL_UPDATES", "2")
+    monkeypatch.setenv("ASQ_STALL_DROP", "1e100")
+    x, res = _solve(asq, g, masses, b, mode, poll_iters=4)
+    steps = 2 if mode == "mixed16" else 1
+    print(f"escalation {mode}: {[(s['iters'], s['reliable_updates'], s['escalations'], s['final_mode']) for s in res.stats]}",
+          flush=True)
+    assert res.rc == 0
+    for c, st in enumerate(res.stats):
+        assert st["converged"] == 1 and st["escalations"] == steps and st["final_mode"] == asq.ASQ_MODE_F64
+        assert oracle.true_residual(dims, fat, lng, masses[c], b[c], x[c]) <= TOL
+    xs, rs = _solve(asq, g, [masses[1]], b[1:2], mode, poll_iters=4)
+    assert rs.stats[0]["iters"] == res.stats[1]["iters"] and rs.stats[0]["escalations"] == steps
+    assert np.array_equal(xs[0], x[1])
+    # the default rule leaves an ordinary solve in its own tier
+    monkeypatch.delenv("ASQ_STALL_UPDATES")
+    monkeypatch.delenv("ASQ_STALL_DROP")
+    x2, r2 = _solve(asq, g, masses, b, mode)
+    assert r2.rc == 0 and all(s["escalations"] == 0 and s["final_mode"] == asq.MODES[mode] for s in r2.stats)
