@@ -176,6 +176,17 @@ size_t asqtad_plaquette_workspace_bytes(const int dims[4]);
 int asqtad_plaquette(const int dims[4], const double* thin_dev, void* work_dev, size_t work_bytes, double* plaq,
                      void* hip_stream);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+   loops, harnesses that forbid allocation): asqtad_plaquette without a
+   workspace.  The partial sums live in a fixed 2 MiB device array of the
+   library (one per GPU, kept until the process ends), so lattices up to
+   67108608 sites (ASQ_ENOMEM beyond); every call on a GPU shares that array,
+   so calls that overlap on one GPU race.  *plaq_dev (device, 8-byte aligned)
+   receives P, the same bits as asqtad_plaquette.  Asynchronous on hip_stream:
+   no allocation, no copy to the host, no synchronization.  thin_dev as for
+   asqtad_plaquette; ASQ_EINVAL on a bad argument (checked on the host). */
+int asqtad_plaquette_noalloc(const int dims[4], const double* thin_dev, double* plaq_dev, void* hip_stream);
+
 /* ---- operator ------------------------------------------------------------ */
 
 /* out = D restricted to sites of out_parity, acting on in (sites of the other

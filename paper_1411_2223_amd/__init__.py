@@ -100,6 +100,7 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_double), _vp]),
     "asqtad_npr_fourfermion": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_int), _vp, _vp]),
+    "asqtad_plaquette_noalloc": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), _vp, _vp, _vp]),
     "asq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "asq_last_error": (ctypes.c_char_p, []),
     "asq_copy_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),

@@ -34,6 +34,9 @@
 // long link 2.
 #include <math.h>
 
+#include <map>
+#include <mutex>
+
 #include "asq_reduce.h"
 
 namespace asq {
@@ -498,5 +501,84 @@ extern "C" int asqtad_plaquette(const int dims[4], const double* thin_dev, void*
   ASQ_HIP_TRY(hipGetLastError());
   ASQ_HIP_TRY(hipMemcpyAsync(plaq, partials + nb, sizeof(double), hipMemcpyDeviceToHost, s));
   ASQ_HIP_TRY(hipStreamSynchronize(s));
+  return ASQ_OK;
+}
+
+// ---- the same without any allocation --------------------------------------
+// For callers that cannot allocate (code under graph capture, tight serving
+// loops): the partial sums live in a fixed device array of the library, one per
+// GPU, found once per device with hipGetSymbolAddress.  Every call on a GPU
+// shares that GPU's array, so calls that overlap on one GPU race.
+namespace asq {
+namespace {
+
+constexpr size_t kNoAllocScratchDoubles = 262144;  // 2 MiB: V up to 67 108 608 sites
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;  // device -> address of its copy of `scratch`
+
+// The device address of this device's scratch array (looked up once per device,
+// with the device current).  nullptr and a message on failure.
+double* scratch_ptr() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+  g_scratch_ptr[dev] = (double*)p;
+  return (double*)p;
+}
+
+// The final pass writes P straight to the caller's device output.
+__global__ void __launch_bounds__(kBlock) plaquette_final_to(const double* partials, int n, double inv_count,
+                                                             double* out) {
+  __shared__ double sh[kBlock / 64];
+  const double tot = block_sum(strided_sum(partials, n), sh);
+  if (threadIdx.x == 0) *out = tot * inv_count;
+}
+
+}  // namespace
+}  // namespace asq
+
+extern "C" int asqtad_plaquette_noalloc(const int dims[4], const double* thin_dev, double* plaq_dev,
+                                        void* hip_stream) {
+  if (!thin_dev || !plaq_dev || !valid_extents(dims)) {
+    set_last_error("asqtad_plaquette_noalloc: null pointer or invalid extents (even, >= 4)");
+    return ASQ_EINVAL;
+  }
+  if (((uintptr_t)thin_dev & 15) || ((uintptr_t)plaq_dev & 7)) {
+    set_last_error("asqtad_plaquette_noalloc: thin links 16-byte and the output 8-byte aligned");
+    return ASQ_EINVAL;
+  }
+  const long V = (long)dims[0] * dims[1] * dims[2] * dims[3];
+  const long nb = (V + kBlock - 1) / kBlock;
+  if ((size_t)nb > kNoAllocScratchDoubles) {
+    set_last_error("asqtad_plaquette_noalloc: lattice too large for the fixed scratch (at most 67108608 sites)");
+    return ASQ_ENOMEM;
+  }
+  const size_t thin_bytes = (size_t)V * 4 * 18 * sizeof(double);
+  const uintptr_t t0 = (uintptr_t)thin_dev, o0 = (uintptr_t)plaq_dev;
+  if (o0 < t0 + thin_bytes && t0 < o0 + sizeof(double)) {
+    set_last_error("asqtad_plaquette_noalloc: the output must not overlap the thin links");
+    return ASQ_EINVAL;
+  }
+  double* partials = scratch_ptr();
+  if (!partials) {
+    set_last_error("asqtad_plaquette_noalloc: hipGetSymbolAddress of the scratch array failed");
+    return ASQ_EHIP;
+  }
+  FattenArgs a{};
+  for (int mu = 0; mu < 4; ++mu) a.d[mu] = dims[mu];
+  a.V = V;
+  a.thin = (const double2*)thin_dev;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // every partial the final pass reads is written by the first pass: nothing to clear
+  plaquette_kernel<<<(unsigned)nb, kBlock, 0, s>>>(a, partials);
+  ASQ_HIP_TRY(hipGetLastError());
+  plaquette_final_to<<<1, kBlock, 0, s>>>(partials, (int)nb, 1.0 / (6.0 * (double)V), plaq_dev);
+  ASQ_HIP_TRY(hipGetLastError());
   return ASQ_OK;
 }
