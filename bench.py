@@ -168,59 +168,78 @@ def read_bandwidth(asq, stream, nbytes=1 << 30, reps=10):
     return nbytes / dt / 1e9
 
 
-def cpu_baseline(w, fat, lng, b, mass, iters_full, seconds):
-    """Oracle CG on the same workload, bounded: time a prefix of iterations, scale to a full solve."""
+CPU_RUNS = 10
+
+
+def _oracle_cg_runs(dims, fat, lng, mass, b, tol, seconds):
+    """Per-iteration time of the oracle's FP64 CG: CPU_RUNS runs of the first n
+    iterations of one solve, n sized so that all runs take about ``seconds``."""
     import oracle
 
-    dims = w["dims"]
     oracle.lib()
     t0 = time.perf_counter()
     oracle.apply_A(dims, fat, lng, mass, b)  # one operator application to size the sample
     per_apply = time.perf_counter() - t0
-    n = max(3, int(seconds / max(per_apply, 1e-6)))
-    t0 = time.perf_counter()
-    _, it, _, _ = oracle.cg(dims, fat, lng, mass, b, tol=w["tol"], maxiter=n)
-    dt = time.perf_counter() - t0
-    # the sample includes one extra operator application (its true residual)
-    per_iter = max(dt - per_apply, 1e-9) / max(it, 1)
-    t_solve = per_iter * iters_full
+    n = max(3, int(seconds / CPU_RUNS / max(per_apply, 1e-6)))
+    per_iter = []
+    for _ in range(CPU_RUNS):
+        t0 = time.perf_counter()
+        _, it, _, _ = oracle.cg(dims, fat, lng, mass, b, tol=tol, maxiter=n)
+        dt = time.perf_counter() - t0
+        # each run ends with one extra operator application (its true residual)
+        per_iter.append(max(dt - per_apply, 1e-9) / max(it, 1))
+    p = np.asarray(per_iter)
+    return it, p
+
+
+def _spread(p, scale):
+    """median, mean and standard error of the mean of CPU_RUNS timings, scaled."""
+    q = p * scale
+    return {"median": float(np.median(q)), "mean": float(q.mean()),
+            "se": float(q.std(ddof=1) / np.sqrt(len(q))) if len(q) > 1 else 0.0, "runs": len(q)}
+
+
+def cpu_baseline(w, fat, lng, b, mass, iters_full, seconds):
+    """Oracle CG on the same workload, bounded: CPU_RUNS timed prefixes of the solve,
+    the median per-iteration time scaled to the full solve's iteration count."""
+    import oracle
+
+    dims = w["dims"]
+    it, p = _oracle_cg_runs(dims, fat, lng, mass, b, w["tol"], seconds)
+    t_solve = _spread(p, iters_full)
     # the oracle's half-Dslash (D_oe on the source), FP64, counted like the GPU's FP64 tier
     half = int(np.prod(dims)) // 2
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
+    td = []
+    for _ in range(CPU_RUNS):
+        t0 = time.perf_counter()
         oracle.dslash(dims, fat, lng, 1, b)
-    t_d = (time.perf_counter() - t0) / reps
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"oracle FP64 CG, first {it} of {iters_full} iterations at {dims[0]}^3x{dims[3]} "
-                      f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled to the full solve",
+        td.append(time.perf_counter() - t0)
+    td = np.asarray(td)
+    return {"value": 1.0 / t_solve["median"], "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle FP64 CG ({oracle.build_flags()}), {CPU_RUNS} runs of the first {it} of {iters_full} "
+                      f"iterations at {dims[0]}^3x{dims[3]} (median {np.median(p) * 1e3:.1f} ms/iteration), "
+                      f"scaled to the full solve",
             "seconds_per_solve": t_solve,
-            "dslash_ms": t_d * 1e3,
-            "dslash_gbs_effective": dslash_bytes_per_site("f64", "f64", 1) * half / t_d / 1e9}
+            "dslash_ms": _spread(td, 1e3),
+            "dslash_gbs_effective": dslash_bytes_per_site("f64", "f64", 1) * half / float(np.median(td)) / 1e9}
 
 
 def cpu_baseline_extrapolated(dims, fat, lng, b0, mass, col_iters, seconds, unit):
-    """Oracle FP64 CG per-iteration time on a bounded prefix of one column's solve, scaled
-    to the batch: the oracle solves the columns one after another, each for the number of
-    iterations the GPU needed for it (labelled extrapolated)."""
+    """Oracle FP64 CG per-iteration time (median of CPU_RUNS timed prefixes of one
+    column's solve), scaled to the batch: the oracle solves the columns one after
+    another, each for the number of iterations the GPU needed for it (labelled
+    extrapolated)."""
     import oracle
 
-    oracle.lib()
-    t0 = time.perf_counter()
-    oracle.apply_A(dims, fat, lng, mass, b0)
-    per_apply = time.perf_counter() - t0
-    n = max(3, int(seconds / max(per_apply, 1e-6)))
-    t0 = time.perf_counter()
-    _, it, _, _ = oracle.cg(dims, fat, lng, mass, b0, tol=1e-10, maxiter=n)
-    dt = time.perf_counter() - t0
-    per_iter = max(dt - per_apply, 1e-9) / max(it, 1)
-    total = per_iter * sum(col_iters)
-    value = len(col_iters) / total if unit == "RHS-solves/s" else total * 1e3
+    it, p = _oracle_cg_runs(dims, fat, lng, mass, b0, 1e-10, seconds)
+    total = _spread(p, sum(col_iters))
+    med = total["median"]
+    value = len(col_iters) / med if unit == "RHS-solves/s" else med * 1e3
     return {"value": value, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle",
             "extrapolated": True,
-            "sample": f"oracle FP64 CG, first {it} iterations of one column at "
-                      f"{'x'.join(map(str, dims))} ({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled to "
-                      f"{len(col_iters)} columns x their GPU iteration counts ({sum(col_iters)} iterations)",
+            "sample": f"oracle FP64 CG ({oracle.build_flags()}), {CPU_RUNS} runs of the first {it} iterations "
+                      f"of one column at {'x'.join(map(str, dims))} (median {np.median(p) * 1e3:.1f} ms/iteration), "
+                      f"scaled to {len(col_iters)} columns x their GPU iteration counts ({sum(col_iters)} iterations)",
             "seconds_per_batch": total}
 
 
@@ -785,17 +804,19 @@ def run_asqtad(args, asq, torch):
         t0 = time.perf_counter()
         oracle.asqtad_links(dims, U, u0, sites=rng.integers(0, V, size=n))
         per_site = (time.perf_counter() - t0) / n
-        n = int(min(V, max(4096, args.cpu_seconds / max(per_site, 1e-9))))
-        sites = rng.integers(0, V, size=n)
-        t0 = time.perf_counter()
-        oracle.asqtad_links(dims, U, u0, sites=sites)
-        dtc = time.perf_counter() - t0
-        full = dtc / n * V
-        cpu = {"value": full * 1e3, "unit": "ms per link construction", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": (f"oracle path sums at {n} random sites of {V} ({dtc:.1f} s), scaled to every site"
-                          if n < V else f"oracle path sums at all {V} sites ({dtc:.1f} s)")}
-        log(f"cpu baseline: {full:.1f} s per construction on {cpu['cores']} threads")
+        n = int(min(V // CPU_RUNS, max(1024, args.cpu_seconds / CPU_RUNS / max(per_site, 1e-9))))
+        per = []
+        for _ in range(CPU_RUNS):
+            sites = rng.integers(0, V, size=n)
+            t0 = time.perf_counter()
+            oracle.asqtad_links(dims, U, u0, sites=sites)
+            per.append((time.perf_counter() - t0) / n)
+        full = _spread(np.asarray(per), V * 1e3)
+        cpu = {"value": full["median"], "unit": "ms per link construction", "cores": oracle.num_threads(),
+               "kind": "oracle", "ms_per_construction": full,
+               "sample": f"oracle path sums ({oracle.build_flags()}), {CPU_RUNS} runs at {n} random sites "
+                         f"of {V} each, median scaled to every site"}
+        log(f"cpu baseline: {full['median'] / 1e3:.1f} s per construction on {cpu['cores']} threads")
     out = {"metric": METRIC, "workload": "asqtad_20x20x20x64", "value": dt * 1e3,
            "unit": "ms per link construction", "higher_is_better": False, "dtype": "f64", "data": "synthetic",
            "u0": u0, "plaquette": plaq, "u0_from_plaquette": plaq ** 0.25, "plaquette_ms": t_plaq * 1e3,
@@ -909,14 +930,18 @@ def run_npr(args, asq, torch):
         t0 = time.perf_counter()
         oracle.npr_fourfermion(dims, U, props_h, ops, zs=np.arange(n))
         per_z = (time.perf_counter() - t0) / n
-        n = int(min(nz, max(n, args.cpu_seconds / max(per_z, 1e-9))))
-        t0 = time.perf_counter()
-        oracle.npr_fourfermion(dims, U, props_h, ops, zs=rng.integers(0, nz, n))
-        t_s = time.perf_counter() - t0
-        t_all = t_s / n * nz
-        cpu = {"value": 1.0 / t_all, "unit": "contractions/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"oracle FP64 contraction of {len(ops)} operators at {n} random hypercubes of {nz} "
-                         f"({t_s:.1f} s), scaled to the whole lattice",
+        n = int(min(nz // CPU_RUNS, max(n, args.cpu_seconds / CPU_RUNS / max(per_z, 1e-9))))
+        per = []
+        for _ in range(CPU_RUNS):
+            zr = rng.integers(0, nz, n)
+            t0 = time.perf_counter()
+            oracle.npr_fourfermion(dims, U, props_h, ops, zs=zr)
+            per.append((time.perf_counter() - t0) / n)
+        t_all = _spread(np.asarray(per), nz)
+        cpu = {"value": 1.0 / t_all["median"], "unit": "contractions/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"oracle FP64 contraction of {len(ops)} operators ({oracle.build_flags()}), {CPU_RUNS} "
+                         f"runs at {n} random hypercubes of {nz} each, median scaled to the whole lattice",
                "seconds_per_contraction": t_all}
     out_j = {"metric": METRIC, "workload": "npr_20x20x20x64", "value": 1.0 / dt, "unit": "contractions/s",
              "ms_per_contraction": dt * 1e3, "operators": len(ops), "hypercubes": nz, "dtype": "f64",
@@ -944,6 +969,10 @@ def main():
     import paper_1411_2223_amd as asq
 
     asq.load()
+    if not args.no_cpu_baseline and not args.kernels_only:
+        import oracle
+
+        oracle.select_native_build()  # the CPU baseline runs code tuned for this host
     if args.workload == "single_20x20x20x64":
         run_single(args, asq, torch)
     elif args.workload == "batched_20x20x20x64":

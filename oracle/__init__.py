@@ -28,18 +28,44 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "asqtad_oracle.c")
 _SRCS = (_SRC, os.path.join(_HERE, "npr_oracle.c"))
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a copy tuned for the host it runs on, compiled in the process that asks for it
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+# -std=c11 alone already turns off FMA contraction in gcc; it is spelled out so that
+# the portable and the host-tuned builds round every product and sum alike
+_CFLAGS = ["-O3", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-fopenmp"]
+_native = False
 
 _dptr = ctypes.POINTER(ctypes.c_double)
 _iptr = ctypes.POINTER(ctypes.c_int)
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle shared library with gcc (-O2, OpenMP)."""
+    """Compile the oracle shared library with gcc (-O3, OpenMP, generic x86-64 code)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", *_SRCS, "-o", _LIB + ".tmp", "-lm"]
+        cmd = ["gcc", *_CFLAGS, *_SRCS, "-o", _LIB + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
+
+
+def select_native_build() -> str:
+    """Load, in place of the portable build, a copy compiled here and now with
+    -O3 -march=native for the CPU this process runs on (the CPU-baseline timing uses
+    it).  Same arithmetic: no FMA contraction and no reassociation in either build.
+    Must be called before the first oracle call of the process."""
+    global _native
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    tmp = f"{_LIB_NATIVE}.tmp{os.getpid()}"
+    subprocess.run(["gcc", *_CFLAGS, "-march=native", *_SRCS, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, _LIB_NATIVE)
+    _native = True
+    return _LIB_NATIVE
+
+
+def build_flags() -> str:
+    """The gcc flags of the build this process loads (or will load)."""
+    return " ".join(_CFLAGS + (["-march=native"] if _native else []))
 
 
 _lib = None
@@ -48,8 +74,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_LIB_NATIVE if _native else build())
         L.oracle_dslash.argtypes = [_iptr, _dptr, _dptr, ctypes.c_int, _dptr, _dptr]
         L.oracle_dslash.restype = ctypes.c_int
         L.oracle_apply_A.argtypes = [_iptr, _dptr, _dptr, ctypes.c_double, _dptr, _dptr]

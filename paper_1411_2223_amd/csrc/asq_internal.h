@@ -124,6 +124,7 @@ struct DslashArgs {
   double coeff_fat;     // 12-real tiers: fat / long coefficients re-applied in-kernel
   double coeff_long;
   int reverse;          // walk the lattice from the last site block to the first
+  int global_sweep;     // no XCD slab remap (kGlobalSweepBit)
 };
 
 // Launch one Dslash.  link_kind / in_kind select the template; out_kind is the
@@ -143,6 +144,11 @@ int launch_dslash_f64f32(int in_kind, int epi, int rtile, const DslashArgs& a, h
 // 16, 64 or all site blocks.
 constexpr int kPipeBit = 0x100;
 constexpr int kOrderShift = 12;
+// Global sweep: blocks go to the XCDs round-robin in dispatch order instead of
+// each XCD walking a contiguous slab, so the eight XCDs advance through the
+// lattice together and the far-hop (t) neighbour records of the shared front
+// stay in the memory-side cache instead of eight separate fronts.
+constexpr int kGlobalSweepBit = 0x8000;
 // The matrix-core form (FP32 18-real links with FP16-with-norm vectors only):
 // kMfmaBit | kMfmaTile | order << kOrderShift, 32 columns per block of sites.
 constexpr int kMfmaBit = 0x10000;
@@ -151,8 +157,8 @@ inline int rtile_order(int rtile) { return (rtile >> kOrderShift) & 3; }
 inline int order_group(int order, int nblk) { return order == 0 ? 0 : (order == 1 ? 16 : (order == 2 ? 64 : nblk)); }
 // Whether the library builds launch variant rtile (for any link and vector tier).
 bool variant_built(int link_kind, int in_kind, int rtile);
-inline int make_rtile(int cols, bool pipe, int order) {
-  return cols | (pipe ? kPipeBit : 0) | (order << kOrderShift);
+inline int make_rtile(int cols, bool pipe, int order, bool global_sweep = false) {
+  return cols | (pipe ? kPipeBit : 0) | (order << kOrderShift) | (global_sweep ? kGlobalSweepBit : 0);
 }
 // Widest column tile whose UPDATE launch may form alpha itself (DslashArgs::apa).
 constexpr int kFoldAlphaMaxTile = 2;

@@ -229,7 +229,7 @@ __device__ __forceinline__ const void* pick_new(const DslashArgs& A, const void*
 template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   using real = typename InT::real;
-  int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  int lin = A.global_sweep ? (int)blockIdx.x : xcd_remap((int)blockIdx.x, (int)gridDim.x);
   // Alternate sweeps start on the links the previous sweep read last, which the
   // memory-side cache (MALL) still holds.
   if (A.reverse) lin = (int)gridDim.x - 1 - lin;
@@ -437,12 +437,13 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
 }
 
 template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
-int go(const DslashArgs& a0, int order, hipStream_t s) {
+int go(const DslashArgs& a0, int order, bool global_sweep, hipStream_t s) {
   // alpha is formed in-kernel only by narrow tiles
   if (a0.apa && R > kFoldAlphaMaxTile) return ASQ_EINVAL;
   DslashArgs a = a0;
   a.ntiles = (a.ncol + R - 1) / R;
   a.sgroup = order_group(order, a.nblk);
+  a.global_sweep = global_sweep ? 1 : 0;
   const long nb = (long)a.nblk * a.ntiles;
   if (nb <= 0) return ASQ_OK;
   if (nb >= (1L << 31)) return ASQ_EINVAL;
@@ -456,15 +457,16 @@ template <class Link, class InT, class OutT, int EPI>
 int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
   const bool pipe = (rtile & kPipeBit) != 0;
   const int ord = rtile_order(rtile);
+  const bool gs = (rtile & kGlobalSweepBit) != 0;
   switch (rtile & 0xff) {
-    case 1: return pipe ? go<Link, InT, OutT, 1, EPI, true>(a, ord, s) : go<Link, InT, OutT, 1, EPI, false>(a, ord, s);
-    case 2: return pipe ? go<Link, InT, OutT, 2, EPI, true>(a, ord, s) : go<Link, InT, OutT, 2, EPI, false>(a, ord, s);
-    case 4: return pipe ? go<Link, InT, OutT, 4, EPI, true>(a, ord, s) : go<Link, InT, OutT, 4, EPI, false>(a, ord, s);
-    case 8: return pipe ? go<Link, InT, OutT, 8, EPI, true>(a, ord, s) : go<Link, InT, OutT, 8, EPI, false>(a, ord, s);
+    case 1: return pipe ? go<Link, InT, OutT, 1, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 1, EPI, false>(a, ord, gs, s);
+    case 2: return pipe ? go<Link, InT, OutT, 2, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 2, EPI, false>(a, ord, gs, s);
+    case 4: return pipe ? go<Link, InT, OutT, 4, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 4, EPI, false>(a, ord, gs, s);
+    case 8: return pipe ? go<Link, InT, OutT, 8, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 8, EPI, false>(a, ord, gs, s);
     case 12:
       // twelve FP64 columns would spill the accumulators: not built
       if constexpr (InT::kind == VEC_F64) return ASQ_EINVAL;
-      else return pipe ? go<Link, InT, OutT, 12, EPI, true>(a, ord, s) : go<Link, InT, OutT, 12, EPI, false>(a, ord, s);
+      else return pipe ? go<Link, InT, OutT, 12, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 12, EPI, false>(a, ord, gs, s);
   }
   return ASQ_EINVAL;
 }

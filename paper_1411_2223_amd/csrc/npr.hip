@@ -16,9 +16,9 @@
 //   2. the 256 averages U_AD by the first step of each path, in rounds of
 //      growing distance |A ^ D| (U_AD = (1/d) sum_mu L(A, mu) U_{A^mu, D});
 //   3. X_AD = G1(A)^dag U_AD G4(D) and Y_AD = G3(A)^dag U_AD G2(D) to LDS;
-//   4. the contraction: a thread owns one (operator, a1) and a quarter of the
-//      A values, and accumulates the 27 outputs (a2, a3, a4) over its 64
-//      terms; the four quarters are summed across lanes.
+//   4. the contraction: a lane owns one (operator, a1) and a fifth of the 256
+//      (A, C) terms, and accumulates the 27 outputs (a2, a3, a4); the five
+//      fifths are summed across lanes.
 #include <math.h>
 #include <string.h>
 
@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kNprThreads = 256;
 constexpr int kNprOpsPerLaunch = 32;
-constexpr int kNprOpsPerPass = 21;  // 21 ops x 3 rows = 63 of the 64 items a pass covers
+constexpr int kNprOpsPerPass = 16;  // 16 ops x 3 rows = 48 items: 12 per wave
 
 struct NprOp {
   unsigned char p1, p2;  // S1 ^ F1, S2 ^ F2: B = A ^ p1, D = C ^ p2
@@ -204,54 +204,74 @@ __global__ void __launch_bounds__(kNprThreads) npr_kernel(const NprArgs P) {
     Ys[tid * 9 + e] = ym[e];
   }
   __syncthreads();
-  // 4. contraction: item j = (operator, a1) of this pass; quarter q of the A values
-  const int q = (tid >> 4) & 3;
-  const int j = (tid & 15) | ((tid >> 6) << 4);
+  // 4. contraction.  Each wave takes 12 items (operator, a1) of a pass of 16
+  //    operators, in 60 of its lanes: lane 5i + s sums the terms k = 16 A + C
+  //    in the s-th of five near-equal ranges of [0, 256) for item i, so all four
+  //    waves (and SIMDs) work; the five partial sums of an item then meet in its
+  //    first lane.
+  const int lane = tid & 63, wv = tid >> 6;
+  const int item_w = lane / 5, split = lane - 5 * (lane / 5);
+  const int j = 12 * wv + item_w;  // item of the pass: 48 per pass
+  const int k0 = (split * 256) / 5, k1 = ((split + 1) * 256) / 5;
   for (int pass = 0; pass * kNprOpsPerPass < P.nop; ++pass) {
     const int opl = pass * kNprOpsPerPass + j / 3;
     const int a1 = j % 3;
-    const bool act = j < 3 * kNprOpsPerPass && opl < P.nop;
+    const bool act = lane < 60 && opl < P.nop;
     c64 acc[27];
 #pragma unroll
     for (int k = 0; k < 27; ++k) acc[k] = make_double2(0.0, 0.0);
     if (act) {
       const NprOp o = P.ops[opl];
-      for (int Aq = 0; Aq < 4; ++Aq) {
-        const int Ai = 4 * q + Aq;
-        const int B = Ai ^ o.p1;
-        const double s1 = (o.neg1 >> Ai & 1) ? -1.0 : 1.0;
-        for (int C = 0; C < 16; ++C) {
-          const int Di = C ^ o.p2;
-          const double s = ((o.neg2 >> C & 1) ? -s1 : s1);
-          const c64* xr = Xs + (Ai * 16 + Di) * 9 + 3 * a1;  // X_AD[a1][a4]
-          const c64* yr = Ys + (C * 16 + B) * 9;              // Y_CB[a3][a2]
-          c64 sx[3];
+      for (int k = k0; k < k1; ++k) {
+        const int Ai = k >> 4, C = k & 15;
+        const int B = Ai ^ o.p1, Di = C ^ o.p2;
+        const double s = (((o.neg1 >> Ai) ^ (o.neg2 >> C)) & 1) ? -1.0 : 1.0;
+        const c64* xr = Xs + (Ai * 16 + Di) * 9 + 3 * a1;  // X_AD[a1][a4]
+        const c64* yr = Ys + (C * 16 + B) * 9;              // Y_CB[a3][a2]
+        c64 sx[3];
 #pragma unroll
-          for (int a4 = 0; a4 < 3; ++a4) sx[a4] = make_double2(s * xr[a4].x, s * xr[a4].y);
-          c64 yv[9];
+        for (int a4 = 0; a4 < 3; ++a4) sx[a4] = make_double2(s * xr[a4].x, s * xr[a4].y);
+        c64 yv[9];
 #pragma unroll
-          for (int e = 0; e < 9; ++e) yv[e] = yr[e];
+        for (int e = 0; e < 9; ++e) yv[e] = yr[e];
 #pragma unroll
-          for (int a2 = 0; a2 < 3; ++a2)
+        for (int a2 = 0; a2 < 3; ++a2)
 #pragma unroll
-            for (int a3 = 0; a3 < 3; ++a3)
+          for (int a3 = 0; a3 < 3; ++a3)
 #pragma unroll
-              for (int a4 = 0; a4 < 3; ++a4) {
-                c64& v = acc[9 * a2 + 3 * a3 + a4];
-                v = cmac(v, sx[a4], yv[3 * a3 + a2]);
-              }
-        }
+            for (int a4 = 0; a4 < 3; ++a4) {
+              c64& v = acc[9 * a2 + 3 * a3 + a4];
+              v = cmac(v, sx[a4], yv[3 * a3 + a2]);
+            }
       }
     }
-    // the four quarters of an item sit in lanes l, l ^ 16, l ^ 32, l ^ 48 of one wave
+    // the five partial sums of an item into its first lane, in place: lanes 0, 1
+    // of the group add lanes 2, 3; lane 0 adds lane 1, then lane 4 (every lane
+    // takes part in the exchanges; a lane that adds nothing reads itself)
+    const int base = lane < 60 ? lane - split : lane;
+    const int src1 = (lane < 60 && split < 2) ? lane + 2 : lane;
+    const int src2 = (lane < 60 && split == 0) ? base + 1 : lane;
+    const int src3 = (lane < 60 && split == 0) ? base + 4 : lane;
+    const bool g1 = lane < 60 && split < 2, g2 = lane < 60 && split == 0;
 #pragma unroll
     for (int k = 0; k < 27; ++k) {
-      acc[k].x += __shfl_xor(acc[k].x, 16, 64);
-      acc[k].y += __shfl_xor(acc[k].y, 16, 64);
-      acc[k].x += __shfl_xor(acc[k].x, 32, 64);
-      acc[k].y += __shfl_xor(acc[k].y, 32, 64);
+      const double pr = __shfl(acc[k].x, src1, 64), pi = __shfl(acc[k].y, src1, 64);
+      acc[k].x += g1 ? pr : 0.0;
+      acc[k].y += g1 ? pi : 0.0;
     }
-    if (act && q == 0) {
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+      const double pr = __shfl(acc[k].x, src2, 64), pi = __shfl(acc[k].y, src2, 64);
+      acc[k].x += g2 ? pr : 0.0;
+      acc[k].y += g2 ? pi : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+      const double pr = __shfl(acc[k].x, src3, 64), pi = __shfl(acc[k].y, src3, 64);
+      acc[k].x += g2 ? pr : 0.0;
+      acc[k].y += g2 ? pi : 0.0;
+    }
+    if (act && split == 0) {
       c64* o = P.out + ((size_t)(P.op0 + opl) * P.nz + z) * 81 + 27 * a1;
 #pragma unroll
       for (int k = 0; k < 27; ++k) o[k] = acc[k];

@@ -139,12 +139,13 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     ASQ_HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f, best_update_ms = 1e30f;
     // columns per thread x hop-loop form x block order (orders differ only when
-    // there are several tiles)
+    // there are several tiles) x XCD slabs or one global sweep
     std::vector<int> cands;
-    for (int order = 0; order < 4; ++order)
-      for (int pipe = 0; pipe < 2; ++pipe)
-        for (int cols : {1, 2, 4, 8, 12})
-          if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, pipe, order));
+    for (int gs = 0; gs < 2; ++gs)
+      for (int order = 0; order < 4; ++order)
+        for (int pipe = 0; pipe < 2; ++pipe)
+          for (int cols : {1, 2, 4, 8, 12})
+            if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, pipe, order, gs != 0));
     for (int r : cands) {
       const int cols = r & 0xff;
       if (cols > 1 && cols > ncol) continue;  // a wider tile than the batch only wastes lanes

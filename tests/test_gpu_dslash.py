@@ -109,16 +109,17 @@ def test_every_launch_variant(asq, prec, recon):
     assert max_err(got, ref).max() <= MAX_TOL[prec]
     # the same input in the solvers' native layout
     vin_n = g.to_native(vin, prec, nrhs)
-    for cols, pipe, order in asq.VARIANTS_ALL:
+    for cols, pipe, order, sweep in asq.VARIANTS_ALL:
         if cols == 12 and prec == "f64":
             continue  # not built for FP64 vectors; refused in test_unbuilt_variant_rejected
-        out = g.dslash(1, vin, prec, nrhs, variant=asq.variant_code(cols, pipe, order))
-        out_n = g.dslash(1, vin_n, prec, nrhs, variant=asq.variant_code(cols, pipe, order, native=True))
+        out = g.dslash(1, vin, prec, nrhs, variant=asq.variant_code(cols, pipe, order, sweep=sweep))
+        out_n = g.dslash(1, vin_n, prec, nrhs, variant=asq.variant_code(cols, pipe, order, native=True, sweep=sweep))
         back = g.from_native(out_n, prec, nrhs)
         torch.cuda.synchronize()
-        print(f"prec={prec} recon={recon} variant cols={cols} pipe={pipe} order={order}", flush=True)
-        assert torch.equal(out, ref_dev), f"variant ({cols}, {pipe}, {order}) differs from the tuned one"
-        assert torch.equal(back, ref_dev), f"native variant ({cols}, {pipe}, {order}) differs from canonical"
+        v = (cols, pipe, order, sweep)
+        print(f"prec={prec} recon={recon} variant {v}", flush=True)
+        assert torch.equal(out, ref_dev), f"variant {v} differs from the tuned one"
+        assert torch.equal(back, ref_dev), f"native variant {v} differs from canonical"
 
 
 def test_unbuilt_variant_rejected(asq):
