@@ -128,6 +128,29 @@ def time_dslash(asq, g, prec, nrhs, launches, stream, native=True):
     return e0.elapsed_time(e1) * 1e-3 / launches
 
 
+def tiled_dslash_rate(asq, dims, fat, lng, prec, link, stream, reps=(2, 2, 2, 2), launches=20):
+    """1-RHS Dslash on the field tiled periodically reps times along (x, y, z, t): a lattice
+    whose links are far beyond the 256 MB memory-side cache, so each launch streams them
+    from HBM.  Returns (lattice, us per launch, algorithmic GB/s)."""
+    import torch
+
+    X, Y, Z, T = dims
+    big = (X * reps[0], Y * reps[1], Z * reps[2], T * reps[3])
+
+    def tile(a):
+        d = asq.links_to_device(a).view(T, Z, Y, X, 72)
+        return d.repeat(reps[3], reps[2], reps[1], reps[0], 1).reshape(-1).contiguous()
+
+    gb = asq.Gauge(big, tile(fat), tile(lng), precs=(link,), recon=18, stream=stream)
+    dt = time_dslash(asq, gb, prec, 1, launches, stream)
+    half = int(np.prod(big)) // 2
+    gbs = dslash_bytes_per_site(link, prec, 1) * half / dt / 1e9
+    gb.close()
+    del gb
+    torch.cuda.empty_cache()
+    return "x".join(map(str, big)), dt * 1e6, gbs
+
+
 def copy_bandwidth(asq, stream, nbytes=1 << 30, reps=10):
     """Read+write GB/s of the library's plain copy kernel on a buffer far beyond the 256 MB MALL."""
     import torch
@@ -418,6 +441,9 @@ def run_single(args, asq, torch):
     copy_gbs = copy_bandwidth(asq, stream)
     read_gbs = read_bandwidth(asq, stream)
     log(f"copy probe: {copy_gbs:.0f} GB/s; read probe: {read_gbs:.0f} GB/s")
+    big, us_big, gbs_big = tiled_dslash_rate(asq, dims, fat, lng, tprec, link, stream)
+    log(f"dslash {tprec} on {big} (links beyond the MALL): {us_big:.1f} us, {gbs_big:.0f} GB/s "
+        f"({gbs_big / PEAK_HBM_GBS:.1%} of HBM peak)")
 
     ms = secs * 1e3
     iters = st["iters"]
@@ -468,7 +494,12 @@ def run_single(args, asq, torch):
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(f"{tprec}_{link}_1rhs", bytes_launch),
                      "kernel": f"dslash_kernel {tprec} vectors, {link} 18-real links, 1 RHS",
-                     "us_per_launch": dt * 1e6, "bytes_per_launch": bytes_launch},
+                     "us_per_launch": dt * 1e6, "bytes_per_launch": bytes_launch,
+                     "basis": "effective (MALL-assisted): the 295 MB of 20^3x64 FP32 links are close to the "
+                              "256 MB memory-side cache, which serves part of each launch's link reads",
+                     "above_mall": {"lattice": big, "how": "the same field tiled 2x2x2x2", "us_per_launch": us_big,
+                                    "achieved": gbs_big, "frac": gbs_big / PEAK_HBM_GBS,
+                                    "read_probe_frac": read_gbs / PEAK_HBM_GBS}},
         "paper_context": {"cg_gflops_titan_black_mixed_own_code": 46.48, "cg_gflops_titan_black_quda": 97.86,
                           "note": "other hardware, real MILC ensemble, flop convention unstated"},
     }

@@ -12,13 +12,18 @@
 // row, at B = A ^ S ^ F, so each operator is 16 x 16 terms (A, C).
 //
 // One workgroup per hypercube:
-//   1. the 16 corners' propagators and the hypercube's internal links to LDS;
+//   1. the 16 corners' propagators to LDS, and the 64 single steps of the
+//      hypercube (from corner A along mu: the link U_mu(z_A) if bit mu of A is
+//      clear, else the conjugate of the link arriving at z_A);
 //   2. the 256 averages U_AD by the first step of each path, in rounds of
-//      growing distance |A ^ D| (U_AD = (1/d) sum_mu L(A, mu) U_{A^mu, D});
+//      growing distance |A ^ D| (U_AD = (1/d) sum_mu step(A, mu) U_{A^mu, D});
+//      the pairs are dealt to threads in order of distance, so the lanes of a
+//      wave share a round;
 //   3. X_AD = G1(A)^dag U_AD G4(D) and Y_AD = G3(A)^dag U_AD G2(D) to LDS;
-//   4. the contraction: a lane owns one (operator, a1) and a fifth of the 256
-//      (A, C) terms, and accumulates the 27 outputs (a2, a3, a4); the five
-//      fifths are summed across lanes.
+//   4. the contraction: a lane owns one operator and one corner A, sums the 16
+//      terms D and accumulates all 81 outputs; the 16 corners' partial sums of
+//      an operator are added across lanes by halving exchanges, after which
+//      each lane stores the outputs it ended with.
 #include <math.h>
 #include <string.h>
 
@@ -31,7 +36,27 @@ namespace {
 
 constexpr int kNprThreads = 256;
 constexpr int kNprOpsPerLaunch = 32;
-constexpr int kNprOpsPerPass = 16;  // 16 ops x 3 rows = 48 items: 12 per wave
+constexpr int kNprOpsPerPass = 16;  // 4 per wave, each over the 16 lanes of its corners A
+// a matrix per pair (A, D) at A * kRow + 9 D complex entries: one spare entry per
+// row A puts the 16 rows A that a wave reads at once in different LDS banks
+constexpr int kRow = 16 * 9 + 1;
+constexpr int kPairMats = 16 * kRow;
+
+// the 256 pairs (A, D), 16 A + D, in order of distance |A ^ D| (then A, then D)
+struct PairOrder {
+  unsigned char p[256];
+};
+constexpr int popcount4(int m) { return (m & 1) + (m >> 1 & 1) + (m >> 2 & 1) + (m >> 3 & 1); }
+constexpr PairOrder make_pair_order() {
+  PairOrder t{};
+  int n = 0;
+  for (int d = 0; d <= 4; ++d)
+    for (int a = 0; a < 16; ++a)
+      for (int b = 0; b < 16; ++b)
+        if (popcount4(a ^ b) == d) t.p[n++] = (unsigned char)(16 * a + b);
+  return t;
+}
+__constant__ PairOrder kPairOrder = make_pair_order();
 
 struct NprOp {
   unsigned char p1, p2;  // S1 ^ F1, S2 ^ F2: B = A ^ p1, D = C ^ p2
@@ -111,16 +136,16 @@ __device__ __forceinline__ void m3mul_bdag(const c64* a, const c64* b, c64* c) {
     }
 }
 
-__global__ void __launch_bounds__(kNprThreads) npr_kernel(const NprArgs P) {
-  // LDS: 73 728 bytes, reused between phases.
-  //   phases 1-2: propagators [f][A][9] at 0, links [A][mu][9] at 9216, U [A][D][9] at 36864
-  //   phases 3-4: X [A][D][9] at 0, Y [A][D][9] at 36864
-  __shared__ c64 lds[4608];
+__global__ void __launch_bounds__(kNprThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) npr_kernel(const NprArgs P) {
+  // LDS: 74 240 bytes, reused between phases.
+  //   phases 1-2: propagators [f][A][9] at 0, steps [A][mu][9] at 576, U (pair layout) at kPairMats
+  //   phases 3-4: X (pair layout) at 0, Y (pair layout) at kPairMats
+  __shared__ c64 lds[2 * kPairMats];
   c64* Gs = lds;
   c64* Ls = lds + 576;
-  c64* Us = lds + 2304;
+  c64* Us = lds + kPairMats;
   c64* Xs = lds;
-  c64* Ys = lds + 2304;
+  c64* Ys = lds + kPairMats;
 
   const int tid = (int)threadIdx.x;
   const long z = (long)blockIdx.x;
@@ -139,51 +164,64 @@ __global__ void __launch_bounds__(kNprThreads) npr_kernel(const NprArgs P) {
     const long zz = 2 * zc[2] + (A >> 2 & 1), t = 2 * zc[3] + (A >> 3 & 1);
     return x + P.X * (y + P.Y * (zz + P.Z * t));
   };
-  // 1. propagators of the 16 corners (4 x 16 x 9 complex) and the links leaving
-  //    each corner along the directions in which it is the lower end (16 x 4 slots)
+  // 1. propagators of the 16 corners (4 x 16 x 9 complex), and the 32 links inside
+  //    the hypercube, each stored as the forward step from its lower corner and,
+  //    conjugated, as the backward step from its upper corner
   for (int k = tid; k < 576; k += kNprThreads) {
     const int f = k / 144, A = (k / 9) % 16, e = k % 9;
     Gs[k] = P.g[f][lex(A) * 9 + e];
   }
-  for (int k = tid; k < 576; k += kNprThreads) {
-    const int A = k / 36, mu = (k / 9) % 4, e = k % 9;
-    if (!(A >> mu & 1)) Ls[k] = P.thin[(lex(A) * 4 + mu) * 9 + e];
+  for (int k = tid; k < 288; k += kNprThreads) {
+    const int j = k / 9, e = k % 9;
+    const int mu = j >> 3, lo = j & 7;
+    const int A = ((lo >> mu) << (mu + 1)) | (lo & ((1 << mu) - 1));  // bit mu clear
+    const c64 v = P.thin[(lex(A) * 4 + mu) * 9 + e];
+    Ls[(A * 4 + mu) * 9 + e] = v;
+    Ls[((A | 1 << mu) * 4 + mu) * 9 + 3 * (e % 3) + e / 3] = make_double2(v.x, -v.y);
   }
   // 2. U_AD for the pair this thread owns, in rounds of growing distance
-  const int A = tid >> 4, D = tid & 15;
+  const int pr = kPairOrder.p[tid];
+  const int A = pr >> 4, D = pr & 15;
   const int d = __popc(A ^ D);
+  c64* const umine = Us + A * kRow + 9 * D;
   c64 u[9];
   if (d == 0) {
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = make_double2(e % 4 == 0 ? 1.0 : 0.0, 0.0);
 #pragma unroll
-    for (int e = 0; e < 9; ++e) Us[tid * 9 + e] = u[e];
+    for (int e = 0; e < 9; ++e) umine[e] = u[e];
   }
-  for (int round = 1; round <= 4; ++round) {
+  __syncthreads();
+  if (d == 1) {
+    const c64* st = Ls + (A * 4 + (__ffs(A ^ D) - 1)) * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = st[e];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) umine[e] = u[e];
+  }
+  for (int round = 2; round <= 4; ++round) {
     __syncthreads();
     if (d == round) {
       c64 acc[9];
 #pragma unroll
       for (int e = 0; e < 9; ++e) acc[e] = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int mu = 0; mu < 4; ++mu) {
-        if (!((A ^ D) >> mu & 1)) continue;
-        const int A2 = A ^ (1 << mu);
-        const c64* rest = Us + (A2 * 16 + D) * 9;
+      int m = A ^ D;
+      for (int q = 0; q < round; ++q) {
+        const int mu = __ffs(m) - 1;
+        m &= m - 1;
         c64 t[9];
-        if (!(A >> mu & 1)) m3mul(Ls + (A * 4 + mu) * 9, rest, t);  // step +mu: U_mu(z_A)
-        else m3mul_dag(Ls + (A2 * 4 + mu) * 9, rest, t);           // step -mu: U_mu(z_A - mu)^dag
+        m3mul(Ls + (A * 4 + mu) * 9, Us + (A ^ 1 << mu) * kRow + 9 * D, t);
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
           acc[e].x += t[e].x;
           acc[e].y += t[e].y;
         }
       }
-      const double inv = 1.0 / (double)d;
+      const double inv = 1.0 / (double)round;
 #pragma unroll
       for (int e = 0; e < 9; ++e) {
         u[e] = make_double2(acc[e].x * inv, acc[e].y * inv);
-        Us[tid * 9 + e] = u[e];
+        umine[e] = u[e];
       }
     }
   }
@@ -197,84 +235,101 @@ __global__ void __launch_bounds__(kNprThreads) npr_kernel(const NprArgs P) {
     m3mul_dag(Gs + (2 * 16 + A) * 9, u, t);  // G3(A)^dag U_AD
     m3mul(t, Gs + (1 * 16 + D) * 9, ym);    // ... G2(D)
   }
-  __syncthreads();  // everyone is done with the propagators, links and U in LDS
+  __syncthreads();  // everyone is done with the propagators, steps and U in LDS
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    Xs[tid * 9 + e] = xm[e];
-    Ys[tid * 9 + e] = ym[e];
+    Xs[A * kRow + 9 * D + e] = xm[e];
+    Ys[A * kRow + 9 * D + e] = ym[e];
   }
   __syncthreads();
-  // 4. contraction.  Each wave takes 12 items (operator, a1) of a pass of 16
-  //    operators, in 60 of its lanes: lane 5i + s sums the terms k = 16 A + C
-  //    in the s-th of five near-equal ranges of [0, 256) for item i, so all four
-  //    waves (and SIMDs) work; the five partial sums of an item then meet in its
-  //    first lane.
+  // 4. contraction.  Lane l of wave w takes operator 4 w + (l >> 4) of the pass
+  //    and corner A = l & 15.  With C = D ^ p2 and B = A ^ p1 it sums, over D,
+  //    sign * X_AD[a1][a4] Y_CB[a3][a2] into out[a1][a2][a3][a4], one a3 at a
+  //    time (27 outputs).  The 16 lanes of an operator read 16 rows A of X and
+  //    16 entries B of a row C of Y, each in its own LDS banks.
   const int lane = tid & 63, wv = tid >> 6;
-  const int item_w = lane / 5, split = lane - 5 * (lane / 5);
-  const int j = 12 * wv + item_w;  // item of the pass: 48 per pass
-  const int k0 = (split * 256) / 5, k1 = ((split + 1) * 256) / 5;
+  const int Ak = lane & 15;
   for (int pass = 0; pass * kNprOpsPerPass < P.nop; ++pass) {
-    const int opl = pass * kNprOpsPerPass + j / 3;
-    const int a1 = j % 3;
-    const bool act = lane < 60 && opl < P.nop;
-    c64 acc[27];
+    const int opl = pass * kNprOpsPerPass + 4 * wv + (lane >> 4);
+    const bool act = opl < P.nop;
+    NprOp o = {0, 0, 0, 0};
+    if (act) o = P.ops[opl];
+    const int B = Ak ^ o.p1;
+    const double s1 = (o.neg1 >> Ak & 1) ? -1.0 : 1.0;
+    const c64* xrow = Xs + Ak * kRow;
+    double* const out = (double*)(P.out + ((size_t)(P.op0 + (act ? opl : 0)) * P.nz + z) * 81);
+#pragma unroll 1
+    for (int a3 = 0; a3 < 3; ++a3) {
+      double v[54];  // [a1][a2][a4] as (re, im) pairs
 #pragma unroll
-    for (int k = 0; k < 27; ++k) acc[k] = make_double2(0.0, 0.0);
-    if (act) {
-      const NprOp o = P.ops[opl];
-      for (int k = k0; k < k1; ++k) {
-        const int Ai = k >> 4, C = k & 15;
-        const int B = Ai ^ o.p1, Di = C ^ o.p2;
-        const double s = (((o.neg1 >> Ai) ^ (o.neg2 >> C)) & 1) ? -1.0 : 1.0;
-        const c64* xr = Xs + (Ai * 16 + Di) * 9 + 3 * a1;  // X_AD[a1][a4]
-        const c64* yr = Ys + (C * 16 + B) * 9;              // Y_CB[a3][a2]
-        c64 sx[3];
+      for (int k = 0; k < 54; ++k) v[k] = 0.0;
+      if (act) {
+        const c64* ybase = Ys + 9 * B + 3 * a3;
+#pragma unroll 2
+        for (int Dk = 0; Dk < 16; ++Dk) {
+          const int C = Dk ^ o.p2;
+          const double s = (o.neg2 >> C & 1) ? -s1 : s1;
+          c64 xv[9], yv[3];
 #pragma unroll
-        for (int a4 = 0; a4 < 3; ++a4) sx[a4] = make_double2(s * xr[a4].x, s * xr[a4].y);
-        c64 yv[9];
+          for (int e = 0; e < 9; ++e) xv[e] = xrow[9 * Dk + e];  // X_AD[a1][a4]
 #pragma unroll
-        for (int e = 0; e < 9; ++e) yv[e] = yr[e];
+          for (int e = 0; e < 3; ++e) {                           // Y_CB[a3][a2]
+            const c64 y = ybase[C * kRow + e];
+            yv[e] = make_double2(s * y.x, s * y.y);
+          }
 #pragma unroll
-        for (int a2 = 0; a2 < 3; ++a2)
+          for (int a1 = 0; a1 < 3; ++a1)
 #pragma unroll
-          for (int a3 = 0; a3 < 3; ++a3)
+            for (int a2 = 0; a2 < 3; ++a2)
 #pragma unroll
-            for (int a4 = 0; a4 < 3; ++a4) {
-              c64& v = acc[9 * a2 + 3 * a3 + a4];
-              v = cmac(v, sx[a4], yv[3 * a3 + a2]);
-            }
+              for (int a4 = 0; a4 < 3; ++a4) {
+                const int k = 2 * (9 * a1 + 3 * a2 + a4);
+                const c64 a = xv[3 * a1 + a4], b = yv[a2];
+                v[k] = __builtin_fma(a.x, b.x, v[k]);
+                v[k] = __builtin_fma(-a.y, b.y, v[k]);
+                v[k + 1] = __builtin_fma(a.x, b.y, v[k + 1]);
+                v[k + 1] = __builtin_fma(a.y, b.x, v[k + 1]);
+              }
+        }
       }
-    }
-    // the five partial sums of an item into its first lane, in place: lanes 0, 1
-    // of the group add lanes 2, 3; lane 0 adds lane 1, then lane 4 (every lane
-    // takes part in the exchanges; a lane that adds nothing reads itself)
-    const int base = lane < 60 ? lane - split : lane;
-    const int src1 = (lane < 60 && split < 2) ? lane + 2 : lane;
-    const int src2 = (lane < 60 && split == 0) ? base + 1 : lane;
-    const int src3 = (lane < 60 && split == 0) ? base + 4 : lane;
-    const bool g1 = lane < 60 && split < 2, g2 = lane < 60 && split == 0;
+      // the 16 lanes of an operator (lane bits 0..3) add their partial sums by
+      // halving: at each step a lane keeps the lower or upper part of its current
+      // range (by one lane bit), adds the partner's copy of that part and hands
+      // over the other part.  Ranges 54 -> 27 -> 14 -> 7 -> 4 (odd lengths padded
+      // by a zero).
+      const bool u3 = lane & 8, u2 = lane & 4, u1 = lane & 2, u0 = lane & 1;
 #pragma unroll
-    for (int k = 0; k < 27; ++k) {
-      const double pr = __shfl(acc[k].x, src1, 64), pi = __shfl(acc[k].y, src1, 64);
-      acc[k].x += g1 ? pr : 0.0;
-      acc[k].y += g1 ? pi : 0.0;
-    }
+      for (int k = 0; k < 27; ++k) {
+        const double lo = v[k], hi = v[k + 27];
+        v[k] = (u3 ? hi : lo) + __shfl_xor(u3 ? lo : hi, 8, 64);
+      }
 #pragma unroll
-    for (int k = 0; k < 27; ++k) {
-      const double pr = __shfl(acc[k].x, src2, 64), pi = __shfl(acc[k].y, src2, 64);
-      acc[k].x += g2 ? pr : 0.0;
-      acc[k].y += g2 ? pi : 0.0;
-    }
+      for (int k = 0; k < 14; ++k) {
+        const double lo = v[k], hi = k + 14 < 27 ? v[k + 14] : 0.0;
+        v[k] = (u2 ? hi : lo) + __shfl_xor(u2 ? lo : hi, 4, 64);
+      }
 #pragma unroll
-    for (int k = 0; k < 27; ++k) {
-      const double pr = __shfl(acc[k].x, src3, 64), pi = __shfl(acc[k].y, src3, 64);
-      acc[k].x += g2 ? pr : 0.0;
-      acc[k].y += g2 ? pi : 0.0;
-    }
-    if (act && split == 0) {
-      c64* o = P.out + ((size_t)(P.op0 + opl) * P.nz + z) * 81 + 27 * a1;
+      for (int k = 0; k < 7; ++k) {
+        const double lo = v[k], hi = k + 7 < 14 ? v[k + 7] : 0.0;
+        v[k] = (u1 ? hi : lo) + __shfl_xor(u1 ? lo : hi, 2, 64);
+      }
 #pragma unroll
-      for (int k = 0; k < 27; ++k) o[k] = acc[k];
+      for (int k = 0; k < 4; ++k) {
+        const double lo = v[k], hi = k + 4 < 7 ? v[k + 4] : 0.0;
+        v[k] = (u0 ? hi : lo) + __shfl_xor(u0 ? lo : hi, 1, 64);
+      }
+      if (act) {
+        // this lane's 4 entries start at 27 u3 + 14 u2 + 7 u1 + 4 u0 of the 54;
+        // an entry is real where it lies inside every range it was cut from
+        const int o3 = 4 * u0, o2 = 7 * u1 + o3, o1 = 14 * u2 + o2, base = 27 * u3 + o1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (o3 + k < 7 && o2 + k < 14 && o1 + k < 27) {
+            const int q = base + k, jj = q >> 1;  // jj = 9 a1 + 3 a2 + a4
+            const int a1 = jj / 9, a2 = jj / 3 % 3, a4 = jj % 3;
+            out[2 * (27 * a1 + 9 * a2 + 3 * a3 + a4) + (q & 1)] = v[k];
+          }
+      }
     }
   }
 }
