@@ -869,10 +869,11 @@ def run_asqtad(args, asq, torch):
 
 
 # SU(3) products per hypercube of the four-fermion operator that do not depend on the
-# operator: the 256 link averages by their first step (sum over pairs of |A ^ D| = 512)
-# and the two bilinear colour matrices of each pair (4 x 256); and the contraction
-# per operator: 16 x 16 corner pairs x 81 complex multiply-adds (8 flops each).
-NPR_PRODUCTS_PER_HYPERCUBE = 512 + 4 * 256
+# operator: the 256 link averages by their first step (sum over pairs of |A ^ D| = 512,
+# less the 64 pairs at distance 1, whose average is the link itself) and the two
+# bilinear colour matrices of each pair (4 x 256); and the contraction per operator:
+# 16 x 16 corner pairs x 81 complex multiply-adds (8 flops each).
+NPR_PRODUCTS_PER_HYPERCUBE = 448 + 4 * 256
 NPR_FLOPS_PER_OP_HYPERCUBE = 256 * 81 * 8
 
 

@@ -19,6 +19,11 @@ inline bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 // Widest batch whose D_eo launch forms alpha itself instead of a scalar launch
 // (its tiles are then at most kFoldAlphaMaxTile columns wide).
 constexpr int kFoldAlphaCols = kFoldAlphaMaxTile;
+// Most site blocks for which the launches fold alpha and beta in: every block
+// re-reads all nblk partials of its columns, which costs nblk^2 partial reads per
+// launch; up to 4 kBlock blocks a thread loads at most four of them, issued before
+// the hop loop (at 48^3 x 96, 20 736 blocks, a fold would re-read 6.9 GB).
+constexpr int kFoldMaxBlocks = 4 * kBlock;
 
 struct Batch {
   const asq_gauge* g = nullptr;

@@ -260,41 +260,26 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     in[r] = (on[r] && A.in_sel) ? pick_new(A, A.in, A.in_alt, c) : A.in;
   }
   if (!any) return;  // uniform over the block
-  // alpha of each column for the UPDATE epilogue: formed in this launch from the
+  // alpha of each column for the UPDATE epilogue, formed in this launch from the
   // partials for the narrow tiles of small batches (same order and tree as the
-  // scalar kernel), read from the column state otherwise.  Up to 4 kBlock
-  // partials per column, the loads are issued here and summed after the hop
-  // loop, which hides their latency; longer sums are done here.
+  // scalar kernel): up to 4 kBlock partials per column (the launch refuses more),
+  // loaded here and summed after the hop loop, which hides their latency.
   [[maybe_unused]] double alpha[R];
   [[maybe_unused]] double qa[R][4], qb[R][4];
-  [[maybe_unused]] bool deferred = false;
+  [[maybe_unused]] bool fold = false;
   if constexpr (EPI == EPI_UPDATE && R <= kFoldAlphaMaxTile) {
-    if (A.apa) {
-      deferred = A.nblk <= 4 * kBlock;
-      if (deferred) {
+    fold = A.apa != nullptr;
+    if (fold) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double* pa = A.apa + (size_t)(c0 + r) * A.nblk;
-          const double* pb = A.apb + (size_t)(c0 + r) * A.nblk;
+      for (int r = 0; r < R; ++r) {
+        const double* pa = A.apa + (size_t)(c0 + r) * A.nblk;
+        const double* pb = A.apb + (size_t)(c0 + r) * A.nblk;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int k = tid + q * kBlock;
-            const bool in = on[r] && k < A.nblk;
-            qa[r][q] = in ? pa[k] : 0.0;
-            qb[r][q] = in ? pb[k] : 0.0;
-          }
-        }
-      } else {
-        __shared__ double sa[2 * (kBlock / 64 + 1)];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          alpha[r] = 0;
-          if (!on[r]) continue;  // uniform over the block
-          const int c = c0 + r;
-          double pp = strided_sum(A.apa + (size_t)c * A.nblk, A.nblk);
-          double tt = strided_sum(A.apb + (size_t)c * A.nblk, A.nblk);
-          block_sum2_all(pp, tt, sa);
-          on[r] = fold_alpha(A, c, sblk, pp, tt, alpha[r]);  // every block takes the same decision
+        for (int q = 0; q < 4; ++q) {
+          const int k = tid + q * kBlock;
+          const bool in = on[r] && k < A.nblk;
+          qa[r][q] = in ? pa[k] : 0.0;
+          qb[r][q] = in ? pb[k] : 0.0;
         }
       }
     }
@@ -331,7 +316,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     }
   } else {
     if constexpr (EPI == EPI_UPDATE && R <= kFoldAlphaMaxTile) {
-      if (deferred) {
+      if (fold) {
         // the sums of the partials loaded before the hop loop (strided_sum's order)
         __shared__ double sa[2 * (kBlock / 64 + 1)];
 #pragma unroll
@@ -438,8 +423,8 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
 
 template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
 int go(const DslashArgs& a0, int order, bool global_sweep, hipStream_t s) {
-  // alpha is formed in-kernel only by narrow tiles
-  if (a0.apa && R > kFoldAlphaMaxTile) return ASQ_EINVAL;
+  // alpha is formed in-kernel only by narrow tiles, from at most 4 kBlock partials
+  if (a0.apa && (R > kFoldAlphaMaxTile || a0.nblk > 4 * kBlock)) return ASQ_EINVAL;
   DslashArgs a = a0;
   a.ntiles = (a.ncol + R - 1) / R;
   a.sgroup = order_group(order, a.nblk);

@@ -133,10 +133,11 @@ int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, si
   B.link = sloppy_link(g, mode);
   B.sweep = env_flag("ASQ_SWEEP", true);
   // Each D_eo block re-sums 2 x nblk partials per column of its tile, which is
-  // cheap next to the Dslash only for narrow batches.
-  B.fold_alpha = ncol <= kFoldAlphaCols && env_flag("ASQ_FOLD_ALPHA", true);
+  // cheap next to the Dslash only for narrow batches on lattices of at most
+  // kFoldMaxBlocks site blocks.
+  B.fold_alpha = ncol <= kFoldAlphaCols && g->nblk <= kFoldMaxBlocks && env_flag("ASQ_FOLD_ALPHA", true);
   // Likewise each direction-update block re-sums nblk partials of its column.
-  B.fold_beta = ncol <= kFoldAlphaCols && env_flag("ASQ_FOLD_BETA", true);
+  B.fold_beta = ncol <= kFoldAlphaCols && g->nblk <= kFoldMaxBlocks && env_flag("ASQ_FOLD_BETA", true);
   batch_pick_tiles(B);
   return ASQ_OK;
 }

@@ -430,10 +430,10 @@ def test_binding_checks_tensor_sizes(asq):
 @pytest.mark.parametrize("mode,ncol", [("mixed32", 1), ("mixed32", 2), ("f64", 1), ("f64", 2)])
 def test_narrow_batch_beyond_1024_site_blocks(asq, mode, ncol, monkeypatch):
     """Batches of one or two columns form alpha inside D_eo and beta inside the direction
-    update.  Beyond 1024 site blocks (24^3 x 48: 1296 blocks of 256 sites) every D_eo block
-    sums the partials in a loop of its own instead of the loads issued before the hop loop,
-    and the direction update's sum takes several passes.  Both must give the bits of the
-    scalar launches (folds switched off) and the FP64 true residual."""
+    update only up to 1024 site blocks, where every block's re-read of all partials stays
+    small; beyond (24^3 x 48: 1296 blocks of 256 sites) the scalars come from the one-block
+    reduction launches whatever the fold switches say.  Both runs must give the same bits
+    and the FP64 true residual."""
     import torch
 
     dims = (24, 24, 24, 48)
