@@ -397,6 +397,18 @@ def run_single(args, asq, torch):
     g64.close()
     del g64
 
+    # the optional link compression: the FP32 copy stored as 12 reals per link (two rows,
+    # the third rebuilt in the kernel), same solver and tolerance; the bench line keeps
+    # the 18-real links of its configuration
+    g12 = asq.Gauge(dims, fat, lng, precs=("f64", "f32"), recon=12)
+    t_r12, times_r12, r_r12 = solve_series(g12, [mass], bd, "mixed32", w["tol"], 5, 1, stream, work, x)
+    dt_r12 = time_dslash(asq, g12, "f32", 1, max(20, args.dslash_launches // 4), stream)
+    r12_bytes = dslash_bytes_per_site("f32r12", "f32", 1) * half
+    log(f"mixed32 CG on FP32 12-real links: iters={r_r12.stats[0]['iters']} "
+        f"resid={r_r12.stats[0]['true_resid']:.3e} {t_r12 * 1e3:.1f} ms; its FP32 Dslash {dt_r12 * 1e6:.1f} us")
+    g12.close()
+    del g12
+
     # the boundary's host-side costs, outside the timed region: importing the host FP64
     # links (once per gauge field), and a solve whose b starts and whose x ends in pinned
     # host memory (PCIe both ways)
@@ -482,6 +494,10 @@ def run_single(args, asq, torch):
                                   "speedup_vs_f64_cg": t64 / t_l64,
                                   "dslash_us": dt_l64 * 1e6, "dslash_bytes_per_launch": l64_bytes,
                                   "dslash_gbs": l64_bytes / dt_l64 / 1e9},
+        "fp32_12real_links": {"time_to_solution": time_stats(times_r12), "ms": t_r12 * 1e3,
+                              "iterations": r_r12.stats[0]["iters"], "true_resid": r_r12.stats[0]["true_resid"],
+                              "speedup_vs_f64_cg": t64 / t_r12, "dslash_us": dt_r12 * 1e6,
+                              "dslash_bytes_per_launch": r12_bytes, "dslash_gbs": r12_bytes / dt_r12 / 1e9},
         "gauge_import_ms": import_ms,
         "pcie_inclusive_solve_ms": float(np.median(host_ms)),
         "fp16_vectors_iterations": r_other.stats[0]["iters"] if r_other else None,
