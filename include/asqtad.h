@@ -205,12 +205,13 @@ int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, con
 /* The same operator with a caller-chosen launch variant instead of the tuned
    one (for tests that cover every variant and for tuning studies; every
    variant computes the same result, bit for bit).  variant = cols | pipe << 8 |
-   order << 12 | sweep << 15: cols = 1, 2, 4, 8 or 12 columns per thread (12
-   not with FP64 vectors); pipe = 1 for the software-pipelined hop loop;
-   order = 0 walks the column tiles of a site block together, 1, 2, 3 walk
+   chunk << 10 | order << 12 | sweep << 15: cols = 1, 2, 4, 8 or 12 columns per
+   thread (12 not with FP64 vectors); pipe = 1 for the software-pipelined hop
+   loop; order = 0 walks the column tiles of a site block together, 1, 2, 3 walk
    tile by tile inside groups of 16, 64 or all site blocks; sweep = 1 deals
    the blocks to the XCDs round-robin (one sweep front through the lattice)
-   instead of a contiguous slab per XCD.  variant = 0x10000 | 32 | order << 12 selects the matrix-core form
+   instead of a contiguous slab per XCD, chunk = 1, 2, 3 (with sweep only) in
+   runs of 16, 64 or 256 consecutive blocks per XCD instead of single blocks.  variant = 0x10000 | 32 | order << 12 selects the matrix-core form
    (prec F16 with FP32 18-real links only): 32 columns per block, FP32 products
    on the matrix cores.  It rounds differently from the other variants (within
    the FP16 tolerance) and is bitwise reproducible against itself.  Adding

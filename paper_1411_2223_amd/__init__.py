@@ -116,13 +116,15 @@ _lib = None
 ASQ_VARIANT_NATIVE = 0x100000
 
 
-def variant_code(cols: int, pipe: bool = False, order: int = 0, native: bool = False, sweep: bool = False) -> int:
+def variant_code(cols: int, pipe: bool = False, order: int = 0, native: bool = False, sweep: bool = False,
+                 chunk: int = 0) -> int:
     """Launch variant of asqtad_dslash_eo_variant: columns per thread (1, 2, 4, 8, 12), pipelined hop
     loop, block order (0 tiles of a site block adjacent; 1, 2, 3 tile by tile in
-    groups of 16, 64 or all site blocks); sweep: one global sweep instead of a slab per XCD;
+    groups of 16, 64 or all site blocks); sweep: one global sweep instead of a slab per XCD,
+    in which each XCD takes single blocks (chunk 0) or runs of 16, 64, 256 blocks (chunk 1, 2, 3);
     native: vectors in the solvers' native layout."""
-    return (int(cols) | (0x100 if pipe else 0) | (int(order) << 12) | (0x8000 if sweep else 0)
-            | (ASQ_VARIANT_NATIVE if native else 0))
+    return (int(cols) | (0x100 if pipe else 0) | (int(order) << 12)
+            | ((0x8000 | (int(chunk) << 10)) if sweep else 0) | (ASQ_VARIANT_NATIVE if native else 0))
 
 
 def variant_code_mfma(order: int = 0) -> int:
@@ -131,9 +133,9 @@ def variant_code_mfma(order: int = 0) -> int:
     return 0x10000 | 32 | (int(order) << 12) | ASQ_VARIANT_NATIVE
 
 
-# Every launch variant the library builds: (cols, pipe, order, sweep).
-VARIANTS_ALL = [(c, p, o, g) for g in (False, True) for o in (0, 1, 2, 3) for p in (False, True)
-                for c in (1, 2, 4, 8, 12)]
+# Every launch variant the library builds: (cols, pipe, order, sweep, chunk).
+VARIANTS_ALL = [(c, p, o, g, k) for g, ks in ((False, (0,)), (True, (0, 1, 2, 3))) for k in ks
+                for o in (0, 1, 2, 3) for p in (False, True) for c in (1, 2, 4, 8, 12)]
 
 
 def load():

@@ -657,4 +657,16 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return k * q + (k < rem ? k : rem) + j;
 }
 
+// One sweep of the whole lattice in which XCD x takes runs of k consecutive
+// blocks: inside each group of 8 k blocks, block b (on XCD b mod 8) gets
+// position (b mod 8) k + (b div 8) mod k; blocks past the last whole group keep
+// their place.  A permutation of [0, n); k = 1 leaves every block in place.
+__device__ __forceinline__ int sweep_remap(int b, int n, int k) {
+  const int g = 8 * k;
+  const int base = (b / g) * g;
+  if (base + g > n) return b;
+  const int r = b - base;
+  return base + (r & 7) * k + (r >> 3);
+}
+
 }  // namespace asq

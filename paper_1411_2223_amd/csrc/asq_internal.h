@@ -124,7 +124,7 @@ struct DslashArgs {
   double coeff_fat;     // 12-real tiers: fat / long coefficients re-applied in-kernel
   double coeff_long;
   int reverse;          // walk the lattice from the last site block to the first
-  int global_sweep;     // no XCD slab remap (kGlobalSweepBit)
+  int sweep_chunk;      // 0: a contiguous slab per XCD; k >= 1: one sweep, each XCD taking runs of k blocks
 };
 
 // Launch one Dslash.  link_kind / in_kind select the template; out_kind is the
@@ -149,6 +149,16 @@ constexpr int kOrderShift = 12;
 // lattice together and the far-hop (t) neighbour records of the shared front
 // stay in the memory-side cache instead of eight separate fronts.
 constexpr int kGlobalSweepBit = 0x8000;
+// With the global sweep, the XCDs can take runs of k consecutive blocks in turn
+// instead of single blocks (k = 16, 64, 256 for chunk codes 1..3 << kChunkShift):
+// the front still advances through the lattice together, and neighbours a few
+// rows or planes away stay in one XCD's L2.
+constexpr int kChunkShift = 10;
+inline int sweep_chunk_of(int rtile) {
+  if (!(rtile & kGlobalSweepBit)) return 0;
+  const int code = (rtile >> kChunkShift) & 3;
+  return code == 0 ? 1 : (code == 1 ? 16 : (code == 2 ? 64 : 256));
+}
 // The matrix-core form (FP32 18-real links with FP16-with-norm vectors only):
 // kMfmaBit | kMfmaTile | order << kOrderShift, 32 columns per block of sites.
 constexpr int kMfmaBit = 0x10000;
@@ -157,8 +167,9 @@ inline int rtile_order(int rtile) { return (rtile >> kOrderShift) & 3; }
 inline int order_group(int order, int nblk) { return order == 0 ? 0 : (order == 1 ? 16 : (order == 2 ? 64 : nblk)); }
 // Whether the library builds launch variant rtile (for any link and vector tier).
 bool variant_built(int link_kind, int in_kind, int rtile);
-inline int make_rtile(int cols, bool pipe, int order, bool global_sweep = false) {
-  return cols | (pipe ? kPipeBit : 0) | (order << kOrderShift) | (global_sweep ? kGlobalSweepBit : 0);
+inline int make_rtile(int cols, bool pipe, int order, bool global_sweep = false, int chunk_code = 0) {
+  return cols | (pipe ? kPipeBit : 0) | (order << kOrderShift) |
+         (global_sweep ? kGlobalSweepBit | (chunk_code << kChunkShift) : 0);
 }
 // Widest column tile whose UPDATE launch may form alpha itself (DslashArgs::apa).
 constexpr int kFoldAlphaMaxTile = 2;

@@ -229,7 +229,8 @@ __device__ __forceinline__ const void* pick_new(const DslashArgs& A, const void*
 template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   using real = typename InT::real;
-  int lin = A.global_sweep ? (int)blockIdx.x : xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  int lin = A.sweep_chunk > 0 ? sweep_remap((int)blockIdx.x, (int)gridDim.x, A.sweep_chunk)
+                              : xcd_remap((int)blockIdx.x, (int)gridDim.x);
   // Alternate sweeps start on the links the previous sweep read last, which the
   // memory-side cache (MALL) still holds.
   if (A.reverse) lin = (int)gridDim.x - 1 - lin;
@@ -422,13 +423,13 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
 }
 
 template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
-int go(const DslashArgs& a0, int order, bool global_sweep, hipStream_t s) {
+int go(const DslashArgs& a0, int order, int sweep_chunk, hipStream_t s) {
   // alpha is formed in-kernel only by narrow tiles, from at most 4 kBlock partials
   if (a0.apa && (R > kFoldAlphaMaxTile || a0.nblk > 4 * kBlock)) return ASQ_EINVAL;
   DslashArgs a = a0;
   a.ntiles = (a.ncol + R - 1) / R;
   a.sgroup = order_group(order, a.nblk);
-  a.global_sweep = global_sweep ? 1 : 0;
+  a.sweep_chunk = sweep_chunk;
   const long nb = (long)a.nblk * a.ntiles;
   if (nb <= 0) return ASQ_OK;
   if (nb >= (1L << 31)) return ASQ_EINVAL;
@@ -442,7 +443,7 @@ template <class Link, class InT, class OutT, int EPI>
 int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
   const bool pipe = (rtile & kPipeBit) != 0;
   const int ord = rtile_order(rtile);
-  const bool gs = (rtile & kGlobalSweepBit) != 0;
+  const int gs = sweep_chunk_of(rtile);
   switch (rtile & 0xff) {
     case 1: return pipe ? go<Link, InT, OutT, 1, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 1, EPI, false>(a, ord, gs, s);
     case 2: return pipe ? go<Link, InT, OutT, 2, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 2, EPI, false>(a, ord, gs, s);

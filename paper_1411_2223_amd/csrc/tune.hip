@@ -139,13 +139,20 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     ASQ_HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f, best_update_ms = 1e30f;
     // columns per thread x hop-loop form x block order (orders differ only when
-    // there are several tiles) x XCD slabs or one global sweep
+    // there are several tiles) x XCD slabs or one global sweep (of single blocks
+    // or of runs of blocks per XCD)
     std::vector<int> cands;
     for (int gs = 0; gs < 2; ++gs)
       for (int order = 0; order < 4; ++order)
         for (int pipe = 0; pipe < 2; ++pipe)
           for (int cols : {1, 2, 4, 8, 12})
             if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, pipe, order, gs != 0));
+    // runs of 16, 64 or 256 blocks per XCD inside the sweep: pipelined loop, the
+    // first two block orders
+    for (int chunk = 1; chunk <= 3; ++chunk)
+      for (int order = 0; order < 2; ++order)
+        for (int cols : {1, 2, 4, 8, 12})
+          if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, true, order, true, chunk));
     // The solver runs D_oe forwards and D_eo backwards, so each sweep starts on
     // the links and vectors the previous one left in the memory-side cache; the
     // candidates are timed in that pattern (pairs of launches), best of two.

@@ -109,17 +109,40 @@ def test_every_launch_variant(asq, prec, recon):
     assert max_err(got, ref).max() <= MAX_TOL[prec]
     # the same input in the solvers' native layout
     vin_n = g.to_native(vin, prec, nrhs)
-    for cols, pipe, order, sweep in asq.VARIANTS_ALL:
+    for cols, pipe, order, sweep, chunk in asq.VARIANTS_ALL:
         if cols == 12 and prec == "f64":
             continue  # not built for FP64 vectors; refused in test_unbuilt_variant_rejected
-        out = g.dslash(1, vin, prec, nrhs, variant=asq.variant_code(cols, pipe, order, sweep=sweep))
-        out_n = g.dslash(1, vin_n, prec, nrhs, variant=asq.variant_code(cols, pipe, order, native=True, sweep=sweep))
+        out = g.dslash(1, vin, prec, nrhs, variant=asq.variant_code(cols, pipe, order, sweep=sweep, chunk=chunk))
+        out_n = g.dslash(1, vin_n, prec, nrhs,
+                         variant=asq.variant_code(cols, pipe, order, native=True, sweep=sweep, chunk=chunk))
         back = g.from_native(out_n, prec, nrhs)
         torch.cuda.synchronize()
-        v = (cols, pipe, order, sweep)
+        v = (cols, pipe, order, sweep, chunk)
         print(f"prec={prec} recon={recon} variant {v}", flush=True)
         assert torch.equal(out, ref_dev), f"variant {v} differs from the tuned one"
         assert torch.equal(back, ref_dev), f"native variant {v} differs from canonical"
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_sweep_in_runs_of_blocks_matches_slab_order(asq, prec):
+    """At 20^3 x 64 (1000 site blocks) with 8 columns, sweeps in which each XCD takes runs
+    of 16, 64 or 256 blocks cover several whole groups of 8 runs and a ragged tail: every
+    block order must give the bits of the slab order."""
+    import torch
+
+    dims = (20, 20, 20, 64)
+    g, fat, lng = _gauge(asq, dims, 0.3, 5, 18)
+    nrhs = 8
+    vin_n = g.to_native(asq.vec_to_device(synth.make_sources(dims, nrhs, 79), prec), prec, nrhs)
+    for cols in (1, 4, 8):
+        for order in (0, 1):
+            ref = g.dslash(1, vin_n, prec, nrhs, variant=asq.variant_code(cols, True, order, native=True))
+            for chunk in (0, 1, 2, 3):
+                got = g.dslash(1, vin_n, prec, nrhs,
+                               variant=asq.variant_code(cols, True, order, native=True, sweep=True, chunk=chunk))
+                torch.cuda.synchronize()
+                print(f"sweep prec={prec} cols={cols} order={order} chunk={chunk}", flush=True)
+                assert torch.equal(got, ref), f"sweep in runs differs: cols={cols} order={order} chunk={chunk}"
 
 
 def test_unbuilt_variant_rejected(asq):
@@ -127,7 +150,8 @@ def test_unbuilt_variant_rejected(asq):
     dims = (4, 4, 4, 8)
     g, fat, lng = _gauge(asq, dims, 0.3, 14112223, 18)
     vin = asq.vec_to_device(synth.make_sources(dims, 8, 1), "f64")
-    for bad in (3, 16, asq.variant_code(4) | (1 << 14), asq.variant_code(12), asq.variant_code(12, True, 2)):
+    for bad in (3, 16, asq.variant_code(4) | (1 << 14), asq.variant_code(4) | (1 << 10), asq.variant_code(12),
+                asq.variant_code(12, True, 2)):
         with pytest.raises(asq.AsqError) as e:
             g.dslash(1, vin, "f64", 8, variant=bad)
         assert e.value.code == asq.ASQ_EINVAL
