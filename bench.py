@@ -171,7 +171,7 @@ def copy_bandwidth(asq, stream, nbytes=1 << 30, reps=10):
     return 2 * nbytes / dt / 1e9
 
 
-def read_bandwidth(asq, stream, nbytes=1 << 30, reps=10):
+def read_bandwidth(asq, stream, nbytes=4 << 30, reps=10):
     """Read-only GB/s of the library's read probe on a buffer far beyond the 256 MB MALL."""
     import torch
 

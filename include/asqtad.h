@@ -205,9 +205,10 @@ int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, con
 /* The same operator with a caller-chosen launch variant instead of the tuned
    one (for tests that cover every variant and for tuning studies; every
    variant computes the same result, bit for bit).  variant = cols | pipe << 8 |
-   chunk << 10 | order << 12 | sweep << 15: cols = 1, 2, 4, 8 or 12 columns per
-   thread (12 not with FP64 vectors); pipe = 1 for the software-pipelined hop
-   loop; order = 0 walks the column tiles of a site block together, 1, 2, 3 walk
+   stream << 9 | chunk << 10 | order << 12 | sweep << 15: cols = 1, 2, 4, 8 or 12
+   columns per thread (12 not with FP64 vectors); pipe = 1 for the
+   software-pipelined hop loop; stream = 1 (one column, FP32 and 16-bit link
+   tiers only) reads the links with non-temporal loads; order = 0 walks the column tiles of a site block together, 1, 2, 3 walk
    tile by tile inside groups of 16, 64 or all site blocks; sweep = 1 deals
    the blocks to the XCDs round-robin (one sweep front through the lattice)
    instead of a contiguous slab per XCD, chunk = 1, 2, 3 (with sweep only) in
@@ -392,9 +393,10 @@ const char* asq_last_error(void);
    bandwidth and hardware counters. */
 int asq_copy_probe(void* dst_dev, const void* src_dev, size_t n, void* hip_stream);
 /* HBM read probe: reads n bytes of src (n a multiple of 16, 16-byte aligned)
-   and writes one 16-byte XOR digest per block to sink_dev (at least
-   asq_read_probe_blocks(n) x 16 bytes), asynchronous.  The read-only ceiling
-   against which a read-dominated kernel such as the Dslash is measured. */
+   with non-temporal loads, eight in flight per thread, and writes one 16-byte
+   XOR digest per block to sink_dev (at least asq_read_probe_blocks(n) x 16
+   bytes), asynchronous.  The read-only ceiling against which a read-dominated
+   kernel such as the Dslash is measured. */
 int asq_read_probe(const void* src_dev, size_t n, void* sink_dev, void* hip_stream);
 size_t asq_read_probe_blocks(size_t n);
 

@@ -313,6 +313,18 @@ struct LinkF32R18 {
     }
     return U;
   }
+  __device__ __forceinline__ static Mat3<float> load_streaming(const void* base, int half, int p, int slot, int i) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2* q = reinterpret_cast<const f2*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    Mat3<float> U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const f2 v = __builtin_nontemporal_load(q + (size_t)k * half);
+      U.e[k / 3][k % 3].re = v.x;
+      U.e[k / 3][k % 3].im = v.y;
+    }
+    return U;
+  }
 };
 
 struct LinkF32R12 {
@@ -326,6 +338,22 @@ struct LinkF32R12 {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float4 v = q[(size_t)k * half];
+      const int e0 = 2 * k, e1 = 2 * k + 1;
+      U.e[e0 / 3][e0 % 3].re = v.x;
+      U.e[e0 / 3][e0 % 3].im = v.y;
+      U.e[e1 / 3][e1 % 3].re = v.z;
+      U.e[e1 / 3][e1 % 3].im = v.w;
+    }
+    reconstruct_row2(U);
+    return U;
+  }
+  __device__ __forceinline__ static Mat3<float> load_streaming(const void* base, int half, int p, int slot, int i) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4* q = reinterpret_cast<const f4*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    Mat3<float> U;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const f4 v = __builtin_nontemporal_load(q + (size_t)k * half);
       const int e0 = 2 * k, e1 = 2 * k + 1;
       U.e[e0 / 3][e0 % 3].re = v.x;
       U.e[e0 / 3][e0 % 3].im = v.y;
@@ -358,6 +386,33 @@ struct LinkI16R12 {
     }
     reconstruct_row2(U);
     return U;
+  }
+  __device__ __forceinline__ static Mat3<float> load_streaming(const void* base, int half, int p, int slot, int i) {
+    typedef short s4 __attribute__((ext_vector_type(4)));
+    const s4* q = reinterpret_cast<const s4*>(base) + (size_t)((p * 8 + slot) * NCH) * half + i;
+    constexpr float inv = 1.0f / 32767.0f;
+    Mat3<float> U;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const s4 v = __builtin_nontemporal_load(q + (size_t)k * half);
+      const int e0 = 2 * k, e1 = 2 * k + 1;
+      U.e[e0 / 3][e0 % 3].re = (float)v.x * inv;
+      U.e[e0 / 3][e0 % 3].im = (float)v.y * inv;
+      U.e[e1 / 3][e1 % 3].re = (float)v.z * inv;
+      U.e[e1 / 3][e1 % 3].im = (float)v.w * inv;
+    }
+    reconstruct_row2(U);
+    return U;
+  }
+};
+
+// A link tier read with non-temporal loads (one-column launches on lattices whose
+// links cannot stay in the memory-side cache: streaming them leaves it to the
+// neighbour vectors).  Same values, same arithmetic.
+template <class L>
+struct Streamed : L {
+  __device__ __forceinline__ static Mat3<typename L::real> load(const void* base, int half, int p, int slot, int i) {
+    return L::load_streaming(base, half, p, slot, i);
   }
 };
 

@@ -143,6 +143,9 @@ int launch_dslash_f64f32(int in_kind, int epi, int rtile, const DslashArgs& a, h
 // 0 the tiles of a site block adjacent; 1, 2, 3 tile by tile inside groups of
 // 16, 64 or all site blocks.
 constexpr int kPipeBit = 0x100;
+// One-column launches of the FP32 and 16-bit link tiers: links read with
+// non-temporal loads (the FP64-stored tiers always stream at one column).
+constexpr int kStreamBit = 0x200;
 constexpr int kOrderShift = 12;
 // Global sweep: blocks go to the XCDs round-robin in dispatch order instead of
 // each XCD walking a contiguous slab, so the eight XCDs advance through the
@@ -167,8 +170,9 @@ inline int rtile_order(int rtile) { return (rtile >> kOrderShift) & 3; }
 inline int order_group(int order, int nblk) { return order == 0 ? 0 : (order == 1 ? 16 : (order == 2 ? 64 : nblk)); }
 // Whether the library builds launch variant rtile (for any link and vector tier).
 bool variant_built(int link_kind, int in_kind, int rtile);
-inline int make_rtile(int cols, bool pipe, int order, bool global_sweep = false, int chunk_code = 0) {
-  return cols | (pipe ? kPipeBit : 0) | (order << kOrderShift) |
+inline int make_rtile(int cols, bool pipe, int order, bool global_sweep = false, int chunk_code = 0,
+                      bool stream = false) {
+  return cols | (pipe ? kPipeBit : 0) | (stream ? kStreamBit : 0) | (order << kOrderShift) |
          (global_sweep ? kGlobalSweepBit | (chunk_code << kChunkShift) : 0);
 }
 // Widest column tile whose UPDATE launch may form alpha itself (DslashArgs::apa).

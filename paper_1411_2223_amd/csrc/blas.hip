@@ -199,18 +199,27 @@ __global__ void __launch_bounds__(256) copy_kernel(uint4* __restrict__ dst, cons
   for (; k < n; k += stride) dst[k] = src[k];
 }
 
-// XOR of the 16-byte words src[k], k = thread, thread + stride, ...; four loads
-// in flight per thread; one digest per block (so the reads cannot be dropped).
+// XOR of the 16-byte words src[k], k = thread, thread + stride, ...; eight
+// non-temporal loads in flight per thread (measured on MI355X over 4 GiB: 7.0 TB/s,
+// against 5.3-6.0 TB/s with four ordinary loads per thread and fewer blocks); one
+// digest per block (so the reads cannot be dropped).
 __global__ void __launch_bounds__(256) read_kernel(const uint4* __restrict__ src, size_t n, uint4* sink) {
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+  const u4v* s4 = reinterpret_cast<const u4v*>(src);
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint4 acc = make_uint4(0, 0, 0, 0);
-  for (; k + 3 * stride < n; k += 4 * stride) {
-    const uint4 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
-    acc.x ^= a.x ^ b.x ^ c.x ^ d.x;
-    acc.y ^= a.y ^ b.y ^ c.y ^ d.y;
-    acc.z ^= a.z ^ b.z ^ c.z ^ d.z;
-    acc.w ^= a.w ^ b.w ^ c.w ^ d.w;
+  for (; k + 7 * stride < n; k += 8 * stride) {
+    u4v v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(s4 + k + u * stride);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      acc.x ^= v[u].x;
+      acc.y ^= v[u].y;
+      acc.z ^= v[u].z;
+      acc.w ^= v[u].w;
+    }
   }
   for (; k < n; k += stride) {
     const uint4 a = src[k];
@@ -301,8 +310,8 @@ extern "C" int asq_copy_probe(void* dst_dev, const void* src_dev, size_t n, void
 
 extern "C" size_t asq_read_probe_blocks(size_t n) {
   const size_t n16 = n / 16;
-  size_t blocks = (n16 + 1023) / 1024;
-  return blocks > 4096 ? 4096 : (blocks ? blocks : 1);
+  size_t blocks = (n16 + 2047) / 2048;
+  return blocks > 16384 ? 16384 : (blocks ? blocks : 1);
 }
 
 extern "C" int asq_read_probe(const void* src_dev, size_t n, void* sink_dev, void* hip_stream) {

@@ -444,6 +444,17 @@ int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
   const bool pipe = (rtile & kPipeBit) != 0;
   const int ord = rtile_order(rtile);
   const int gs = sweep_chunk_of(rtile);
+  if (rtile & kStreamBit) {
+    // links streamed past the caches: one column, FP32 and 16-bit tiers (the
+    // FP64-stored tiers always stream at one column)
+    if constexpr (std::is_same<Link, LinkF64R18>::value || std::is_same<Link, LinkF64F32>::value) {
+      return ASQ_EINVAL;
+    } else {
+      if ((rtile & 0xff) != 1) return ASQ_EINVAL;
+      return pipe ? go<Streamed<Link>, InT, OutT, 1, EPI, true>(a, ord, gs, s)
+                  : go<Streamed<Link>, InT, OutT, 1, EPI, false>(a, ord, gs, s);
+    }
+  }
   switch (rtile & 0xff) {
     case 1: return pipe ? go<Link, InT, OutT, 1, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 1, EPI, false>(a, ord, gs, s);
     case 2: return pipe ? go<Link, InT, OutT, 2, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 2, EPI, false>(a, ord, gs, s);

@@ -153,6 +153,12 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
       for (int order = 0; order < 2; ++order)
         for (int cols : {1, 2, 4, 8, 12})
           if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, true, order, true, chunk));
+    // one-column tiles with streamed links, where the tier has that form
+    {
+      const size_t n = cands.size();
+      for (size_t q = 0; q < n; ++q)
+        if ((cands[q] & 0xff) == 1 && variant_built(link, in, cands[q] | kStreamBit)) cands.push_back(cands[q] | kStreamBit);
+    }
     // The solver runs D_oe forwards and D_eo backwards, so each sweep starts on
     // the links and vectors the previous one left in the memory-side cache; the
     // candidates are timed in that pattern (pairs of launches), best of two.

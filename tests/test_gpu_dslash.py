@@ -145,6 +145,29 @@ def test_sweep_in_runs_of_blocks_matches_slab_order(asq, prec):
                 assert torch.equal(got, ref), f"sweep in runs differs: cols={cols} order={order} chunk={chunk}"
 
 
+@pytest.mark.parametrize("prec,recon", [("f32", 18), ("f32", 12), ("f16", 12), ("f16", 18)])
+def test_streamed_links_match(asq, prec, recon):
+    """One-column launches that read their links with non-temporal loads (FP32 18- and
+    12-real, 16-bit 12-real tiers) give the bits of ordinary loads, in every sweep form."""
+    import torch
+
+    dims = (20, 20, 20, 64)
+    g, fat, lng = _gauge(asq, dims, 0.3, 5, recon)
+    vin_n = g.to_native(asq.vec_to_device(synth.make_sources(dims, 1, 80), prec), prec, 1)
+    for pipe in (False, True):
+        for sweep, chunk in ((False, 0), (True, 0), (True, 2)):
+            ref = g.dslash(1, vin_n, prec, 1, variant=asq.variant_code(1, pipe, 0, native=True, sweep=sweep,
+                                                                        chunk=chunk))
+            got = g.dslash(1, vin_n, prec, 1, variant=asq.variant_code(1, pipe, 0, native=True, sweep=sweep,
+                                                                        chunk=chunk, stream=True))
+            torch.cuda.synchronize()
+            print(f"streamed links prec={prec} recon={recon} pipe={pipe} sweep={sweep} chunk={chunk}", flush=True)
+            assert torch.equal(got, ref)
+    # wider tiles and the FP64-stored tiers have no streamed form
+    with pytest.raises(asq.AsqError):
+        g.dslash(1, vin_n, prec, 1, variant=asq.variant_code(2, True, 0, native=True, stream=True))
+
+
 def test_unbuilt_variant_rejected(asq):
     # codes outside the documented set are refused without launching
     dims = (4, 4, 4, 8)
