@@ -14,6 +14,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -101,7 +102,7 @@ COPY_KERNEL = "copy_kernel"
 COPY_BYTES = 1 << 30
 
 
-def write_counters(fetch_csv: str, write_csv: str, lattice: str = "20x20x20x64") -> None:
+def write_counters(fetch_csv: str, write_csv: str, lattice: str = "20x20x20x64", tune_cache: str = "") -> None:
     """profiles/dslash_counters_<lattice>.json (read by bench.py) and its Markdown summary."""
     spec = KERNELS_ONLY[lattice]
     fetch = counter_means(fetch_csv, "FETCH_SIZE", by_grid=True)
@@ -124,8 +125,10 @@ def write_counters(fetch_csv: str, write_csv: str, lattice: str = "20x20x20x64")
 
     def find(prefix, ncol=0):
         # the launch variant the timed loop used: among launches over ncol columns
-        # (grid = site blocks x column tiles), the one with the most dispatches
-        hits = [(k, g) for (k, g) in fetch if short_name(k).startswith(prefix) and is_plain(k)
+        # (grid = site blocks x column tiles), the one with the most dispatches; a
+        # link tier read with streaming loads counts as that tier
+        hits = [(k, g) for (k, g) in fetch
+                if re.sub(r"Streamed<(\w+)>", r"\1", short_name(k)).startswith(prefix) and is_plain(k)
                 and (ncol == 0 or g == nblk * 256 * -(-ncol // tile(k)))]
         if not hits:
             raise KeyError(prefix)
@@ -144,11 +147,16 @@ def write_counters(fetch_csv: str, write_csv: str, lattice: str = "20x20x20x64")
                         "kernel": short_name(k[0]), "grid_threads": k[1]}
     wl = "" if spec["workload"] == "single_20x20x20x64" else f"--workload {spec['workload']} "
     # each pass wrote its CSV into the directory given to -d
-    cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {os.path.dirname(fetch_csv)} -o k -- "
-            f"python -u bench.py {wl}--kernels-only",
-            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {os.path.dirname(write_csv)} -o k -- "
-            f"python -u bench.py {wl}--kernels-only",
-            f"python -m paper_1411_2223_amd.profiling write-counters {fetch_csv} {write_csv} --lattice {lattice}"]
+    # with a tune cache, an unprofiled run picks the launch variants first and both
+    # counter passes take them from the file (no timing under the profiler)
+    env = f"ASQ_TUNE_CACHE={tune_cache} " if tune_cache else ""
+    cmds = ([f"{env}python -u bench.py {wl}--kernels-only"] if tune_cache else []) + [
+        f"{env}rocprofv3 --pmc FETCH_SIZE --output-format csv -d {os.path.dirname(fetch_csv)} -o k -- "
+        f"python -u bench.py {wl}--kernels-only",
+        f"{env}rocprofv3 --pmc WRITE_SIZE --output-format csv -d {os.path.dirname(write_csv)} -o k -- "
+        f"python -u bench.py {wl}--kernels-only",
+        f"python -m paper_1411_2223_amd.profiling write-counters {fetch_csv} {write_csv} --lattice {lattice}"
+        + (f" --tune-cache {tune_cache}" if tune_cache else "")]
     out = {"kernel_source_sha": h, "lattice": lattice, "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
            "calibration": {"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES,
                            "copy_FETCH_SIZE_KiB": fetch[copy][1], "copy_WRITE_SIZE_KiB": write[copy][1]},
@@ -160,7 +168,9 @@ def write_counters(fetch_csv: str, write_csv: str, lattice: str = "20x20x20x64")
     lines += ["    " + c for c in cmds]
     lines += ["", f"Kernel sources hash (`python -m paper_1411_2223_amd.profiling hash`): `{h}`", "",
               "Each row averages the timed launches of the variant the autotuner chose (the last",
-              "dispatches of that kernel and grid; the tuner's trial launches come first).", "",
+              "dispatches of that kernel and grid; the tuner's trial launches come first)"
+              + (", taken by both passes from the tune cache of the unprofiled first run." if tune_cache else "."),
+              "",
               f"Calibration with the plain copy kernel (`asq_copy_probe`, {COPY_BYTES >> 30} GiB read + "
               f"{COPY_BYTES >> 30} GiB written): FETCH_SIZE = {fetch[copy][1]:.1f} KiB, WRITE_SIZE = "
               f"{write[copy][1]:.1f} KiB per dispatch, so bytes = 1024 x ({ff:.4f} x FETCH_SIZE + {wf:.4f} x "
@@ -235,12 +245,32 @@ def write_valu(counter_csv: str, trace_csv: str, out: str, command: str, lattice
         f.write("\n".join(lines) + "\n")
 
 
-def write_stats(stats_csv: str, log: str, out: str, title: str, command: str, top: int = 14, note: str = "") -> None:
+def launches_by_grid(trace_csv: str, kernel: str) -> dict:
+    """grid size in work-items -> (launches, mean, min, max duration in us) of the kernel
+    whose short name is `kernel`, from a rocprofv3 kernel_trace.csv."""
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        if short_name(r["Kernel_Name"]) != kernel:
+            continue
+        acc[int(r["Grid_Size_X"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return {g: (len(v), sum(v) / len(v), min(v), max(v)) for g, v in sorted(acc.items())}
+
+
+def write_stats(stats_csv: str, log: str, out: str, title: str, command: str, top: int = 14, note: str = "",
+                focus: str = "") -> None:
     bench = [l.rstrip() for l in open(log) if l.startswith("[bench]")]
     lines = [f"# {title}", "", "Command (repository root, MI355X box):", "", "    " + command,
              f"    python -m paper_1411_2223_amd.profiling stats {stats_csv} --top {top}", ""]
     if note:
         lines += [note, ""]
+    if focus:
+        trace = stats_csv.replace("_kernel_stats.csv", "_kernel_trace.csv")
+        lines += [f"Launches of `{focus}` by grid size (work-items), from the kernel trace of the same run",
+                  f"(`python -m paper_1411_2223_amd.profiling grid {trace} '{focus}'`):", "",
+                  "| grid | launches | avg us | min us | max us |", "|---|---|---|---|---|"]
+        for g, (n, avg, lo, hi) in launches_by_grid(trace, focus).items():
+            lines.append(f"| {g} | {n} | {avg:.2f} | {lo:.2f} | {hi:.2f} |")
+        lines.append("")
     lines += ["Template arguments of `dslash_kernel`: link tier, input tier, output (or residual) tier, columns",
               "per thread, epilogue (0 plain, 1 |out|^2, 2 update of r and x, 3 FP64 residual), software-pipelined",
               "hop loop.  Minimum durations near 1 us are masked no-op launches (columns that are converged or",
@@ -264,6 +294,7 @@ def main():
     s4.add_argument("fetch_csv")
     s4.add_argument("write_csv")
     s4.add_argument("--lattice", default="20x20x20x64", choices=sorted(KERNELS_ONLY))
+    s4.add_argument("--tune-cache", default="", help="the ASQ_TUNE_CACHE file the passes shared")
     s5 = sub.add_parser("write-stats")
     s5.add_argument("csv")
     s5.add_argument("log")
@@ -272,6 +303,10 @@ def main():
     s5.add_argument("--command", required=True)
     s5.add_argument("--note", default="")
     s5.add_argument("--top", type=int, default=14)
+    s5.add_argument("--focus", default="", help="a kernel's short name: its launches by grid size")
+    s7 = sub.add_parser("grid")
+    s7.add_argument("trace_csv")
+    s7.add_argument("kernel")
     s6 = sub.add_parser("write-valu")
     s6.add_argument("counter_csv")
     s6.add_argument("trace_csv")
@@ -283,10 +318,14 @@ def main():
         write_valu(a.counter_csv, a.trace_csv, a.out, a.command, a.lattice)
         return
     if a.cmd == "write-counters":
-        write_counters(a.fetch_csv, a.write_csv, a.lattice)
+        write_counters(a.fetch_csv, a.write_csv, a.lattice, a.tune_cache)
         return
     if a.cmd == "write-stats":
-        write_stats(a.csv, a.log, a.out, a.title, a.command, a.top, a.note)
+        write_stats(a.csv, a.log, a.out, a.title, a.command, a.top, a.note, a.focus)
+        return
+    if a.cmd == "grid":
+        for g, (n, avg, lo, hi) in launches_by_grid(a.trace_csv, a.kernel).items():
+            print(f"grid {g}: {n} launches, avg {avg:.2f} us, min {lo:.2f}, max {hi:.2f}")
         return
     if a.cmd == "stats":
         print(stats_table(a.csv, a.top))
