@@ -64,7 +64,9 @@ int next_mode(int mode);
 int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, size_t bytes, const double* b,
                 double* x);
 void batch_pick_tiles(Batch& B);
-int batch_tune(Batch& B, hipStream_t s);
+// Tune the batch's Dslash launches (trial data: B.b, which trial_b first fills
+// with hashed values for a batch whose b holds nothing yet).
+int batch_tune(Batch& B, hipStream_t s, bool trial_b = false);
 int enqueue_init(const Batch& B, int c0, int n, hipStream_t s);
 int enqueue_iteration(const Batch& B, hipStream_t s);
 int enqueue_iteration(const Batch& B, hipStream_t s, ColState* in, ColState* out, bool defer_beta);

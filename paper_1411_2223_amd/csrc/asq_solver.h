@@ -25,6 +25,8 @@ struct VecArgs {
 };
 
 int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hipStream_t s);
+// x[0..n) = hashed values in [-1, 1) (trial data for the autotuner).
+int fill_trial_values(double* x, size_t n, hipStream_t s);
 int launch_reduce(int op, ColState* st, const double* pa, const double* pb, int nblk, int ncol, hipStream_t s,
                   ColState* dst = nullptr);
 

@@ -8,6 +8,8 @@
 // depends on the other columns of the batch.
 #include <math.h>
 
+#include <algorithm>
+
 #include "asq_reduce.h"
 #include "asq_solver.h"
 
@@ -268,7 +270,27 @@ int launch_vec(int which, const VecArgs& a, int ncol, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }
 
+// Values in [-1, 1) from a hash of the element index (the finaliser of
+// SplitMix64): stand-in data for the autotuner's trial launches where a batch
+// holds no caller data yet.
+__global__ void __launch_bounds__(256) fill_trial_kernel(double* __restrict__ x, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    uint64_t z = (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[k] = (double)(int64_t)z * 0x1p-63;
+  }
+}
+
 }  // namespace
+
+int fill_trial_values(double* x, size_t n, hipStream_t s) {
+  if (n == 0) return ASQ_OK;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
+  fill_trial_kernel<<<(unsigned)blocks, 256, 0, s>>>(x, n);
+  return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
+}
 
 int launch_vec_kernel(int which, int pt, int rt, const VecArgs& a, int ncol, hipStream_t s) {
   if (pt == VEC_F64 && rt == VEC_F64) return launch_vec<VecF64, VecF64>(which, a, ncol, s);

@@ -546,7 +546,7 @@ void tune_fields(asq_server* S) {
         if (!S->arena.alloc(need, &off)) continue;
         Batch B;
         if (batch_carve(B, g, w, mode, S->arena.base + off, need, nullptr, nullptr) == ASQ_OK)
-          (void)batch_tune(B, st);
+          (void)batch_tune(B, st, true);
         (void)hipStreamSynchronize(st);
         S->arena.release(off, need);
       }

@@ -152,11 +152,24 @@ void batch_pick_tiles(Batch& B) {
 
 // Autotune the batch's Dslash launches on its own buffers (p -> t, x -> t64),
 // before the buffers hold solver data.
-int batch_tune(Batch& B, hipStream_t s) {
-  int rc = tune_dslash(B.g, B.link, B.pt, B.ncol, B.p, B.t, s);
-  if (rc) return rc;
-  rc = tune_dslash(B.g, LINK_F64_R18, VEC_F64, B.ncol, B.x, B.t64, s);
-  if (rc) return rc;
+int batch_tune(Batch& B, hipStream_t s, bool trial_b) {
+  // The trial launches read the sources, and the sloppy ones the sources
+  // converted to the direction tier in the direction buffer (the start of the
+  // solve overwrites it).  A fresh workspace often holds zeros, on which a
+  // many-column Dslash draws less power and runs faster than on a solve's data
+  // (about 9 % at 96 columns), which biased the timings and the choice.
+  const size_t n = (size_t)B.ncol * B.g->geom.half;
+  const bool lo = tune_pending(B.g, B.link, B.pt, B.ncol);
+  const bool hi = tune_pending(B.g, LINK_F64_R18, VEC_F64, B.ncol);
+  int rc;
+  if ((lo || hi) && trial_b && (rc = fill_trial_values(B.b, n * 6, s))) return rc;
+  const void* lo_in = B.b;
+  if (lo && B.pt != VEC_F64) {
+    if ((rc = asq_vec_convert(n, ASQ_F64, B.b, B.pt == VEC_F32 ? ASQ_F32 : ASQ_F16, B.p, s))) return rc;
+    lo_in = B.p;
+  }
+  if ((rc = tune_dslash(B.g, B.link, B.pt, B.ncol, lo_in, B.t, s))) return rc;
+  if ((rc = tune_dslash(B.g, LINK_F64_R18, VEC_F64, B.ncol, B.b, B.t64, s))) return rc;
   batch_pick_tiles(B);
   return ASQ_OK;
 }

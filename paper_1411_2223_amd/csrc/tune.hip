@@ -105,6 +105,15 @@ int tuned_rtile(const asq_gauge* g, int link, int in, int out, int epi, int ncol
   return default_rtile(link, ncol);
 }
 
+// True when tune_dslash would time candidates for this configuration (timing
+// on, no recorded winner), so the caller can put trial data in place first.
+bool tune_pending(const asq_gauge* g, int link, int in, int ncol, int epi_timed) {
+  if (!tuning_on()) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_cache_locked();
+  return g_cache.count(key_of(g, link, in, in, epi_timed, ncol)) == 0;
+}
+
 // Time the PLAIN Dslash (the loop shared by every epilogue) for each tile on
 // in_buf -> out_buf and record the winner for every epilogue; with
 // epi = EPI_CANON, time and record the public operator on the canonical
