@@ -64,6 +64,9 @@ int next_mode(int mode);
 int batch_carve(Batch& B, const asq_gauge* g, int ncol, int mode, void* work, size_t bytes, const double* b,
                 double* x);
 void batch_pick_tiles(Batch& B);
+// Whether tune_dslash (tune.hip) would time this configuration (false once a
+// winner is recorded, or with timing off).
+bool tune_pending(const asq_gauge* g, int link_kind, int in_kind, int ncol, int epi_timed = EPI_PLAIN);
 // Tune the batch's Dslash launches (trial data: B.b, which trial_b first fills
 // with hashed values for a batch whose b holds nothing yet).
 int batch_tune(Batch& B, hipStream_t s, bool trial_b = false);

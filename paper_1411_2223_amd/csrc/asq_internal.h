@@ -185,8 +185,5 @@ int tuned_rtile(const asq_gauge* g, int link_kind, int in_kind, int out_kind, in
 // or EPI_CANON (the public operator); persist: also write the ASQ_TUNE_CACHE file.
 int tune_dslash(const asq_gauge* g, int link_kind, int in_kind, int ncol, const void* in_buf, void* out_buf,
                 hipStream_t s, int epi_timed = EPI_PLAIN, bool persist = true);
-// Whether tune_dslash would time this configuration (false once a winner is
-// recorded, or with timing off).
-bool tune_pending(const asq_gauge* g, int link_kind, int in_kind, int ncol, int epi_timed = EPI_PLAIN);
 
 }  // namespace asq
