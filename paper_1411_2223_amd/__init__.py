@@ -118,7 +118,7 @@ ASQ_VARIANT_NATIVE = 0x100000
 
 def variant_code(cols: int, pipe: bool = False, order: int = 0, native: bool = False, sweep: bool = False,
                  chunk: int = 0, stream: bool = False) -> int:
-    """Launch variant of asqtad_dslash_eo_variant: columns per thread (1, 2, 4, 8, 12), pipelined hop
+    """Launch variant of asqtad_dslash_eo_variant: columns per thread (1, 2, 4, 6, 8, 12), pipelined hop
     loop, block order (0 tiles of a site block adjacent; 1, 2, 3 tile by tile in
     groups of 16, 64 or all site blocks); sweep: one global sweep instead of a slab per XCD,
     in which each XCD takes single blocks (chunk 0) or runs of 16, 64, 256 blocks (chunk 1, 2, 3);
@@ -136,7 +136,7 @@ def variant_code_mfma(order: int = 0) -> int:
 
 # Every launch variant the library builds: (cols, pipe, order, sweep, chunk).
 VARIANTS_ALL = [(c, p, o, g, k) for g, ks in ((False, (0,)), (True, (0, 1, 2, 3))) for k in ks
-                for o in (0, 1, 2, 3) for p in (False, True) for c in (1, 2, 4, 8, 12)]
+                for o in (0, 1, 2, 3) for p in (False, True) for c in (1, 2, 4, 6, 8, 12)]
 
 
 def load():

@@ -138,7 +138,7 @@ int launch_dslash_f32r12(int in_kind, int epi, int rtile, const DslashArgs& a, h
 int launch_dslash_i16r12(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
 int launch_dslash_f64f32(int in_kind, int epi, int rtile, const DslashArgs& a, hipStream_t s);
 // (each also takes epi = EPI_CANON: the PLAIN operator on canonical layouts)
-// Launch variant code: columns per thread (1, 2, 4, 8, 12) in the low byte,
+// Launch variant code: columns per thread (1, 2, 4, 6, 8, 12) in the low byte,
 // kPipeBit for the software-pipelined hop loop, and the block order << kOrderShift:
 // 0 the tiles of a site block adjacent; 1, 2, 3 tile by tile inside groups of
 // 16, 64 or all site blocks.

@@ -16,7 +16,7 @@ bool variant_built(int link_kind, int in_kind, int rtile) {
   if ((rtile & (3 << kChunkShift)) && !(rtile & kGlobalSweepBit)) return false;  // runs only within a sweep
   // streamed links: one column, and not the FP64-stored tiers (which always stream there)
   if ((rtile & kStreamBit) && (cols != 1 || link_kind == LINK_F64_R18 || link_kind == LINK_F64_F32)) return false;
-  return cols == 1 || cols == 2 || cols == 4 || cols == 8 || (cols == 12 && in_kind != VEC_F64);
+  return cols == 1 || cols == 2 || cols == 4 || cols == 6 || cols == 8 || (cols == 12 && in_kind != VEC_F64);
 }
 
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,

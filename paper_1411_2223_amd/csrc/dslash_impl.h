@@ -459,6 +459,7 @@ int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
     case 1: return pipe ? go<Link, InT, OutT, 1, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 1, EPI, false>(a, ord, gs, s);
     case 2: return pipe ? go<Link, InT, OutT, 2, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 2, EPI, false>(a, ord, gs, s);
     case 4: return pipe ? go<Link, InT, OutT, 4, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 4, EPI, false>(a, ord, gs, s);
+    case 6: return pipe ? go<Link, InT, OutT, 6, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 6, EPI, false>(a, ord, gs, s);
     case 8: return pipe ? go<Link, InT, OutT, 8, EPI, true>(a, ord, gs, s) : go<Link, InT, OutT, 8, EPI, false>(a, ord, gs, s);
     case 12:
       // twelve FP64 columns would spill the accumulators: not built

@@ -154,13 +154,13 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
     for (int gs = 0; gs < 2; ++gs)
       for (int order = 0; order < 4; ++order)
         for (int pipe = 0; pipe < 2; ++pipe)
-          for (int cols : {1, 2, 4, 8, 12})
+          for (int cols : {1, 2, 4, 6, 8, 12})
             if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, pipe, order, gs != 0));
     // runs of 16, 64 or 256 blocks per XCD inside the sweep: pipelined loop, the
     // first two block orders
     for (int chunk = 1; chunk <= 3; ++chunk)
       for (int order = 0; order < 2; ++order)
-        for (int cols : {1, 2, 4, 8, 12})
+        for (int cols : {1, 2, 4, 6, 8, 12})
           if (order == 0 || (ncol + cols - 1) / cols >= 2) cands.push_back(make_rtile(cols, true, order, true, chunk));
     // one-column tiles with streamed links, where the tier has that form
     {
