@@ -274,7 +274,11 @@ int cg_solve(const asq_gauge* g, double mass, const double* b_dev, double* x_dev
    columns.)  Each
    column's arithmetic does not depend on the other columns.  For this call,
    cg_solve, cg_solve_multishift and cg_solve_full, b_dev, x_dev and the
-   workspace must be pairwise disjoint (ASQ_EINVAL otherwise). */
+   workspace must be pairwise disjoint (ASQ_EINVAL otherwise).  The first
+   solve of a (lattice, precision tiers, column count) on a device first times
+   the Dslash launch variants on that call's own sources, converted to the
+   iteration's tier (the autotuner; ASQ_TUNE=0 takes built-in choices instead,
+   ASQ_TUNE_CACHE=<file> keeps the choices across processes). */
 int cg_solve_batch(const asq_gauge* g, int nrhs, const double* masses, const double* b_dev, double* x_dev,
                    void* work_dev, size_t work_bytes, const asq_cg_params* params, asq_cg_stats* stats,
                    void* hip_stream);
