@@ -205,10 +205,13 @@ int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, con
 /* The same operator with a caller-chosen launch variant instead of the tuned
    one (for tests that cover every variant and for tuning studies; every
    variant computes the same result, bit for bit).  variant = cols | pipe << 8 |
-   stream << 9 | chunk << 10 | order << 12 | sweep << 15: cols = 1, 2, 4, 6, 8 or 12
+   stream << 9 | chunk << 10 | order << 12 | lds << 14 | sweep << 15: cols = 1, 2, 4, 6, 8 or 12
    columns per thread (12 not with FP64 vectors); pipe = 1 for the
    software-pipelined hop loop; stream = 1 (one column, FP32 and 16-bit link
-   tiers only) reads the links with non-temporal loads; order = 0 walks the column tiles of a site block together, 1, 2, 3 walk
+   tiers only) reads the links with non-temporal loads; lds = 1 (one column,
+   pipe = 1, native vectors only) first stages the input records within
+   three y-rows of each block's sites in LDS, where its x and y hops read
+   them; order = 0 walks the column tiles of a site block together, 1, 2, 3 walk
    tile by tile inside groups of 16, 64 or all site blocks; sweep = 1 deals
    the blocks to the XCDs round-robin (one sweep front through the lattice)
    instead of a contiguous slab per XCD, chunk = 1, 2, 3 (with sweep only) in

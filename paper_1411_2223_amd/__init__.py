@@ -117,14 +117,16 @@ ASQ_VARIANT_NATIVE = 0x100000
 
 
 def variant_code(cols: int, pipe: bool = False, order: int = 0, native: bool = False, sweep: bool = False,
-                 chunk: int = 0, stream: bool = False) -> int:
+                 chunk: int = 0, stream: bool = False, lds: bool = False) -> int:
     """Launch variant of asqtad_dslash_eo_variant: columns per thread (1, 2, 4, 6, 8, 12), pipelined hop
     loop, block order (0 tiles of a site block adjacent; 1, 2, 3 tile by tile in
     groups of 16, 64 or all site blocks); sweep: one global sweep instead of a slab per XCD,
     in which each XCD takes single blocks (chunk 0) or runs of 16, 64, 256 blocks (chunk 1, 2, 3);
     stream: links read with non-temporal loads (one column, FP32 and 16-bit link tiers);
+    lds: each block stages the input records within three y-rows of its sites in LDS for its x
+    and y hops (one column, pipelined loop, native layout);
     native: vectors in the solvers' native layout."""
-    return (int(cols) | (0x100 if pipe else 0) | (0x200 if stream else 0) | (int(order) << 12)
+    return (int(cols) | (0x100 if pipe else 0) | (0x200 if stream else 0) | (0x4000 if lds else 0) | (int(order) << 12)
             | ((0x8000 | (int(chunk) << 10)) if sweep else 0) | (ASQ_VARIANT_NATIVE if native else 0))
 
 

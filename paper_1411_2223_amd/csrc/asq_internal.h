@@ -147,6 +147,11 @@ constexpr int kPipeBit = 0x100;
 // non-temporal loads (the FP64-stored tiers always stream at one column).
 constexpr int kStreamBit = 0x200;
 constexpr int kOrderShift = 12;
+// One-column pipelined launches on the solvers' native layouts: each block
+// first copies the input records within three y-rows of its sites into LDS
+// (the window every x hop and every non-wrapping y hop reads), and those hops
+// read LDS instead of the caches.
+constexpr int kLdsBit = 0x4000;
 // Global sweep: blocks go to the XCDs round-robin in dispatch order instead of
 // each XCD walking a contiguous slab, so the eight XCDs advance through the
 // lattice together and the far-hop (t) neighbour records of the shared front
@@ -171,8 +176,8 @@ inline int order_group(int order, int nblk) { return order == 0 ? 0 : (order == 
 // Whether the library builds launch variant rtile (for any link and vector tier).
 bool variant_built(int link_kind, int in_kind, int rtile);
 inline int make_rtile(int cols, bool pipe, int order, bool global_sweep = false, int chunk_code = 0,
-                      bool stream = false) {
-  return cols | (pipe ? kPipeBit : 0) | (stream ? kStreamBit : 0) | (order << kOrderShift) |
+                      bool stream = false, bool lds = false) {
+  return cols | (pipe ? kPipeBit : 0) | (stream ? kStreamBit : 0) | (lds ? kLdsBit : 0) | (order << kOrderShift) |
          (global_sweep ? kGlobalSweepBit | (chunk_code << kChunkShift) : 0);
 }
 // Widest column tile whose UPDATE launch may form alpha itself (DslashArgs::apa).

@@ -11,8 +11,12 @@ bool variant_built(int link_kind, int in_kind, int rtile) {
     if ((rtile & ~(kMfmaBit | 0xff | (3 << kOrderShift))) != 0) return false;
     return link_kind == LINK_F32_R18 && in_kind == VEC_F16 && cols == kMfmaTile;
   }
-  if ((rtile & ~(0xff | kPipeBit | kStreamBit | (3 << kOrderShift) | kGlobalSweepBit | (3 << kChunkShift))) != 0)
+  if ((rtile & ~(0xff | kPipeBit | kStreamBit | kLdsBit | (3 << kOrderShift) | kGlobalSweepBit | (3 << kChunkShift))) !=
+      0)
     return false;
+  // the LDS window: one column, pipelined loop (native layouts only: the public
+  // operator on canonical vectors refuses it)
+  if ((rtile & kLdsBit) && (cols != 1 || !(rtile & kPipeBit))) return false;
   if ((rtile & (3 << kChunkShift)) && !(rtile & kGlobalSweepBit)) return false;  // runs only within a sweep
   // streamed links: one column, and not the FP64-stored tiers (which always stream there)
   if ((rtile & kStreamBit) && (cols != 1 || link_kind == LINK_F64_R18 || link_kind == LINK_F64_F32)) return false;

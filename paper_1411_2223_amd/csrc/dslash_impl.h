@@ -136,6 +136,47 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
   link_term<Link, InT, R, true>(A, 1 - p, 4 + MU, jb3, jb3, half, on, col, in, sb3, true, acc);
 }
 
+// The LDS window of a block (launch variant kLdsBit, one column): the input
+// records [lo, lo + n) of its column, kept word-major (word k of record q at
+// k * stride + q) so that the lanes of a wave read consecutive words.  The
+// window spans the block's sites and three y-rows on either side, which holds
+// every x neighbour and every y neighbour that does not wrap round the lattice.
+constexpr size_t kLdsWindowMax = 32768;  // bytes of LDS a window may take
+__host__ __device__ inline int lds_window(int xh) { return kBlock + 6 * xh; }
+
+template <class InT>
+struct LdsWin {
+  using raw = typename InT::raw;
+  static constexpr bool kRecord = InT::kind == VEC_F16;  // FP16: one 16-byte word per record
+  using word = typename std::conditional<kRecord, uint4, typename InT::real>::type;
+  word* w = nullptr;
+  int lo = 0, n = 0, stride = 0;
+  __device__ __forceinline__ void put(int q, const raw& v) const {
+    if constexpr (kRecord) {
+      w[q] = v;
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        w[(2 * a) * stride + q] = v.c[a].re;
+        w[(2 * a + 1) * stride + q] = v.c[a].im;
+      }
+    }
+  }
+  __device__ __forceinline__ raw get(int q) const {
+    if constexpr (kRecord) {
+      return w[q];
+    } else {
+      raw v;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        v.c[a].re = w[(2 * a) * stride + q];
+        v.c[a].im = w[(2 * a + 1) * stride + q];
+      }
+      return v;
+    }
+  }
+};
+
 // Software-pipelined form of the 16 terms: the link and the R neighbour records
 // of term K+1 are loaded before the arithmetic of term K, so each wave keeps
 // loads in flight while it computes (two stages of registers).
@@ -154,16 +195,25 @@ struct TermK {
   static constexpr bool back = (kind & 1) != 0;
 };
 
-template <class Link, class InT, int R, int K>
+template <class Link, class InT, int R, int K, bool LDS>
 __device__ __forceinline__ void stage_load(const DslashArgs& A, int i, const Site& s, const int (&col)[R],
-                                           const void* const (&in)[R], Stage<Link, InT, R>& st) {
+                                           const void* const (&in)[R], const LdsWin<InT>& win,
+                                           Stage<Link, InT, R>& st) {
   using T = TermK<K>;
   const int half = A.g.half;
   const int p = A.out_parity;
   const int j = neighbour<T::MU>(A.g, i, s, T::hop);
   st.U = load_link<Link, R>(A.links, half, T::back ? 1 - p : p, T::slot, T::back ? j : i);
+  if constexpr (LDS && T::MU < 2) {
+    static_assert(R == 1, "the LDS window holds one column");
+    // y hops that wrap round the lattice leave the window: those lanes load as usual
+    const int q = j - win.lo;
+    if ((unsigned)q < (unsigned)win.n) st.w[0] = win.get(q);
+    else st.w[0] = fetch<InT>(in[0], half, A.ncol, col[0], j);
+  } else {
 #pragma unroll
-  for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, A.ncol, col[r], j);
+    for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, A.ncol, col[r], j);
+  }
 }
 
 template <class Link, class InT, int R, int K>
@@ -185,13 +235,13 @@ __device__ __forceinline__ void stage_compute(const DslashArgs& A, const Site& s
     if (on[r]) term<Link, InT, T::back>(st.w[r], st.U, sc, T::back, acc[r]);
 }
 
-template <class Link, class InT, int R, int K>
+template <class Link, class InT, int R, int K, bool LDS>
 __device__ __forceinline__ void pipe_run(const DslashArgs& A, int i, const Site& s, const bool (&on)[R],
-                                         const int (&col)[R], const void* const (&in)[R],
+                                         const int (&col)[R], const void* const (&in)[R], const LdsWin<InT>& win,
                                          Stage<Link, InT, R> (&st)[2], Vec3<typename InT::real> (&acc)[R]) {
-  if constexpr (K + 1 < 16) stage_load<Link, InT, R, K + 1>(A, i, s, col, in, st[(K + 1) & 1]);
+  if constexpr (K + 1 < 16) stage_load<Link, InT, R, K + 1, LDS>(A, i, s, col, in, win, st[(K + 1) & 1]);
   stage_compute<Link, InT, R, K>(A, s, on, st[K & 1], acc);
-  if constexpr (K + 1 < 16) pipe_run<Link, InT, R, K + 1>(A, i, s, on, col, in, st, acc);
+  if constexpr (K + 1 < 16) pipe_run<Link, InT, R, K + 1, LDS>(A, i, s, on, col, in, win, st, acc);
 }
 
 // alpha of column c from its reduced |p|^2 and |t|^2 partial sums: false (and
@@ -226,7 +276,7 @@ __device__ __forceinline__ const void* pick_new(const DslashArgs& A, const void*
 // tiles of a site block adjacent, a link leaves HBM once for all tiles; with
 // all site blocks of a tile adjacent (inside groups of site blocks), a column's
 // far neighbours (the t and z hops) are re-read while still in L2.
-template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
+template <class Link, class InT, class OutT, int R, int EPI, bool PIPE, bool LDS = false>
 __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   using real = typename InT::real;
   int lin = A.sweep_chunk > 0 ? sweep_remap((int)blockIdx.x, (int)gridDim.x, A.sweep_chunk)
@@ -289,6 +339,19 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   const int i = sblk * kBlock + tid;
   const bool valid = i < half;
 
+  LdsWin<InT> win;
+  if constexpr (LDS) {
+    // every thread of the block, in range or not, helps fill the window
+    extern __shared__ __align__(16) unsigned char dslash_window[];
+    win.w = reinterpret_cast<typename LdsWin<InT>::word*>(dslash_window);
+    win.stride = lds_window(A.g.Xh);
+    const int i0 = sblk * kBlock;
+    win.lo = max(0, i0 - 3 * A.g.Xh);
+    win.n = min(half, i0 + kBlock + 3 * A.g.Xh) - win.lo;
+    for (int q = tid; q < win.n; q += kBlock) win.put(q, fetch<InT>(in[0], half, A.ncol, col[0], win.lo + q));
+    __syncthreads();
+  }
+
   Vec3<real> acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -299,8 +362,8 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
     const Site s = decode(A.g, i, A.out_parity);
     if constexpr (PIPE) {
       Stage<Link, InT, R> st[2];
-      stage_load<Link, InT, R, 0>(A, i, s, col, in, st[0]);
-      pipe_run<Link, InT, R, 0>(A, i, s, on, col, in, st, acc);
+      stage_load<Link, InT, R, 0, LDS>(A, i, s, col, in, win, st[0]);
+      pipe_run<Link, InT, R, 0, LDS>(A, i, s, on, col, in, win, st, acc);
     } else {
       hop_dir<Link, InT, R, 0>(A, i, s, on, col, in, acc);
       hop_dir<Link, InT, R, 1>(A, i, s, on, col, in, acc);
@@ -422,7 +485,7 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   }
 }
 
-template <class Link, class InT, class OutT, int R, int EPI, bool PIPE>
+template <class Link, class InT, class OutT, int R, int EPI, bool PIPE, bool LDS = false>
 int go(const DslashArgs& a0, int order, int sweep_chunk, hipStream_t s) {
   // alpha is formed in-kernel only by narrow tiles, from at most 4 kBlock partials
   if (a0.apa && (R > kFoldAlphaMaxTile || a0.nblk > 4 * kBlock)) return ASQ_EINVAL;
@@ -433,7 +496,12 @@ int go(const DslashArgs& a0, int order, int sweep_chunk, hipStream_t s) {
   const long nb = (long)a.nblk * a.ntiles;
   if (nb <= 0) return ASQ_OK;
   if (nb >= (1L << 31)) return ASQ_EINVAL;
-  dslash_kernel<Link, InT, OutT, R, EPI, PIPE><<<(unsigned)nb, kBlock, 0, s>>>(a);
+  size_t lds = 0;
+  if constexpr (LDS) {
+    lds = (size_t)lds_window(a.g.Xh) * sizeof(typename InT::raw);
+    if (lds > kLdsWindowMax) return ASQ_EINVAL;  // rows too long for the window
+  }
+  dslash_kernel<Link, InT, OutT, R, EPI, PIPE, LDS><<<(unsigned)nb, kBlock, lds, s>>>(a);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
 }
 
@@ -444,6 +512,23 @@ int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
   const bool pipe = (rtile & kPipeBit) != 0;
   const int ord = rtile_order(rtile);
   const int gs = sweep_chunk_of(rtile);
+  if (rtile & kLdsBit) {
+    // the LDS window: one column, pipelined loop, native layouts; links
+    // ordinary or streamed
+    constexpr bool canon = std::is_same<InT, VecF64C>::value || std::is_same<InT, VecF32C>::value ||
+                           std::is_same<InT, VecF16C>::value;
+    constexpr bool f64_links = std::is_same<Link, LinkF64R18>::value || std::is_same<Link, LinkF64F32>::value;
+    if constexpr (canon) {
+      return ASQ_EINVAL;
+    } else {
+      if ((rtile & 0xff) != 1 || !pipe) return ASQ_EINVAL;
+      if (rtile & kStreamBit) {
+        if constexpr (f64_links) return ASQ_EINVAL;
+        else return go<Streamed<Link>, InT, OutT, 1, EPI, true, true>(a, ord, gs, s);
+      }
+      return go<Link, InT, OutT, 1, EPI, true, true>(a, ord, gs, s);
+    }
+  }
   if (rtile & kStreamBit) {
     // links streamed past the caches: one column, FP32 and 16-bit tiers (the
     // FP64-stored tiers always stream at one column)

@@ -168,6 +168,13 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
       for (size_t q = 0; q < n; ++q)
         if ((cands[q] & 0xff) == 1 && variant_built(link, in, cands[q] | kStreamBit)) cands.push_back(cands[q] | kStreamBit);
     }
+    // and every one-column pipelined candidate with the LDS window (the
+    // canonical layouts refuse it; a candidate that fails to launch is skipped)
+    {
+      const size_t n = cands.size();
+      for (size_t q = 0; q < n; ++q)
+        if (variant_built(link, in, cands[q] | kLdsBit)) cands.push_back(cands[q] | kLdsBit);
+    }
     // The solver runs D_oe forwards and D_eo backwards, so each sweep starts on
     // the links and vectors the previous one left in the memory-side cache; the
     // candidates are timed in that pattern (pairs of launches), best of two.

@@ -168,6 +168,42 @@ def test_streamed_links_match(asq, prec, recon):
         g.dslash(1, vin_n, prec, 1, variant=asq.variant_code(2, True, 0, native=True, stream=True))
 
 
+@pytest.mark.parametrize("prec,recon", [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 12), ("f16", 18), ("f32", 64)])
+def test_lds_window_matches(asq, prec, recon):
+    """One-column launches whose blocks stage the input records within three y-rows of
+    their sites in LDS (x hops and non-wrapping y hops read there) give the bits of the
+    plain kernel: on lattices whose window covers the whole parity (4^3x8), whose blocks
+    are ragged and whose y hops wrap (6x4x8x10, 20^3x64), both parities, every sweep form,
+    with ordinary and, where the tier has them, streamed links."""
+    import torch
+
+    for dims in ((4, 4, 4, 8), (6, 4, 8, 10), (20, 20, 20, 64)):
+        g, fat, lng = _gauge(asq, dims, 0.3, 5, recon)
+        vin = g.to_native(asq.vec_to_device(synth.make_sources(dims, 1, 82), prec), prec, 1)
+        streams = (False,) if prec == "f64" or recon == 64 else (False, True)
+        for parity in (0, 1):
+            for sweep, chunk in ((False, 0), (True, 0), (True, 2)):
+                kw = dict(native=True, sweep=sweep, chunk=chunk)
+                ref = g.dslash(parity, vin, prec, 1, variant=asq.variant_code(1, True, 0, **kw))
+                for st in streams:
+                    got = g.dslash(parity, vin, prec, 1, variant=asq.variant_code(1, True, 0, stream=st, lds=True, **kw))
+                    torch.cuda.synchronize()
+                    print(f"lds window dims={dims} prec={prec} recon={recon} parity={parity} sweep={sweep} "
+                          f"chunk={chunk} stream={st}", flush=True)
+                    assert torch.equal(got, ref)
+        g.close()
+    # no LDS form: wider tiles, the plain loop, the canonical layout
+    dims = (6, 4, 8, 10)
+    g, fat, lng = _gauge(asq, dims, 0.3, 5, recon)
+    v4 = g.to_native(asq.vec_to_device(synth.make_sources(dims, 4, 82), prec), prec, 4)
+    vc = asq.vec_to_device(synth.make_sources(dims, 1, 82), prec)
+    for v, n, code in ((v4, 4, asq.variant_code(4, True, 0, native=True, lds=True)),
+                       (v4, 1, asq.variant_code(1, False, 0, native=True, lds=True)),
+                       (vc, 1, asq.variant_code(1, True, 0, lds=True))):
+        with pytest.raises(asq.AsqError):
+            g.dslash(1, v, prec, n, variant=code)
+
+
 def test_unbuilt_variant_rejected(asq):
     # codes outside the documented set are refused without launching
     dims = (4, 4, 4, 8)
