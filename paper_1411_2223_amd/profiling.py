@@ -273,8 +273,8 @@ def write_stats(stats_csv: str, log: str, out: str, title: str, command: str, to
         lines.append("")
     lines += ["Template arguments of `dslash_kernel`: link tier, input tier, output (or residual) tier, columns",
               "per thread, epilogue (0 plain, 1 |out|^2, 2 update of r and x, 3 FP64 residual), software-pipelined",
-              "hop loop.  Minimum durations near 1 us are masked no-op launches (columns that are converged or",
-              "did not ask for a reliable update).", "", stats_table(stats_csv, top), "", "bench output of that run:", ""]
+              "hop loop, LDS window of x and y neighbours.  Minimum durations near 1 us are masked no-op launches",
+              "(columns that are converged or did not ask for a reliable update).", "", stats_table(stats_csv, top), "", "bench output of that run:", ""]
     lines += ["    " + l for l in bench]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
