@@ -839,8 +839,9 @@ def run_asqtad(args, asq, torch):
         log("oracle: links of every site and the full residual ...")
         ofat, olng = oracle.asqtad_links(dims, U, u0)
         half = V // 2
-        xe = asq.vec_from_device(xf[0:1], 1, half, "f64")[0]
-        xo = asq.vec_from_device(xf[1:2], 1, half, "f64")[0]
+        # xf: the canonical even half (half x 6 reals), then the odd half
+        xe = asq.vec_from_device(xf[: half * 6], 1, half, "f64")[0]
+        xo = asq.vec_from_device(xf[half * 6:], 1, half, "f64")[0]
         re = bfull[0] - 2 * mass * xe - oracle.dslash(dims, ofat, olng, 0, xo)
         ro = bfull[1] - 2 * mass * xo - oracle.dslash(dims, ofat, olng, 1, xe)
         full_oracle = float(np.sqrt((np.vdot(re, re) + np.vdot(ro, ro)).real /
