@@ -208,10 +208,11 @@ int asqtad_dslash_eo(const asq_gauge* g, int out_parity, int prec, int nrhs, con
    stream << 9 | chunk << 10 | order << 12 | lds << 14 | sweep << 15: cols = 1, 2, 4, 6, 8 or 12
    columns per thread (12 not with FP64 vectors); pipe = 1 for the
    software-pipelined hop loop; stream = 1 (one column, FP32 and 16-bit link
-   tiers only) reads the links with non-temporal loads; lds = 1 (one column,
-   pipe = 1, native vectors only) first stages the input records within
-   three y-rows of each block's sites in LDS, where its x and y hops read
-   them; order = 0 walks the column tiles of a site block together, 1, 2, 3 walk
+   tiers only) reads the links with non-temporal loads; lds = 1 (pipe = 1,
+   native vectors only; with stream only at one column; refused when the
+   window of the tile's columns exceeds 64 KB) first stages the input records
+   within three y-rows of each block's sites in LDS, where its x and y hops
+   read them; order = 0 walks the column tiles of a site block together, 1, 2, 3 walk
    tile by tile inside groups of 16, 64 or all site blocks; sweep = 1 deals
    the blocks to the XCDs round-robin (one sweep front through the lattice)
    instead of a contiguous slab per XCD, chunk = 1, 2, 3 (with sweep only) in

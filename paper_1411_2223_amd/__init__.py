@@ -123,8 +123,8 @@ def variant_code(cols: int, pipe: bool = False, order: int = 0, native: bool = F
     groups of 16, 64 or all site blocks); sweep: one global sweep instead of a slab per XCD,
     in which each XCD takes single blocks (chunk 0) or runs of 16, 64, 256 blocks (chunk 1, 2, 3);
     stream: links read with non-temporal loads (one column, FP32 and 16-bit link tiers);
-    lds: each block stages the input records within three y-rows of its sites in LDS for its x
-    and y hops (one column, pipelined loop, native layout);
+    lds: each block stages the input records of its columns within three y-rows of its sites in
+    LDS for its x and y hops (pipelined loop, native layout; streamed links only at one column);
     native: vectors in the solvers' native layout."""
     return (int(cols) | (0x100 if pipe else 0) | (0x200 if stream else 0) | (0x4000 if lds else 0) | (int(order) << 12)
             | ((0x8000 | (int(chunk) << 10)) if sweep else 0) | (ASQ_VARIANT_NATIVE if native else 0))

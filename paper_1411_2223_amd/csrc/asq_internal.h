@@ -147,11 +147,15 @@ constexpr int kPipeBit = 0x100;
 // non-temporal loads (the FP64-stored tiers always stream at one column).
 constexpr int kStreamBit = 0x200;
 constexpr int kOrderShift = 12;
-// One-column pipelined launches on the solvers' native layouts: each block
-// first copies the input records within three y-rows of its sites into LDS
+// Pipelined launches on the solvers' native layouts: each block first copies
+// the input records of its columns within three y-rows of its sites into LDS
 // (the window every x hop and every non-wrapping y hop reads), and those hops
 // read LDS instead of the caches.
 constexpr int kLdsBit = 0x4000;
+// Records per column in a block's window (its kBlock sites and three y-rows of
+// xh checkerboard sites on either side), and the most LDS a window may take.
+__host__ __device__ inline int lds_window(int xh) { return kBlock + 6 * xh; }
+constexpr size_t kLdsWindowMax = 65536;
 // Global sweep: blocks go to the XCDs round-robin in dispatch order instead of
 // each XCD walking a contiguous slab, so the eight XCDs advance through the
 // lattice together and the far-hop (t) neighbour records of the shared front
@@ -175,6 +179,9 @@ inline int rtile_order(int rtile) { return (rtile >> kOrderShift) & 3; }
 inline int order_group(int order, int nblk) { return order == 0 ? 0 : (order == 1 ? 16 : (order == 2 ? 64 : nblk)); }
 // Whether the library builds launch variant rtile (for any link and vector tier).
 bool variant_built(int link_kind, int in_kind, int rtile);
+// Whether a built variant can launch on this lattice: an LDS window of the
+// tile's columns must fit in kLdsWindowMax bytes.
+bool variant_fits(const Geom& g, int in_kind, int rtile);
 inline int make_rtile(int cols, bool pipe, int order, bool global_sweep = false, int chunk_code = 0,
                       bool stream = false, bool lds = false) {
   return cols | (pipe ? kPipeBit : 0) | (stream ? kStreamBit : 0) | (lds ? kLdsBit : 0) | (order << kOrderShift) |

@@ -14,13 +14,18 @@ bool variant_built(int link_kind, int in_kind, int rtile) {
   if ((rtile & ~(0xff | kPipeBit | kStreamBit | kLdsBit | (3 << kOrderShift) | kGlobalSweepBit | (3 << kChunkShift))) !=
       0)
     return false;
-  // the LDS window: one column, pipelined loop (native layouts only: the public
-  // operator on canonical vectors refuses it)
-  if ((rtile & kLdsBit) && (cols != 1 || !(rtile & kPipeBit))) return false;
+  // the LDS window: pipelined loop, streamed links only at one column (native
+  // layouts only: the public operator on canonical vectors refuses it)
+  if ((rtile & kLdsBit) && (!(rtile & kPipeBit) || ((rtile & kStreamBit) && cols != 1))) return false;
   if ((rtile & (3 << kChunkShift)) && !(rtile & kGlobalSweepBit)) return false;  // runs only within a sweep
   // streamed links: one column, and not the FP64-stored tiers (which always stream there)
   if ((rtile & kStreamBit) && (cols != 1 || link_kind == LINK_F64_R18 || link_kind == LINK_F64_F32)) return false;
   return cols == 1 || cols == 2 || cols == 4 || cols == 6 || cols == 8 || (cols == 12 && in_kind != VEC_F64);
+}
+
+bool variant_fits(const Geom& g, int in_kind, int rtile) {
+  if (!(rtile & kLdsBit)) return true;
+  return (size_t)(rtile & 0xff) * lds_window(g.Xh) * vec_site_bytes(in_kind) <= kLdsWindowMax;
 }
 
 int launch_dslash(int link_kind, int in_kind, int out_kind, int epi, int rtile, const DslashArgs& a,

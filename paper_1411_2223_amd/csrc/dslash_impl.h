@@ -27,6 +27,11 @@
 
 #include "asq_reduce.h"
 
+// The dynamic LDS of a Dslash launch: the block's window of neighbour records
+// (launch variant kLdsBit).  Declared here, at file scope, so that the helpers
+// that read and write it address it as LDS.
+extern __shared__ __align__(16) unsigned char dslash_window[];
+
 namespace asq {
 namespace {
 
@@ -136,41 +141,42 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& A, int i, const Site& 
   link_term<Link, InT, R, true>(A, 1 - p, 4 + MU, jb3, jb3, half, on, col, in, sb3, true, acc);
 }
 
-// The LDS window of a block (launch variant kLdsBit, one column): the input
-// records [lo, lo + n) of its column, kept word-major (word k of record q at
-// k * stride + q) so that the lanes of a wave read consecutive words.  The
-// window spans the block's sites and three y-rows on either side, which holds
-// every x neighbour and every y neighbour that does not wrap round the lattice.
-constexpr size_t kLdsWindowMax = 32768;  // bytes of LDS a window may take
-__host__ __device__ inline int lds_window(int xh) { return kBlock + 6 * xh; }
-
-template <class InT>
+// The LDS window of a block (launch variant kLdsBit): the input records
+// [lo, lo + n) of each of its R columns, kept word-major per column (word k of
+// record q of column r at (r * kWords + k) * stride + q) so that the lanes of a
+// wave read consecutive words.  The window spans the block's sites and three
+// y-rows on either side, which holds every x neighbour and every y neighbour
+// that does not wrap round the lattice.
+template <class InT, int R>
 struct LdsWin {
   using raw = typename InT::raw;
   static constexpr bool kRecord = InT::kind == VEC_F16;  // FP16: one 16-byte word per record
   using word = typename std::conditional<kRecord, uint4, typename InT::real>::type;
-  word* w = nullptr;
+  static constexpr int kWords = kRecord ? 1 : 6;
   int lo = 0, n = 0, stride = 0;
-  __device__ __forceinline__ void put(int q, const raw& v) const {
+  __device__ __forceinline__ static word* words() { return reinterpret_cast<word*>(dslash_window); }
+  __device__ __forceinline__ void put(int r, int q, const raw& v) const {
+    const int b = r * kWords * stride + q;
     if constexpr (kRecord) {
-      w[q] = v;
+      words()[b] = v;
     } else {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        w[(2 * a) * stride + q] = v.c[a].re;
-        w[(2 * a + 1) * stride + q] = v.c[a].im;
+        words()[b + (2 * a) * stride] = v.c[a].re;
+        words()[b + (2 * a + 1) * stride] = v.c[a].im;
       }
     }
   }
-  __device__ __forceinline__ raw get(int q) const {
+  __device__ __forceinline__ raw get(int r, int q) const {
+    const int b = r * kWords * stride + q;
     if constexpr (kRecord) {
-      return w[q];
+      return words()[b];
     } else {
       raw v;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        v.c[a].re = w[(2 * a) * stride + q];
-        v.c[a].im = w[(2 * a + 1) * stride + q];
+        v.c[a].re = words()[b + (2 * a) * stride];
+        v.c[a].im = words()[b + (2 * a + 1) * stride];
       }
       return v;
     }
@@ -197,7 +203,7 @@ struct TermK {
 
 template <class Link, class InT, int R, int K, bool LDS>
 __device__ __forceinline__ void stage_load(const DslashArgs& A, int i, const Site& s, const int (&col)[R],
-                                           const void* const (&in)[R], const LdsWin<InT>& win,
+                                           const void* const (&in)[R], const LdsWin<InT, R>& win,
                                            Stage<Link, InT, R>& st) {
   using T = TermK<K>;
   const int half = A.g.half;
@@ -205,11 +211,15 @@ __device__ __forceinline__ void stage_load(const DslashArgs& A, int i, const Sit
   const int j = neighbour<T::MU>(A.g, i, s, T::hop);
   st.U = load_link<Link, R>(A.links, half, T::back ? 1 - p : p, T::slot, T::back ? j : i);
   if constexpr (LDS && T::MU < 2) {
-    static_assert(R == 1, "the LDS window holds one column");
     // y hops that wrap round the lattice leave the window: those lanes load as usual
     const int q = j - win.lo;
-    if ((unsigned)q < (unsigned)win.n) st.w[0] = win.get(q);
-    else st.w[0] = fetch<InT>(in[0], half, A.ncol, col[0], j);
+    if ((unsigned)q < (unsigned)win.n) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) st.w[r] = win.get(r, q);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, A.ncol, col[r], j);
+    }
   } else {
 #pragma unroll
     for (int r = 0; r < R; ++r) st.w[r] = fetch<InT>(in[r], half, A.ncol, col[r], j);
@@ -237,7 +247,7 @@ __device__ __forceinline__ void stage_compute(const DslashArgs& A, const Site& s
 
 template <class Link, class InT, int R, int K, bool LDS>
 __device__ __forceinline__ void pipe_run(const DslashArgs& A, int i, const Site& s, const bool (&on)[R],
-                                         const int (&col)[R], const void* const (&in)[R], const LdsWin<InT>& win,
+                                         const int (&col)[R], const void* const (&in)[R], const LdsWin<InT, R>& win,
                                          Stage<Link, InT, R> (&st)[2], Vec3<typename InT::real> (&acc)[R]) {
   if constexpr (K + 1 < 16) stage_load<Link, InT, R, K + 1, LDS>(A, i, s, col, in, win, st[(K + 1) & 1]);
   stage_compute<Link, InT, R, K>(A, s, on, st[K & 1], acc);
@@ -339,16 +349,18 @@ __global__ void __launch_bounds__(kBlock) dslash_kernel(const DslashArgs A) {
   const int i = sblk * kBlock + tid;
   const bool valid = i < half;
 
-  LdsWin<InT> win;
+  LdsWin<InT, R> win;
   if constexpr (LDS) {
-    // every thread of the block, in range or not, helps fill the window
-    extern __shared__ __align__(16) unsigned char dslash_window[];
-    win.w = reinterpret_cast<typename LdsWin<InT>::word*>(dslash_window);
+    // every thread of the block, in range or not, helps fill the window (the
+    // columns past the batch, or not active, are read as the hop loop reads them)
     win.stride = lds_window(A.g.Xh);
     const int i0 = sblk * kBlock;
     win.lo = max(0, i0 - 3 * A.g.Xh);
     win.n = min(half, i0 + kBlock + 3 * A.g.Xh) - win.lo;
-    for (int q = tid; q < win.n; q += kBlock) win.put(q, fetch<InT>(in[0], half, A.ncol, col[0], win.lo + q));
+    for (int q = tid; q < win.n; q += kBlock) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) win.put(r, q, fetch<InT>(in[r], half, A.ncol, col[r], win.lo + q));
+    }
     __syncthreads();
   }
 
@@ -498,8 +510,8 @@ int go(const DslashArgs& a0, int order, int sweep_chunk, hipStream_t s) {
   if (nb >= (1L << 31)) return ASQ_EINVAL;
   size_t lds = 0;
   if constexpr (LDS) {
-    lds = (size_t)lds_window(a.g.Xh) * sizeof(typename InT::raw);
-    if (lds > kLdsWindowMax) return ASQ_EINVAL;  // rows too long for the window
+    lds = (size_t)R * lds_window(a.g.Xh) * sizeof(typename InT::raw);
+    if (lds > kLdsWindowMax) return ASQ_EINVAL;  // rows too long, or too many columns, for the window
   }
   dslash_kernel<Link, InT, OutT, R, EPI, PIPE, LDS><<<(unsigned)nb, kBlock, lds, s>>>(a);
   return hipGetLastError() == hipSuccess ? ASQ_OK : ASQ_EHIP;
@@ -513,20 +525,30 @@ int pick_r(int rtile, const DslashArgs& a, hipStream_t s) {
   const int ord = rtile_order(rtile);
   const int gs = sweep_chunk_of(rtile);
   if (rtile & kLdsBit) {
-    // the LDS window: one column, pipelined loop, native layouts; links
-    // ordinary or streamed
+    // the LDS window: pipelined loop, native layouts; one column with ordinary
+    // or streamed links, or a tile of 2 to 12 columns
     constexpr bool canon = std::is_same<InT, VecF64C>::value || std::is_same<InT, VecF32C>::value ||
                            std::is_same<InT, VecF16C>::value;
     constexpr bool f64_links = std::is_same<Link, LinkF64R18>::value || std::is_same<Link, LinkF64F32>::value;
     if constexpr (canon) {
       return ASQ_EINVAL;
     } else {
-      if ((rtile & 0xff) != 1 || !pipe) return ASQ_EINVAL;
+      if (!pipe) return ASQ_EINVAL;
       if (rtile & kStreamBit) {
         if constexpr (f64_links) return ASQ_EINVAL;
-        else return go<Streamed<Link>, InT, OutT, 1, EPI, true, true>(a, ord, gs, s);
+        else return (rtile & 0xff) == 1 ? go<Streamed<Link>, InT, OutT, 1, EPI, true, true>(a, ord, gs, s) : ASQ_EINVAL;
       }
-      return go<Link, InT, OutT, 1, EPI, true, true>(a, ord, gs, s);
+      switch (rtile & 0xff) {
+        case 1: return go<Link, InT, OutT, 1, EPI, true, true>(a, ord, gs, s);
+        case 2: return go<Link, InT, OutT, 2, EPI, true, true>(a, ord, gs, s);
+        case 4: return go<Link, InT, OutT, 4, EPI, true, true>(a, ord, gs, s);
+        case 6: return go<Link, InT, OutT, 6, EPI, true, true>(a, ord, gs, s);
+        case 8: return go<Link, InT, OutT, 8, EPI, true, true>(a, ord, gs, s);
+        case 12:
+          if constexpr (InT::kind == VEC_F64) return ASQ_EINVAL;
+          else return go<Link, InT, OutT, 12, EPI, true, true>(a, ord, gs, s);
+      }
+      return ASQ_EINVAL;
     }
   }
   if (rtile & kStreamBit) {

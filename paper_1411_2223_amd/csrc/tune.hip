@@ -89,10 +89,11 @@ int forced_variant(int link, int in) {
 
 int tuned_rtile(const asq_gauge* g, int link, int in, int out, int epi, int ncol) {
   const int fv = forced_variant(link, in);
-  // a forced tile wider than the batch is ignored, except the matrix-core form,
-  // which masks its idle columns; that form takes alpha from the column state,
-  // so it is not forced where the update launch forms alpha itself
-  if (fv >= 0 && !(fv & kMfmaBit) && (fv & 0xff) <= (ncol > 1 ? ncol : 1)) return fv;
+  // a forced tile wider than the batch, or whose LDS window does not fit this
+  // lattice, is ignored, except the matrix-core form, which masks its idle
+  // columns; that form takes alpha from the column state, so it is not forced
+  // where the update launch forms alpha itself
+  if (fv >= 0 && !(fv & kMfmaBit) && (fv & 0xff) <= (ncol > 1 ? ncol : 1) && variant_fits(g->geom, in, fv)) return fv;
   if (fv >= 0 && (fv & kMfmaBit) && ncol > kFoldAlphaMaxTile) return fv;
   std::lock_guard<std::mutex> lk(g_mu);
   load_cache_locked();
@@ -100,7 +101,7 @@ int tuned_rtile(const asq_gauge* g, int link, int in, int out, int epi, int ncol
   // a cache file may come from another build: only variants the tuner itself
   // could have chosen are taken from it
   if (it != g_cache.end() && variant_built(link, in, it->second) && !(it->second & kMfmaBit) &&
-      (it->second & 0xff) <= (ncol > 1 ? ncol : 1))
+      (it->second & 0xff) <= (ncol > 1 ? ncol : 1) && variant_fits(g->geom, in, it->second))
     return it->second;
   return default_rtile(link, ncol);
 }
@@ -168,8 +169,9 @@ int tune_dslash(const asq_gauge* g, int link, int in, int ncol, const void* in_b
       for (size_t q = 0; q < n; ++q)
         if ((cands[q] & 0xff) == 1 && variant_built(link, in, cands[q] | kStreamBit)) cands.push_back(cands[q] | kStreamBit);
     }
-    // and every one-column pipelined candidate with the LDS window (the
-    // canonical layouts refuse it; a candidate that fails to launch is skipped)
+    // and every pipelined candidate with the LDS window (the canonical layouts
+    // refuse it, and so do windows too large for LDS; a candidate that fails to
+    // launch is skipped)
     {
       const size_t n = cands.size();
       for (size_t q = 0; q < n; ++q)

@@ -170,11 +170,11 @@ def test_streamed_links_match(asq, prec, recon):
 
 @pytest.mark.parametrize("prec,recon", [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 12), ("f16", 18), ("f32", 64)])
 def test_lds_window_matches(asq, prec, recon):
-    """One-column launches whose blocks stage the input records within three y-rows of
-    their sites in LDS (x hops and non-wrapping y hops read there) give the bits of the
-    plain kernel: on lattices whose window covers the whole parity (4^3x8), whose blocks
-    are ragged and whose y hops wrap (6x4x8x10, 20^3x64), both parities, every sweep form,
-    with ordinary and, where the tier has them, streamed links."""
+    """Launches whose blocks stage the input records within three y-rows of their sites in
+    LDS (x hops and non-wrapping y hops read there) give the bits of the plain kernel: one
+    column on lattices whose window covers the whole parity (4^3x8), whose blocks are
+    ragged and whose y hops wrap (6x4x8x10, 20^3x64), both parities, every sweep form,
+    with ordinary and, where the tier has them, streamed links; and every column tile."""
     import torch
 
     for dims in ((4, 4, 4, 8), (6, 4, 8, 10), (20, 20, 20, 64)):
@@ -192,12 +192,34 @@ def test_lds_window_matches(asq, prec, recon):
                           f"chunk={chunk} stream={st}", flush=True)
                     assert torch.equal(got, ref)
         g.close()
-    # no LDS form: wider tiles, the plain loop, the canonical layout
+    # column tiles with the window: a 13-column batch (ragged last tile) in every tile
+    # width, both block orders, slabs and sweeps
     dims = (6, 4, 8, 10)
     g, fat, lng = _gauge(asq, dims, 0.3, 5, recon)
+    nrhs = 13
+    vn = g.to_native(asq.vec_to_device(synth.make_sources(dims, nrhs, 83), prec), prec, nrhs)
+    site_bytes = {"f64": 48, "f32": 24, "f16": 16}[prec]
+    for cols in (2, 4, 6, 8, 12):
+        if cols == 12 and prec == "f64":
+            continue
+        too_big = cols * (256 + 6 * (dims[0] // 2)) * site_bytes > 65536  # the window's LDS limit
+        for order in (0, 1):
+            for sweep, chunk in ((False, 0), (True, 1)):
+                kw = dict(native=True, sweep=sweep, chunk=chunk)
+                ref = g.dslash(1, vn, prec, nrhs, variant=asq.variant_code(cols, True, order, **kw))
+                if too_big:
+                    with pytest.raises(asq.AsqError):
+                        g.dslash(1, vn, prec, nrhs, variant=asq.variant_code(cols, True, order, lds=True, **kw))
+                    continue
+                got = g.dslash(1, vn, prec, nrhs, variant=asq.variant_code(cols, True, order, lds=True, **kw))
+                torch.cuda.synchronize()
+                print(f"lds window prec={prec} recon={recon} cols={cols} order={order} sweep={sweep}", flush=True)
+                assert torch.equal(got, ref)
+    # no LDS form: the plain loop, streamed links beyond one column, the canonical layout
     v4 = g.to_native(asq.vec_to_device(synth.make_sources(dims, 4, 82), prec), prec, 4)
     vc = asq.vec_to_device(synth.make_sources(dims, 1, 82), prec)
-    for v, n, code in ((v4, 4, asq.variant_code(4, True, 0, native=True, lds=True)),
+    for v, n, code in ((v4, 4, asq.variant_code(4, False, 0, native=True, lds=True)),
+                       (v4, 4, asq.variant_code(4, True, 0, native=True, stream=True, lds=True)),
                        (v4, 1, asq.variant_code(1, False, 0, native=True, lds=True)),
                        (vc, 1, asq.variant_code(1, True, 0, lds=True))):
         with pytest.raises(asq.AsqError):

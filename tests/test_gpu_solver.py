@@ -102,11 +102,11 @@ def test_batch_every_launch_variant(asq, mode, recon, monkeypatch):
         assert r.rc == 0
         assert [s["iters"] for s in r.stats] == [s["iters"] for s in r0.stats]
         assert np.array_equal(x, x0), f"variant ({cols}, {pipe}, {order}) changes the solution"
-    # one-column tiles that stage their x and y neighbours in LDS
-    for sweep in (False, True):
-        monkeypatch.setenv("ASQ_VARIANT", str(asq.variant_code(1, True, 0, sweep=sweep, lds=True)))
+    # tiles that stage their x and y neighbours in LDS
+    for cols, sweep in ((1, False), (1, True), (4, True), (8, False)):
+        monkeypatch.setenv("ASQ_VARIANT", str(asq.variant_code(cols, True, 0, sweep=sweep, lds=True)))
         x, r = _solve(asq, g, masses, b, mode)
-        print(f"mode={mode} recon={recon} variant cols=1 pipe=True lds=True sweep={sweep}", flush=True)
+        print(f"mode={mode} recon={recon} variant cols={cols} pipe=True lds=True sweep={sweep}", flush=True)
         assert r.rc == 0
         assert [s["iters"] for s in r.stats] == [s["iters"] for s in r0.stats]
         assert np.array_equal(x, x0), "the LDS window changes the solution"
