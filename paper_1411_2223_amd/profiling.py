@@ -228,7 +228,8 @@ def write_valu(counter_csv: str, trace_csv: str, out: str, command: str, lattice
         def tile(name):
             return int(short_name(name).split(", ")[3])
 
-        hits = [(k, g) for (k, g) in full if short_name(k).startswith(prefix) and short_name(k).split(", ")[4] == "0"
+        hits = [(k, g) for (k, g) in full
+                if re.sub(r"Streamed<(\w+)>", r"\1", short_name(k)).startswith(prefix) and short_name(k).split(", ")[4] == "0"
                 and g == nblk * 256 * -(-ncol // tile(k))]
         if not hits:
             continue
