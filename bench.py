@@ -670,6 +670,40 @@ def run_threelevel(args, asq, torch):
     print(json.dumps(out), flush=True)
 
 
+def serving_summary(done, trace, n_warm, lattices):
+    """Load and latency figures of a served request stream.  done: one tuple per finished
+    request (trace index, rc, latency s, columns, lattice index, max true residual, completion
+    time s on the trace's clock); the first n_warm requests of the trace are warm-up and stay
+    out of every figure.  The served rate is taken over the measured window, from the first
+    measured arrival to the last measured completion; stable: served >= 0.95 offered."""
+    meas = [d for d in done if d[0] >= n_warm]
+    lats = np.array([d[2] for d in meas])
+    rhs = sum(d[3] for d in meas)
+    span = trace[-1]["arrival"] - trace[n_warm]["arrival"]
+    window = max(d[6] for d in meas) - trace[n_warm]["arrival"]
+    per_lat = {}
+    for i in range(len(lattices)):
+        li = [d[2] for d in meas if d[4] == i]
+        if li:
+            per_lat["x".join(map(str, lattices[i]))] = {"n": len(li), "p50_ms": float(np.percentile(li, 50) * 1e3),
+                                                        "p99_ms": float(np.percentile(li, 99) * 1e3)}
+    return {"value": len(meas) / window, "stable": len(meas) / window >= 0.95 * len(meas) / span,
+            "requests": len(meas), "rhs_solves": rhs, "window_s": window,
+            "offered_requests_per_s": len(meas) / span, "achieved_rhs_per_s": rhs / window,
+            "p50_latency_ms": float(np.percentile(lats, 50) * 1e3), "p99_latency_ms": float(np.percentile(lats, 99) * 1e3),
+            "failed": sum(1 for d in meas if d[1] != 0), "true_resid_max": max(d[5] for d in meas),
+            "per_lattice": per_lat}
+
+
+def split_parities(x, half):
+    """A full-lattice canonical FP64 vector (flat: the even half's half x 6 reals, then the odd
+    half's) -> (even, odd) flat views."""
+    n = int(half) * 6
+    if x.numel() != 2 * n:
+        raise ValueError(f"a full-lattice vector of {2 * n} reals was expected, got {x.numel()}")
+    return x[:n], x[n:]
+
+
 def run_serving(args, asq, torch):
     """Poisson stream of solves on four resident lattices (continuous batching, HBM budget)."""
     lattices = synth.SERVING_LATTICES
@@ -746,28 +780,10 @@ def run_serving(args, asq, torch):
         oracle_max = max(rs) if rs else None
         log(f"oracle FP64 residual of {len(kept)} sampled requests ({len(rs)} columns): max {oracle_max:.3e}")
     del arrays
-    meas = [d for d in done if d[0] >= n_warm]
-    lats = np.array([d[2] for d in meas])
-    rhs = sum(d[3] for d in meas)
-    bad = [d for d in meas if d[1] != 0]
-    span = trace[-1]["arrival"] - trace[n_warm]["arrival"]
-    # served rate over the measured window: first measured arrival to last measured completion
-    # (the warm-up requests and their time stay outside it)
-    window = max(d[6] for d in meas) - trace[n_warm]["arrival"]
-    per_lat = {}
-    for i in range(len(lattices)):
-        li = [d[2] for d in meas if d[4] == i]
-        if li:
-            per_lat["x".join(map(str, lattices[i]))] = {"n": len(li), "p50_ms": float(np.percentile(li, 50) * 1e3),
-                                                        "p99_ms": float(np.percentile(li, 99) * 1e3)}
-    out = {"metric": METRIC, "workload": "serving", "value": len(meas) / window, "unit": "requests/s",
-           "rate": args.rate, "mode": mode, "max_cols": args.serve_cols, "max_streams": args.serve_streams,
-           "stable": len(meas) / window >= 0.95 * len(meas) / span,
-           "requests": len(meas), "rhs_solves": rhs, "window_s": window, "wall_s": wall,
-           "offered_requests_per_s": len(meas) / span, "achieved_rhs_per_s": rhs / window, "p50_latency_ms": float(np.percentile(lats, 50) * 1e3),
-           "p99_latency_ms": float(np.percentile(lats, 99) * 1e3), "failed": len(bad),
-           "true_resid_max": max(d[5] for d in meas), "per_lattice": per_lat,
-           "oracle_checked_requests": len(kept), "oracle_true_resid_max": oracle_max}
+    out = {"metric": METRIC, "workload": "serving", "unit": "requests/s", "rate": args.rate, "mode": mode,
+           "max_cols": args.serve_cols, "max_streams": args.serve_streams}
+    out.update(serving_summary(done, trace, n_warm, lattices))
+    out.update({"wall_s": wall, "oracle_checked_requests": len(kept), "oracle_true_resid_max": oracle_max})
     log(f"serving: {out['value']:.1f} req/s, p50 {out['p50_latency_ms']:.1f} ms, p99 {out['p99_latency_ms']:.1f} ms")
     print(json.dumps(out), flush=True)
 
@@ -839,9 +855,9 @@ def run_asqtad(args, asq, torch):
         log("oracle: links of every site and the full residual ...")
         ofat, olng = oracle.asqtad_links(dims, U, u0)
         half = V // 2
-        # xf: the canonical even half (half x 6 reals), then the odd half
-        xe = asq.vec_from_device(xf[: half * 6], 1, half, "f64")[0]
-        xo = asq.vec_from_device(xf[half * 6:], 1, half, "f64")[0]
+        xfe, xfo = split_parities(xf, half)
+        xe = asq.vec_from_device(xfe, 1, half, "f64")[0]
+        xo = asq.vec_from_device(xfo, 1, half, "f64")[0]
         re = bfull[0] - 2 * mass * xe - oracle.dslash(dims, ofat, olng, 0, xo)
         ro = bfull[1] - 2 * mass * xo - oracle.dslash(dims, ofat, olng, 1, xe)
         full_oracle = float(np.sqrt((np.vdot(re, re) + np.vdot(ro, ro)).real /
